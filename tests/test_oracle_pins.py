@@ -1,0 +1,460 @@
+"""Pins for the CPU oracle: each test fixes part of it against something
+other than itself — closed forms derived from Eq. 1, a dense linear solve,
+invariants, brute-force set computations from the definitions, and the
+paper's worked example (Section 4.1.2, Figure 1)."""
+import math
+import os
+import subprocess
+import sys
+
+import numpy as np
+import pytest
+from hypothesis import given, settings, strategies as st, HealthCheck
+
+import oracle
+from oracle import OracleGraph, brute, mark_initial_csr, expand_csr
+from paper_2401_03256_amd import synth
+
+ALPHA = 0.85
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _arr(pairs):
+    if not pairs:
+        return np.zeros(0, np.int32), np.zeros(0, np.int32)
+    a = np.array(pairs, dtype=np.int32)
+    return a[:, 0].copy(), a[:, 1].copy()
+
+
+def _batch(dels, ins):
+    ds, dd = _arr(dels)
+    is_, id_ = _arr(ins)
+    return synth.Batch(ds, dd, is_, id_)
+
+
+# ---------------------------------------------------------------------------
+# closed forms (Eq. 1)
+# ---------------------------------------------------------------------------
+
+def test_directed_cycle_is_uniform():
+    # in(v) = {v-1, v} and every out-degree is 2, so sum_{u in in(v)} 1/|out(u)| = 1
+    # and R = 1/n solves Eq. 1.
+    n = 7
+    g = OracleGraph(n, np.arange(n), (np.arange(n) + 1) % n)
+    R, st_ = g.static(tol=1e-15)
+    assert np.max(np.abs(R - 1.0 / n)) < 1e-16
+    assert st_.iterations == 1 and st_.converged
+
+
+def test_complete_digraph_is_uniform():
+    n = 6
+    src, dst = zip(*[(u, v) for u in range(n) for v in range(n) if u != v])
+    g = OracleGraph(n, src, dst)
+    R, _ = g.static(tol=1e-15)
+    assert np.max(np.abs(R - 1.0 / n)) < 1e-16
+
+
+def test_circulant_regular_is_uniform():
+    n, d = 11, 3
+    src = np.repeat(np.arange(n), d)
+    dst = (src + np.tile(np.arange(1, d + 1), n)) % n
+    g = OracleGraph(n, src, dst)
+    R, _ = g.static(tol=1e-15)
+    assert np.max(np.abs(R - 1.0 / n)) < 1e-16
+
+
+def star_closed_form(n, k, alpha=ALPHA):
+    """Bidirectional star with k leaves (and self-loops) inside an n-vertex
+    graph whose other vertices are isolated.  From Eq. 1 for the centre c
+    and a leaf l: R_c = a(R_c/(k+1) + k R_l/2) + (1-a)/n and
+    R_l = a(R_c/(k+1) + R_l/2) + (1-a)/n."""
+    D = 2 * (k + 1) + alpha * (k - 1)
+    leaf = (k + 1) / n * 2 / D
+    centre = (k + 1) / n * (2 + alpha * (k - 1)) / D
+    return centre, leaf
+
+
+def in_star_closed_form(n, k, alpha=ALPHA):
+    """Leaves point at the centre only: R_l = a R_l/2 + (1-a)/n and
+    R_c = a(R_c + k R_l/2) + (1-a)/n."""
+    leaf = 2 * (1 - alpha) / (n * (2 - alpha))
+    centre = (2 - alpha + alpha * k) / (n * (2 - alpha))
+    return centre, leaf
+
+
+def _star_edges(c, leaves):
+    return [(c, l) for l in leaves] + [(l, c) for l in leaves]
+
+
+@pytest.mark.parametrize("k,n", [(1, 2), (3, 4), (5, 10), (40, 50)])
+def test_bidirectional_star(k, n):
+    src, dst = _arr(_star_edges(0, range(1, k + 1)))
+    g = OracleGraph(n, src, dst)
+    R, _ = g.static(tol=1e-15)
+    c, l = star_closed_form(n, k)
+    assert abs(R[0] - c) < 1e-14
+    assert np.max(np.abs(R[1:k + 1] - l)) < 1e-14
+    if n > k + 1:
+        assert np.max(np.abs(R[k + 1:] - 1.0 / n)) < 1e-15
+
+
+@pytest.mark.parametrize("k,n", [(1, 3), (4, 5), (9, 20)])
+def test_in_star(k, n):
+    # asymmetric: catches an in/out swap and using in-degree for |out(u)|
+    src = np.arange(1, k + 1)
+    dst = np.zeros(k, np.int64)
+    g = OracleGraph(n, src, dst)
+    R, _ = g.static(tol=1e-15)
+    c, l = in_star_closed_form(n, k)
+    assert abs(R[0] - c) < 1e-14
+    assert np.max(np.abs(R[1:k + 1] - l)) < 1e-14
+
+
+def test_star_dynamic_update_lands_on_new_closed_form():
+    # star(k) -> delete both edges of leaf k -> star(k-1) plus an isolated vertex
+    n, k = 30, 8
+    g = OracleGraph(n, *_arr(_star_edges(0, range(1, k + 1))))
+    R0, _ = g.static(tol=1e-14)
+    b = _batch([(0, k), (k, 0)], [])
+    assert g.apply_batch(b) == (2, 0)
+    for name, (R, st_) in {
+        "df": g.dynamic_frontier(b, R0, frontier_tol=1e-15),
+        "naive": g.naive_dynamic(R0),
+    }.items():
+        c, l = star_closed_form(n, k - 1)
+        assert abs(R[0] - c) < 1e-9, name
+        assert np.max(np.abs(R[1:k] - l)) < 1e-9, name
+        assert abs(R[k] - 1.0 / n) < 1e-9, name
+        assert st_.converged
+
+
+# ---------------------------------------------------------------------------
+# dense solve (tiny graphs) and invariants
+# ---------------------------------------------------------------------------
+
+@st.composite
+def tiny_graph(draw, max_n=12):
+    n = draw(st.integers(2, max_n))
+    pairs = draw(st.lists(st.tuples(st.integers(0, n - 1), st.integers(0, n - 1)),
+                          max_size=3 * n))
+    return n, pairs
+
+
+@settings(max_examples=60, deadline=None, suppress_health_check=[HealthCheck.too_slow])
+@given(tiny_graph())
+def test_static_matches_dense_solve(gr):
+    n, pairs = gr
+    src, dst = _arr(pairs)
+    g = OracleGraph(n, src, dst)
+    R, st_ = g.static(tol=1e-14)
+    x = brute.pagerank_dense(n, brute.edge_set(n, src, dst))
+    # a-posteriori bound for the alpha-contraction in L1:
+    # |x_k - x*|_1 <= alpha/(1-alpha) |x_k - x_{k-1}|_1 <= alpha/(1-alpha) n tol
+    bound = ALPHA / (1 - ALPHA) * n * max(st_.final_linf, 1e-16) + 1e-15
+    assert np.sum(np.abs(R - x)) <= bound
+    assert np.max(np.abs(R - x)) < 1e-12
+
+
+@settings(max_examples=30, deadline=None)
+@given(tiny_graph(), st.integers(0, 2**31 - 1))
+def test_dynamic_matches_dense_solve_of_updated_graph(gr, seed):
+    n, pairs = gr
+    src, dst = _arr(pairs)
+    g = OracleGraph(n, src, dst)
+    R0, _ = g.static(tol=1e-14)
+    rng = np.random.default_rng(seed)
+    E = brute.edge_set(n, src, dst)
+    nonloop = sorted(e for e in E if e[0] != e[1])
+    dels = [nonloop[i] for i in rng.permutation(len(nonloop))[: rng.integers(0, 4)]]
+    absent = [(u, v) for u in range(n) for v in range(n) if u != v and (u, v) not in E]
+    ins = [absent[i] for i in rng.permutation(len(absent))[: rng.integers(0, 4)]]
+    b = _batch(dels, ins)
+    g.apply_batch(b)
+    E2 = (E - set(dels)) | set(ins)
+    x = brute.pagerank_dense(n, E2)
+    Rd, _ = g.dynamic_frontier(b, R0, tol=1e-13, frontier_tol=1e-18)
+    Rn, _ = g.naive_dynamic(R0, tol=1e-13)
+    assert np.max(np.abs(Rd - x)) < 1e-10
+    assert np.max(np.abs(Rn - x)) < 1e-10
+
+
+def test_ranks_sum_to_one():
+    n, src, dst = synth.rmat(10, 8, seed=3)
+    g = OracleGraph(n, src, dst)
+    R, st_ = g.static()
+    assert st_.converged
+    assert abs(math.fsum(R) - 1.0) < 1e-9
+    Rref, _ = g.reference()
+    assert abs(math.fsum(Rref) - 1.0) < 1e-12
+
+
+def test_dynamic_equals_from_scratch_static():
+    n = 2000
+    src, dst = synth.gnm(n, 16000, seed=5)
+    g = OracleGraph(n, src, dst)
+    R0, _ = g.static()
+    nd, ni = synth.batch_counts(1e-3, g.m)
+    b = synth.random_batch(src, dst, n, max(nd, 3), max(ni, 12), seed=9)
+    g.apply_batch(b)
+    Rref, _ = g.reference()
+    Rd, sd = g.dynamic_frontier(b, R0)
+    Rn, sn = g.naive_dynamic(R0)
+    Rs, ss = g.static()
+    for R in (Rd, Rn, Rs):
+        assert np.max(np.abs(R - Rref)) < 1e-9
+    assert sd.converged and sn.converged and ss.converged
+    # Dynamic Frontier processes fewer rows than Naive-dynamic (Section 4.1)
+    assert sd.vertices_processed < sn.vertices_processed
+    assert abs(math.fsum(Rd) - 1.0) < 1e-6
+
+
+# ---------------------------------------------------------------------------
+# Dynamic Frontier special cases
+# ---------------------------------------------------------------------------
+
+def _two_components(seed=1):
+    nA, nB = 300, 200
+    sa, da = synth.gnm(nA, 1500, seed=seed)
+    sb, db = synth.gnm(nB, 900, seed=seed + 1)
+    src = np.concatenate([sa, sb + nA])
+    dst = np.concatenate([da, db + nA])
+    return nA + nB, nA, src, dst, (sa, da)
+
+
+def test_untouched_component_is_bitwise_unchanged():
+    n, nA, src, dst, (sa, da) = _two_components()
+    g = OracleGraph(n, src, dst)
+    R0, _ = g.static()
+    b = synth.random_batch(sa, da, nA, 3, 10, seed=4)
+    g.apply_batch(b)
+    R, st_, f0, f1 = g.dynamic_frontier(b, R0, return_flags=True)
+    assert not f1[nA:].any()
+    assert np.array_equal(R[nA:], R0[nA:])
+    assert st_.converged
+
+
+def test_infinite_frontier_tolerance_keeps_initial_set():
+    n = 1000
+    src, dst = synth.gnm(n, 6000, seed=2)
+    g = OracleGraph(n, src, dst)
+    R0, _ = g.static()
+    b = synth.random_batch(src, dst, n, 2, 8, seed=3)
+    g.apply_batch(b)
+    _, st_, f0, f1 = g.dynamic_frontier(b, R0, frontier_tol=math.inf, return_flags=True)
+    assert np.array_equal(f0, f1)
+    assert st_.affected_initial == st_.affected_final == int(f0.sum())
+
+
+def test_zero_frontier_tolerance_marks_reachable_set():
+    # with tau_f = 0 every vertex whose rank moves marks its out-neighbours,
+    # so the marks spread like a traversal from the batch sources
+    n = 400
+    src, dst = synth.gnm(n, 2000, seed=7)
+    g = OracleGraph(n, src, dst)
+    R0, _ = g.static()
+    b = synth.random_batch(src, dst, n, 1, 4, seed=8)
+    g.apply_batch(b)
+    _, st_, f0, f1 = g.dynamic_frontier(b, R0, frontier_tol=0.0, return_flags=True)
+    assert f1.sum() >= f0.sum()
+    assert st_.affected_final > st_.affected_initial
+
+
+def test_empty_batch_returns_previous_ranks_in_one_iteration():
+    n = 500
+    src, dst = synth.gnm(n, 3000, seed=11)
+    g = OracleGraph(n, src, dst)
+    R0, _ = g.static()
+    R, st_ = g.dynamic_frontier(synth.Batch.empty(), R0)
+    assert np.array_equal(R, R0)
+    assert st_.iterations == 1 and st_.converged and st_.affected_final == 0
+
+
+def test_max_iterations_cap():
+    n = 500
+    src, dst = synth.gnm(n, 3000, seed=12)
+    g = OracleGraph(n, src, dst)
+    _, st_ = g.static(max_iters=3)
+    assert st_.iterations == 3 and not st_.converged
+    # the reference run stops only at 500 iterations or at an exact
+    # floating-point fixed point (Delta R = 0 <= 1e-100)
+    _, st_ = g.reference()
+    assert st_.iterations == 500 or st_.final_linf == 0.0
+
+
+# ---------------------------------------------------------------------------
+# marking rules: the worked example and brute force from the definition
+# ---------------------------------------------------------------------------
+
+def _load_fig1():
+    vals = {}
+    with open(os.path.join(GOLDEN, "fig1_example.txt")) as f:
+        for line in f:
+            line = line.split("#", 1)[0].strip()
+            if not line:
+                continue
+            key, *rest = line.split()
+            vals[key] = rest
+    pairs = lambda xs: [tuple(int(t) for t in x.split(":")) for x in xs]
+    return {
+        "n": int(vals["vertices"][0]),
+        "edges": pairs(vals["edges_before"]),
+        "delete": pairs(vals["delete"]),
+        "insert": pairs(vals["insert"]),
+        **{k: sorted(int(x) for x in vals[k]) for k in
+           ("initial_affected", "iter1_exceed", "iter1_marked", "iter2_exceed", "iter2_marked")},
+    }
+
+
+def test_worked_example_marking():
+    ex = _load_fig1()
+    n = ex["n"]
+    E_after = (set(ex["edges"]) - set(ex["delete"])) | set(ex["insert"])
+    off, idx = brute.csr_from_set(n, E_after, out=True)   # no self-loops, as drawn
+    b = _batch(ex["delete"], ex["insert"])
+    f0 = mark_initial_csr(n, off, idx, b)
+    assert sorted(np.flatnonzero(f0)) == ex["initial_affected"]
+    assert f0[2] == 0   # the source of the deletion is not marked
+    dr = np.zeros(n)
+    dr[ex["iter1_exceed"]] = 1.0
+    f1 = expand_csr(n, off, idx, f0, dr, 1e-15)
+    # the text lists the out-neighbours marked in each iteration (3 was
+    # already marked); the affected set grows by their union
+    assert sorted(np.flatnonzero(f1)) == sorted(set(ex["initial_affected"]) | set(ex["iter1_marked"]))
+    dr = np.zeros(n)
+    dr[ex["iter2_exceed"]] = 1.0
+    f2 = expand_csr(n, off, idx, f1, dr, 1e-15)
+    assert sorted(np.flatnonzero(f2)) == sorted(set(np.flatnonzero(f1).tolist()) | set(ex["iter2_marked"]))
+    # a change of exactly tau_f does not expand (strict comparison)
+    dr = np.zeros(n)
+    dr[ex["iter1_exceed"]] = 1e-15
+    assert np.array_equal(expand_csr(n, off, idx, f0, dr, 1e-15), f0)
+
+
+def test_worked_example_with_self_loops_marks_sources():
+    # with a self-loop on every vertex (Section 3.1) u is in out(u), so the
+    # source of each change is marked as well
+    ex = _load_fig1()
+    n = ex["n"]
+    src, dst = _arr(ex["edges"])
+    g = OracleGraph(n, src, dst)
+    b = _batch(ex["delete"], ex["insert"])
+    g.apply_batch(b)
+    f0 = g.mark_initial(b)
+    assert sorted(np.flatnonzero(f0)) == sorted(set(ex["initial_affected"]) | {2})
+
+
+@st.composite
+def graph_and_batch(draw, max_n=20):
+    n = draw(st.integers(2, max_n))
+    pairs = draw(st.lists(st.tuples(st.integers(0, n - 1), st.integers(0, n - 1)),
+                          max_size=4 * n))
+    E = {(u, v) for u, v in pairs} | {(v, v) for v in range(n)}
+    nonloop = sorted(e for e in E if e[0] != e[1])
+    dels = draw(st.lists(st.sampled_from(nonloop), unique=True, max_size=5)) if nonloop else []
+    absent = [(u, v) for u in range(n) for v in range(n) if (u, v) not in E]
+    ins = draw(st.lists(st.sampled_from(absent), unique=True, max_size=5)) if absent else []
+    return n, pairs, dels, ins
+
+
+@settings(max_examples=80, deadline=None)
+@given(graph_and_batch())
+def test_initial_marking_matches_definition(case):
+    # Algorithm 1: mark every v' in (G^{t-1} U G^t).out(u) for (u, v) in the batch
+    n, pairs, dels, ins = case
+    src, dst = _arr(pairs)
+    E0 = brute.edge_set(n, src, dst)
+    E1 = (E0 - set(dels)) | set(ins)
+    expect = set()
+    for u, _ in dels + ins:
+        expect |= {w for (a, w) in E0 | E1 if a == u}
+    g = OracleGraph(n, src, dst)
+    b = _batch(dels, ins)
+    assert g.apply_batch(b) == (len(dels), len(ins))
+    f0 = g.mark_initial(b)
+    assert set(np.flatnonzero(f0).tolist()) == expect
+
+
+@settings(max_examples=60, deadline=None)
+@given(graph_and_batch(), st.integers(0, 2**31 - 1))
+def test_expansion_matches_definition(case, seed):
+    n, pairs, _, _ = case
+    src, dst = _arr(pairs)
+    E = brute.edge_set(n, src, dst)
+    off, idx = brute.csr_from_set(n, E, out=True)
+    rng = np.random.default_rng(seed)
+    aff = (rng.random(n) < 0.4).astype(np.uint8)
+    dr = np.where(rng.random(n) < 0.5, 1e-12, 1e-16)
+    nxt = expand_csr(n, off, idx, aff, dr, 1e-13)
+    expect = set(np.flatnonzero(aff).tolist())
+    for u, w in E:
+        if aff[u] and dr[u] > 1e-13:
+            expect.add(w)
+    assert set(np.flatnonzero(nxt).tolist()) == expect
+
+
+# ---------------------------------------------------------------------------
+# graph loading and batch application against set arithmetic
+# ---------------------------------------------------------------------------
+
+@st.composite
+def messy_batch(draw, max_n=16):
+    n = draw(st.integers(1, max_n))
+    pair = st.tuples(st.integers(0, n - 1), st.integers(0, n - 1))
+    pairs = draw(st.lists(pair, max_size=4 * n))
+    dels = draw(st.lists(pair, max_size=8))       # may hold absent edges, loops, repeats
+    ins = draw(st.lists(pair, max_size=8))        # may hold present edges, loops, repeats
+    return n, pairs, dels, ins
+
+
+@settings(max_examples=120, deadline=None)
+@given(messy_batch())
+def test_load_and_apply_match_set_arithmetic(case):
+    n, pairs, dels, ins = case
+    src, dst = _arr(pairs)
+    g = OracleGraph(n, src, dst)
+    E = brute.edge_set(n, src, dst)
+    for out in (True, False):
+        off, idx = g.csr(out)
+        eo, ei = brute.csr_from_set(n, E, out)
+        assert np.array_equal(off, eo) and np.array_equal(idx, ei)
+    applied = g.apply_batch(_batch(dels, ins))
+    D = {e for e in dels if e[0] != e[1]}
+    E1 = E - D
+    E2 = E1 | set(ins)
+    assert applied == (len(E - E1), len(E2 - E1))
+    for out in (True, False):
+        off, idx = g.csr(out)
+        eo, ei = brute.csr_from_set(n, E2, out)
+        assert np.array_equal(off, eo) and np.array_equal(idx, ei)
+
+
+def test_out_of_range_batch_is_rejected_unchanged():
+    n = 10
+    g = OracleGraph(n, [0, 1, 2], [1, 2, 3])
+    before = g.csr(True)
+    with pytest.raises(ValueError):
+        g.apply_batch(_batch([(0, 1)], [(3, 10)]))
+    after = g.csr(True)
+    assert np.array_equal(before[0], after[0]) and np.array_equal(before[1], after[1])
+    with pytest.raises(ValueError):
+        OracleGraph(n, [0, -1], [1, 2])
+
+
+def test_results_do_not_depend_on_thread_count():
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    code = (
+        "import hashlib, sys; sys.path.insert(0, %r)\n"
+        "from oracle import OracleGraph\n"
+        "from paper_2401_03256_amd import synth\n"
+        "n, s, d = synth.rmat(11, 8, seed=2)\n"
+        "g = OracleGraph(n, s, d); R0, _ = g.static()\n"
+        "b = synth.random_batch(s, d, n, 4, 16, seed=5); g.apply_batch(b)\n"
+        "R, st = g.dynamic_frontier(b, R0)\n"
+        "sys.stdout.write(hashlib.sha256(R.tobytes() + R0.tobytes()).hexdigest() + str(st))\n"
+    ) % root
+    outs = []
+    for t in ("1", "5"):
+        env = dict(os.environ, OMP_NUM_THREADS=t)
+        outs.append(subprocess.run([sys.executable, "-c", code], env=env, check=True,
+                                   capture_output=True, text=True).stdout)
+    assert outs[0] == outs[1]
