@@ -1,0 +1,209 @@
+/*
+ * dfpr.h — Dynamic Frontier PageRank on one AMD Instinct MI355X (gfx950).
+ *
+ * C-ABI of libdfpr.so.  Plain pointers and sizes only.  Every call returns a
+ * status code (DFPR_OK = 0, negative on error); on error a message is
+ * available from dfpr_last_error() (thread-local) and, unless stated
+ * otherwise, the graph is left as it was before the call.
+ *
+ * The method (Sahu, "An Incrementally Expanding Approach for Updating
+ * PageRank on Dynamic Graphs"):
+ *   - PageRank of v:  R[v] = alpha * sum_{u in in(v)} R[u]/|out(u)| + (1-alpha)/n
+ *     (Eq. 1), solved by power iteration from R = 1/n until the L-inf change
+ *     of an iteration is <= tol (Section 3.1);
+ *   - every vertex carries a self-loop, so there are no dead ends
+ *     (Section 3.1, Section 5.1.3);
+ *   - a batch update is a set of deletions and a set of insertions of
+ *     edges; vertices are never added or removed (Section 3.2, 5.1.4);
+ *   - Naive-dynamic restarts the iteration from the previous ranks
+ *     (Section 3.3.1);
+ *   - Dynamic Frontier marks the out-neighbours (before and after the update)
+ *     of the source of every changed edge, recomputes only marked vertices,
+ *     and marks the out-neighbours of any vertex whose rank moved by more
+ *     than frontier_tol, until the L-inf change is <= tol (Section 4.1,
+ *     Algorithm 1).
+ * This library runs the synchronous form of Section 4.2: each iteration
+ * reads one rank vector and writes another; vertices marked during an
+ * iteration are processed from the next one; marks are never cleared within
+ * one update.  Ranks are FP64 and vertex ids int32 (Section 5.1.2).
+ *
+ * Memory.  The library owns all device memory of a graph: the in-edge CSR
+ * (for the pull of Eq. 1) and the out-edge CSR (for marking and |out(u)|),
+ * both with per-row slack so a batch is merged in place, the two rank
+ * vectors and the work lists.  Pointers documented as "host" are ordinary
+ * host memory, borrowed for the duration of the call.  Pointers documented
+ * as "device" are device memory of the current HIP device, borrowed for the
+ * call and accessed on the graph's stream.
+ *
+ * Threading.  One writer per graph (Section 3.2): calls on one graph must
+ * not overlap.  Different graphs may be used from different threads.
+ */
+#ifndef DFPR_H
+#define DFPR_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* status codes */
+#define DFPR_OK 0
+#define DFPR_E_ARG (-1)     /* bad argument (null pointer, negative size, ...) */
+#define DFPR_E_RANGE (-2)   /* a vertex id is outside [0, n)                   */
+#define DFPR_E_NOMEM (-3)   /* device or host allocation failed                */
+#define DFPR_E_DEVICE (-4)  /* a HIP call failed                               */
+#define DFPR_E_BUSY (-5)    /* the graph is in use by another call             */
+#define DFPR_E_LIMIT (-6)   /* graph too large for 32-bit edge offsets         */
+
+/* precision forms */
+#define DFPR_FP64 0         /* ranks and contributions in FP64 (the method)   */
+#define DFPR_FP32_KAHAN 1   /* FP32 contributions, compensated FP32 row sums,
+                               FP64 L-inf, renormalisation and final FP64
+                               sweeps (see dfpr_pagerank_dynamic_frontier)    */
+
+typedef struct dfpr_graph dfpr_graph;
+
+typedef struct {
+    double alpha;          /* damping factor; default 0.85 (Section 5.1.2)      */
+    double tol;            /* iteration tolerance tau on the L-inf change;
+                              default 1e-10 (Section 5.1.2)                     */
+    double frontier_tol;   /* frontier tolerance tau_f; a vertex whose rank
+                              changes by MORE than this marks its out-
+                              neighbours; default tol/1e5 (Section 4.3)         */
+    int32_t max_iters;     /* iteration cap; default 500 (Section 5.1.2)       */
+    int32_t precision;     /* DFPR_FP64 (default) or DFPR_FP32_KAHAN           */
+} dfpr_params;
+
+typedef struct {
+    int32_t iterations;         /* iterations performed (FP64 iterations in
+                                   the FP32 form count separately below)      */
+    int32_t converged;          /* 1 if the L-inf change reached <= tol;
+                                   reaching max_iters is not an error         */
+    int32_t refine_sweeps;      /* FP64 iterations after the FP32 phase       */
+    int32_t reserved;
+    double final_linf;          /* L-inf change of the last iteration          */
+    double ms_device;           /* device time of the call (HIP events)        */
+    int64_t affected_initial;   /* vertices marked by the initial marking      */
+    int64_t affected_final;     /* vertices marked when the loop ended         */
+    int64_t vertices_processed; /* rank updates, summed over iterations        */
+    int64_t edges_processed;    /* in-edges gathered, summed over iterations   */
+} dfpr_stats;
+
+/* Defaults of Section 5.1.2 and Section 4.3. */
+void dfpr_params_default(dfpr_params *p);
+
+/* Build a graph of n vertices (1 <= n < 2^31) from m directed edges
+ * src[i] -> dst[i] (host arrays).  Repeated edges count once and a
+ * self-loop is added to every vertex (Section 3.1).  The ranks held by the
+ * graph start at 1/n.  Rows get slack of max(2, deg/8) entries.
+ * *out receives a handle owned by the library (free with dfpr_free_graph).
+ * Errors: DFPR_E_ARG, DFPR_E_RANGE (id outside [0, n)), DFPR_E_NOMEM,
+ * DFPR_E_LIMIT (more than 2^32 - 1 edge slots). */
+int dfpr_load_graph(int32_t n, int64_t m, const int32_t *src, const int32_t *dst,
+                    dfpr_graph **out);
+
+/* Free the graph and all its device memory.  NULL is ignored. */
+void dfpr_free_graph(dfpr_graph *g);
+
+/* Make the graph issue its work on this HIP stream (hipStream_t passed as
+ * void*); NULL selects the graph's own stream (the default).  The stream
+ * must stay valid while the graph uses it. */
+int dfpr_set_stream(dfpr_graph *g, void *hip_stream);
+
+/* Number of vertices and of edges (self-loops included) of G. */
+int dfpr_graph_info(const dfpr_graph *g, int32_t *n, int64_t *m);
+
+/* Apply one batch update (Section 3.2): E <- (E minus deletions) union
+ * insertions, on both CSRs, on the device.  Host arrays.  Deletions are
+ * applied before insertions; deleting a self-loop or an absent edge and
+ * inserting a present edge change nothing; repeats count once.
+ * applied (host, nullable, 2 entries) receives the number of edges
+ * actually deleted and actually inserted.  Any id outside [0, n): the
+ * whole batch is rejected with DFPR_E_RANGE and G is unchanged. */
+int dfpr_apply_batch(dfpr_graph *g,
+                     int64_t n_del, const int32_t *del_src, const int32_t *del_dst,
+                     int64_t n_ins, const int32_t *ins_src, const int32_t *ins_dst,
+                     int64_t applied[2]);
+
+/* As dfpr_apply_batch, with the four id arrays in device memory.
+ * applied stays a host pointer (nullable). */
+int dfpr_apply_batch_device(dfpr_graph *g,
+                            int64_t n_del, const int32_t *del_src, const int32_t *del_dst,
+                            int64_t n_ins, const int32_t *ins_src, const int32_t *ins_dst,
+                            int64_t applied[2]);
+
+/* Static PageRank (Section 3.1): R = 1/n, then iterate Eq. 1 over all
+ * vertices until the L-inf change is <= p->tol or p->max_iters iterations.
+ * p NULL selects the defaults.  ranks_out (host, n doubles, nullable)
+ * receives the ranks, which also become the graph's resident ranks.
+ * st (host, nullable) receives statistics. */
+int dfpr_pagerank_static(dfpr_graph *g, const dfpr_params *p, double *ranks_out,
+                         dfpr_stats *st);
+
+/* Naive-dynamic PageRank (Section 3.3.1): as static, but starting from
+ * prev (host, n doubles) or, if prev is NULL, from the graph's resident
+ * ranks.  ranks_out (host, nullable) may alias prev. */
+int dfpr_pagerank_naive_dynamic(dfpr_graph *g, const dfpr_params *p,
+                                const double *prev, double *ranks_out,
+                                dfpr_stats *st);
+
+/* Dynamic Frontier PageRank (Algorithm 1) on the current graph G^t.  The
+ * batch (host arrays) is the one that produced G^t from G^{t-1}, i.e. the
+ * one last given to dfpr_apply_batch.  prev (host, nullable: resident
+ * ranks) holds R^{t-1}; ranks_out (host, nullable) receives R^t, which also
+ * becomes the resident ranks.  Ids are checked as in dfpr_apply_batch.
+ *
+ * With p->precision == DFPR_FP32_KAHAN the marked vertices are first
+ * iterated with FP32 contributions and compensated FP32 row sums (Delta r
+ * and the L-inf test in FP64) until the change stalls at FP32 resolution;
+ * the ranks are then renormalised to sum 1 in FP64 and the FP64 iteration
+ * continues over the marked vertices until the L-inf change is <= tol. */
+int dfpr_pagerank_dynamic_frontier(dfpr_graph *g, const dfpr_params *p,
+                                   int64_t n_del, const int32_t *del_src,
+                                   const int32_t *del_dst, int64_t n_ins,
+                                   const int32_t *ins_src, const int32_t *ins_dst,
+                                   const double *prev, double *ranks_out,
+                                   dfpr_stats *st);
+
+/* As dfpr_pagerank_dynamic_frontier with the batch arrays, prev and
+ * ranks_out in device memory (prev and ranks_out nullable as above). */
+int dfpr_pagerank_dynamic_frontier_device(dfpr_graph *g, const dfpr_params *p,
+                                          int64_t n_del, const int32_t *del_src,
+                                          const int32_t *del_dst, int64_t n_ins,
+                                          const int32_t *ins_src,
+                                          const int32_t *ins_dst, const double *prev,
+                                          double *ranks_out, dfpr_stats *st);
+
+/* Initial marking only (Section 4.1.1, first rule): flags_out (host, n
+ * bytes) receives 1 for every w in G^t.out(u) of each batch edge (u, v) and
+ * for the v of each deletion, 0 elsewhere.  Ranks are not touched. */
+int dfpr_mark_affected(dfpr_graph *g,
+                       int64_t n_del, const int32_t *del_src, const int32_t *del_dst,
+                       int64_t n_ins, const int32_t *ins_src, const int32_t *ins_dst,
+                       uint8_t *flags_out);
+
+/* Marks held when the last Dynamic Frontier call ended (host, n bytes). */
+int dfpr_get_affected(const dfpr_graph *g, uint8_t *flags_out);
+
+/* Copy the resident ranks out (host or device pointer, n doubles). */
+int dfpr_get_ranks(const dfpr_graph *g, double *ranks, int on_device);
+
+/* Replace the resident ranks (host or device pointer, n doubles). */
+int dfpr_set_ranks(dfpr_graph *g, const double *ranks, int on_device);
+
+/* Compacted CSR of G (host arrays): out_orientation 1 gives rows = sources,
+ * entries = destinations; 0 gives rows = destinations, entries = sources.
+ * offsets has n+1 entries, idx has m entries (dfpr_graph_info); each row is
+ * sorted ascending. */
+int dfpr_export_csr(const dfpr_graph *g, int out_orientation, int64_t *offsets,
+                    int32_t *idx);
+
+/* Message for the last non-OK status returned on this thread. */
+const char *dfpr_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif

@@ -1,0 +1,698 @@
+// Device batch applier: E <- (E minus deletions) union insertions on both
+// CSRs (Section 3.2; self-loops are permanent, Section 5.1.4).
+//
+// Steps, all on the device:
+//   1. keys: each batch entry becomes, per orientation, the 64-bit key
+//      row << 33 | col << 1 | type (type 0 = deletion, 1 = insertion);
+//      self-loop deletions become a sentinel that sorts last; an id outside
+//      [0, n) sets the error flag and every later step does nothing.
+//   2. sort: each workgroup sorts a tile of 2048 keys in LDS (bitonic), then
+//      merge passes double the sorted runs (each key finds its output slot by
+//      a binary search in the other run).
+//   3. heads: the first key of each row opens a "touched row" entry; rows
+//      whose capacity fits in LDS go to one list, larger rows to another.
+//   4. merge: one workgroup per touched row.  It copies the row (LDS or a
+//      global slab), works out which deletions hit a present edge and which
+//      insertions add a new one, and writes every surviving entry and every
+//      new entry straight to its final slot (positions from prefix counts
+//      and binary searches), keeping the row sorted.  The out-orientation
+//      pass also refreshes the row's contribution R/|out|.
+//   5. a row whose slack is too small is left for a re-layout: new
+//      capacities, a prefix sum, a copy of every row to its new place, and
+//      the merge is run again for those rows (a no-op for the parts already
+//      applied).
+#include <algorithm>
+#include <vector>
+
+#include "common.h"
+
+namespace dfpr {
+
+constexpr int kTile = 2048;    // keys sorted per workgroup in LDS
+constexpr int kOpsLds = 1024;  // batch entries of one row per round
+constexpr int kRowLds = 4096;  // rows up to this capacity are copied to LDS
+constexpr int kBigGrid = 64;   // workgroups (and slabs) for larger rows
+
+__device__ inline uint32_t key_row(uint64_t k) { return (uint32_t)(k >> 33); }
+__device__ inline int32_t key_col(uint64_t k) { return (int32_t)((k >> 1) & 0xFFFFFFFFull); }
+
+template <typename T>
+__device__ inline uint32_t lower_bound_dev(const T *a, uint32_t len, T x)
+{
+    uint32_t lo = 0, hi = len;
+    while (lo < hi) {
+        uint32_t mid = (lo + hi) >> 1;
+        if (a[mid] < x) lo = mid + 1;
+        else hi = mid;
+    }
+    return lo;
+}
+
+template <typename T>
+__device__ inline uint32_t upper_bound_dev(const T *a, uint32_t len, T x)
+{
+    uint32_t lo = 0, hi = len;
+    while (lo < hi) {
+        uint32_t mid = (lo + hi) >> 1;
+        if (a[mid] <= x) lo = mid + 1;
+        else hi = mid;
+    }
+    return lo;
+}
+
+struct ApplyArgs {
+    int32_t n;
+    int64_t nd, ni;
+    const int32_t *ds, *dd, *is, *id;
+    uint64_t *keys[2];          // unsorted / sorted keys per orientation
+    uint32_t *small_list[2], *big_list[2], *ovf_list[2];
+    int32_t *ovf_need[2];
+    uint32_t *beg[2], *cnt[2];
+    int32_t *idx[2];
+    double *R0, *R1, *C0, *C1;
+    int32_t *slab;
+    uint64_t slab_stride;
+    Ctl *ctl;
+};
+
+__global__ void k_apply_reset(Ctl *ctl)
+{
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        ctl->err = 0;
+        for (int o = 0; o < 2; o++) {
+            ctl->nsmall[o] = ctl->nbig[o] = ctl->novf[o] = 0;
+            ctl->applied[o] = 0;
+        }
+    }
+}
+
+__global__ void k_apply_keys(ApplyArgs a)
+{
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= a.nd + a.ni) return;
+    const bool del = i < a.nd;
+    const int32_t s = del ? a.ds[i] : a.is[i - a.nd];
+    const int32_t d = del ? a.dd[i] : a.id[i - a.nd];
+    if (s < 0 || s >= a.n || d < 0 || d >= a.n) {
+        atomicOr(&a.ctl->err, 1u);
+        a.keys[0][i] = a.keys[1][i] = kSentinel;
+        return;
+    }
+    if (del && s == d) {   // self-loops are never deleted
+        a.keys[0][i] = a.keys[1][i] = kSentinel;
+        return;
+    }
+    const uint64_t t = del ? 0 : 1;
+    a.keys[0][i] = ((uint64_t)d << 33) | ((uint64_t)(uint32_t)s << 1) | t;   // in-CSR: row = dst
+    a.keys[1][i] = ((uint64_t)s << 33) | ((uint64_t)(uint32_t)d << 1) | t;   // out-CSR: row = src
+}
+
+// Bitonic sort of one tile of kTile keys in LDS; grid.y = orientation.
+__global__ __launch_bounds__(kBlock) void k_tile_sort(uint64_t *k0, uint64_t *k1, uint32_t len)
+{
+    __shared__ uint64_t s[kTile];
+    uint64_t *keys = blockIdx.y ? k1 : k0;
+    const uint32_t base = blockIdx.x * kTile;
+    for (uint32_t i = threadIdx.x; i < kTile; i += kBlock)
+        s[i] = base + i < len ? keys[base + i] : kSentinel;
+    __syncthreads();
+    for (uint32_t k = 2; k <= kTile; k <<= 1) {
+        for (uint32_t j = k >> 1; j > 0; j >>= 1) {
+            for (uint32_t i = threadIdx.x; i < kTile; i += kBlock) {
+                uint32_t ixj = i ^ j;
+                if (ixj > i) {
+                    uint64_t x = s[i], y = s[ixj];
+                    bool up = (i & k) == 0;
+                    if ((x > y) == up) {
+                        s[i] = y;
+                        s[ixj] = x;
+                    }
+                }
+            }
+            __syncthreads();
+        }
+    }
+    for (uint32_t i = threadIdx.x; i < kTile; i += kBlock)
+        if (base + i < len) keys[base + i] = s[i];
+}
+
+// Merge sorted runs of `width` keys pairwise: in -> out.
+__global__ void k_merge_pass(const uint64_t *in0, uint64_t *out0, const uint64_t *in1,
+                             uint64_t *out1, uint32_t len, uint32_t width)
+{
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= len) return;
+    const uint64_t *in = blockIdx.y ? in1 : in0;
+    uint64_t *out = blockIdx.y ? out1 : out0;
+    const uint64_t key = in[i];
+    const uint32_t start = (i / (2 * width)) * (2 * width);
+    const uint32_t mid = min(start + width, len), end = min(start + 2 * width, len);
+    uint32_t pos;
+    if (i < mid) pos = (i - start) + lower_bound_dev(in + mid, end - mid, key);
+    else pos = (i - mid) + upper_bound_dev(in + start, mid - start, key);
+    out[start + pos] = key;
+}
+
+// Open one touched-row entry at the first key of every row.
+__global__ void k_heads(ApplyArgs a, uint32_t len)
+{
+    if (a.ctl->err) return;
+    const int o = blockIdx.y;
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    const uint64_t *keys = a.keys[o];
+    bool head = false, big = false;
+    if (i < len) {
+        const uint64_t k = keys[i];
+        if (k != kSentinel) {
+            const uint32_t r = key_row(k);
+            head = i == 0 || key_row(keys[i - 1]) != r;
+            if (head) big = (a.beg[o][r + 1] - a.beg[o][r]) > (uint32_t)kRowLds;
+        }
+    }
+    const int lane = __lane_id();
+    const unsigned long long below = (1ull << lane) - 1ull;
+    for (int which = 0; which < 2; which++) {
+        const bool take = head && (big == (which == 1));
+        const unsigned long long m = __ballot(take);
+        if (!m) continue;
+        const int leader = __ffsll((long long)m) - 1;
+        uint32_t base = 0;
+        if (lane == leader)
+            base = atomicAdd(which ? &a.ctl->nbig[o] : &a.ctl->nsmall[o], (uint32_t)__popcll(m));
+        base = __shfl(base, leader);
+        if (take) (which ? a.big_list[o] : a.small_list[o])[base + __popcll(m & below)] = i;
+    }
+}
+
+// Exclusive prefix sum of in[0 .. len) (len <= 4 * kBlock) into out[0 .. len],
+// out[len] = total.  All threads of the workgroup call it.
+__device__ inline void block_scan_u8(const uint8_t *in, uint32_t len, uint32_t *out, uint32_t *tmp)
+{
+    const uint32_t t = threadIdx.x, b = t * 4;
+    uint32_t v[4], sum = 0;
+#pragma unroll
+    for (int r = 0; r < 4; r++) {
+        v[r] = b + r < len ? in[b + r] : 0;
+        sum += v[r];
+    }
+    tmp[t] = sum;
+    __syncthreads();
+    for (uint32_t off = 1; off < kBlock; off <<= 1) {
+        uint32_t x = t >= off ? tmp[t - off] : 0;
+        __syncthreads();
+        tmp[t] += x;
+        __syncthreads();
+    }
+    uint32_t ex = tmp[t] - sum;
+#pragma unroll
+    for (int r = 0; r < 4; r++) {
+        if (b + r < len) out[b + r] = ex;
+        ex += v[r];
+    }
+    if (t == kBlock - 1) out[len] = tmp[t];
+    __syncthreads();
+}
+
+// Merge the batch entries of touched rows into their rows.  BIG selects the
+// global-slab copy for rows whose capacity exceeds kRowLds.
+template <bool BIG>
+__global__ __launch_bounds__(kBlock) void k_apply_rows(ApplyArgs a, uint32_t len, int only_o)
+{
+    __shared__ int32_t s_d[kOpsLds];
+    __shared__ int32_t s_i[kOpsLds];
+    __shared__ uint8_t s_fd[kOpsLds];
+    __shared__ uint8_t s_fi[kOpsLds];
+    __shared__ uint32_t s_pd[kOpsLds + 1];
+    __shared__ uint32_t s_pi[kOpsLds + 1];
+    __shared__ uint32_t s_tmp[kBlock];
+    __shared__ int32_t s_row[BIG ? 1 : kRowLds];
+
+    const int o = only_o >= 0 ? only_o : blockIdx.y;
+    if (only_o >= 0 && blockIdx.y > 0) return;
+    Ctl *ctl = a.ctl;
+    if (ctl->err) return;
+    const uint32_t count = BIG ? ctl->nbig[o] : ctl->nsmall[o];
+    const uint32_t *list = BIG ? a.big_list[o] : a.small_list[o];
+    const uint64_t *keys = a.keys[o];
+    uint32_t *beg_a = a.beg[o], *cnt_a = a.cnt[o];
+    int32_t *idx = a.idx[o];
+    // one slab per (workgroup, orientation): both orientations run at once
+    int32_t *buf = BIG ? a.slab + ((uint64_t)blockIdx.y * kBigGrid + blockIdx.x) * a.slab_stride
+                       : s_row;
+
+    for (uint32_t t = blockIdx.x; t < count; t += gridDim.x) {
+        // list entries point at the first batch key of the row, or, for a
+        // re-run after a re-layout, at the first key of the round that did
+        // not fit (earlier rounds were applied)
+        const uint32_t start = list[t];
+        const uint32_t row = key_row(keys[start]);
+        const uint32_t end =
+            start + lower_bound_dev(keys + start, len - start, (uint64_t)(row + 1) << 33);
+        const uint32_t beg = beg_a[row], cap = beg_a[row + 1] - beg;
+        for (uint32_t j0 = start; j0 < end; j0 += kOpsLds) {
+            const uint32_t nops = min((uint32_t)kOpsLds, end - j0);
+            // distinct deletions / insertions of this round (keys are sorted
+            // by col then type, so repeats are adjacent)
+            for (uint32_t q = threadIdx.x; q < kOpsLds; q += kBlock) {
+                uint8_t fd = 0, fi = 0;
+                if (q < nops) {
+                    const uint32_t j = j0 + q;
+                    const uint64_t k = keys[j];
+                    const bool first = j == 0 || keys[j - 1] != k;
+                    fd = first && !(k & 1);
+                    fi = first && (k & 1);
+                }
+                s_fd[q] = fd;
+                s_fi[q] = fi;
+            }
+            __syncthreads();
+            block_scan_u8(s_fd, nops, s_pd, s_tmp);
+            block_scan_u8(s_fi, nops, s_pi, s_tmp);
+            for (uint32_t q = threadIdx.x; q < nops; q += kBlock) {
+                const int32_t col = key_col(keys[j0 + q]);
+                if (s_fd[q]) s_d[s_pd[q]] = col;
+                if (s_fi[q]) s_i[s_pi[q]] = col;
+            }
+            const uint32_t nd = s_pd[nops], ni = s_pi[nops];
+            const uint32_t c = cnt_a[row];
+            for (uint32_t p = threadIdx.x; p < c; p += kBlock) buf[p] = idx[beg + p];
+            __syncthreads();
+            // which entries take effect
+            for (uint32_t q = threadIdx.x; q < nd; q += kBlock) {
+                const uint32_t pos = lower_bound_dev(buf, c, s_d[q]);
+                s_fd[q] = pos < c && buf[pos] == s_d[q];
+            }
+            for (uint32_t q = threadIdx.x; q < ni; q += kBlock) {
+                const int32_t col = s_i[q];
+                const uint32_t pos = lower_bound_dev(buf, c, col);
+                const bool present = pos < c && buf[pos] == col;
+                const uint32_t pd = lower_bound_dev(s_d, nd, col);
+                const bool deleted = pd < nd && s_d[pd] == col;
+                s_fi[q] = !present || deleted;
+            }
+            __syncthreads();
+            block_scan_u8(s_fd, nd, s_pd, s_tmp);
+            block_scan_u8(s_fi, ni, s_pi, s_tmp);
+            const uint32_t ndel = s_pd[nd], nins = s_pi[ni];
+            const uint32_t nc = c - ndel + nins;
+            if (nc > cap) {
+                if (threadIdx.x == 0) {
+                    const uint32_t slot = atomicAdd(&ctl->novf[o], 1u);
+                    a.ovf_list[o][slot] = j0;
+                    a.ovf_need[o][slot] = (int32_t)(c + (end - j0));
+                }
+                __syncthreads();
+                break;
+            }
+            // surviving entries shift left past deletions, right past insertions
+            for (uint32_t p = threadIdx.x; p < c; p += kBlock) {
+                const int32_t e = buf[p];
+                const uint32_t kd = lower_bound_dev(s_d, nd, e);
+                if (kd < nd && s_d[kd] == e) continue;
+                const uint32_t ki = lower_bound_dev(s_i, ni, e);
+                idx[beg + p - s_pd[kd] + s_pi[ki]] = e;
+            }
+            for (uint32_t q = threadIdx.x; q < ni; q += kBlock) {
+                if (!s_fi[q]) continue;
+                const int32_t col = s_i[q];
+                const uint32_t below = lower_bound_dev(buf, c, col) - s_pd[lower_bound_dev(s_d, nd, col)];
+                idx[beg + s_pi[q] + below] = col;
+            }
+            __syncthreads();
+            if (threadIdx.x == 0) {
+                cnt_a[row] = nc;
+                if (o == 1) {
+                    atomicAdd(&ctl->applied[0], (unsigned long long)ndel);
+                    atomicAdd(&ctl->applied[1], (unsigned long long)nins);
+                    // |out(row)| changed: refresh the stored contributions
+                    a.C0[row] = a.R0[row] / (double)nc;
+                    a.C1[row] = a.R1[row] / (double)nc;
+                }
+            }
+            __syncthreads();
+        }
+    }
+}
+
+// ---- re-layout of one orientation after slack overflow --------------------
+
+__global__ void k_caps(int32_t n, const uint32_t *beg, uint64_t *caps)
+{
+    for (int32_t r = blockIdx.x * blockDim.x + threadIdx.x; r <= n; r += gridDim.x * blockDim.x)
+        caps[r] = r < n ? (uint64_t)(beg[r + 1] - beg[r]) : 0;
+}
+
+__global__ void k_ovf_caps(uint32_t count, const uint32_t *list, const int32_t *need,
+                           const uint64_t *keys, uint64_t *caps)
+{
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= count) return;
+    const uint64_t d = (uint64_t)need[i];
+    caps[key_row(keys[list[i]])] = d + (d / 8 > 2 ? d / 8 : 2);
+}
+
+// exclusive scan of caps[0 .. len) in place, 3 phases, 2048 per workgroup
+constexpr int kScanTile = 2048;
+
+__global__ __launch_bounds__(kBlock) void k_scan_sums(const uint64_t *x, uint64_t len,
+                                                      uint64_t *sums)
+{
+    __shared__ uint64_t s[kBlock];
+    const uint64_t base = blockIdx.x * (uint64_t)kScanTile;
+    uint64_t acc = 0;
+    for (int r = 0; r < kScanTile / kBlock; r++) {
+        uint64_t i = base + threadIdx.x * (kScanTile / kBlock) + r;
+        if (i < len) acc += x[i];
+    }
+    s[threadIdx.x] = acc;
+    __syncthreads();
+    for (int st = kBlock / 2; st > 0; st >>= 1) {
+        if (threadIdx.x < st) s[threadIdx.x] += s[threadIdx.x + st];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) sums[blockIdx.x] = s[0];
+}
+
+__global__ __launch_bounds__(kBlock) void k_scan_top(uint64_t *sums, uint32_t nb)
+{
+    __shared__ uint64_t s[kBlock];
+    uint64_t carry = 0;
+    for (uint32_t b0 = 0; b0 < nb; b0 += kBlock) {
+        const uint32_t i = b0 + threadIdx.x;
+        const uint64_t v = i < nb ? sums[i] : 0;
+        s[threadIdx.x] = v;
+        __syncthreads();
+        for (int off = 1; off < kBlock; off <<= 1) {
+            uint64_t t = threadIdx.x >= off ? s[threadIdx.x - off] : 0;
+            __syncthreads();
+            s[threadIdx.x] += t;
+            __syncthreads();
+        }
+        if (i < nb) sums[i] = carry + s[threadIdx.x] - v;
+        const uint64_t tot = s[kBlock - 1];
+        __syncthreads();
+        carry += tot;
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_scan_apply(uint64_t *x, uint64_t len,
+                                                       const uint64_t *sums)
+{
+    __shared__ uint64_t s[kBlock];
+    constexpr int per = kScanTile / kBlock;
+    const uint64_t base = blockIdx.x * (uint64_t)kScanTile + threadIdx.x * per;
+    uint64_t v[per], acc = 0;
+    for (int r = 0; r < per; r++) {
+        v[r] = base + r < len ? x[base + r] : 0;
+        acc += v[r];
+    }
+    s[threadIdx.x] = acc;
+    __syncthreads();
+    for (int off = 1; off < kBlock; off <<= 1) {
+        uint64_t t = threadIdx.x >= off ? s[threadIdx.x - off] : 0;
+        __syncthreads();
+        s[threadIdx.x] += t;
+        __syncthreads();
+    }
+    uint64_t ex = sums[blockIdx.x] + s[threadIdx.x] - acc;
+    for (int r = 0; r < per; r++) {
+        if (base + r < len) x[base + r] = ex;
+        ex += v[r];
+    }
+}
+
+// copy every row's live entries to its new place (one wave per row)
+__global__ __launch_bounds__(kBlock) void k_move_rows(int32_t n, const uint32_t *beg,
+                                                      const uint32_t *cnt, const int32_t *idx,
+                                                      const uint64_t *nbeg, int32_t *nidx,
+                                                      uint32_t *nbeg32)
+{
+    const int lane = __lane_id();
+    const int64_t waves = (int64_t)gridDim.x * (kBlock / kWave);
+    for (int64_t r = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) / kWave; r <= n; r += waves) {
+        if (lane == 0) nbeg32[r] = (uint32_t)nbeg[r];
+        if (r == n) continue;
+        const uint32_t b = beg[r], c = cnt[r];
+        const uint64_t nb = nbeg[r];
+        for (uint32_t k = lane; k < c; k += kWave) nidx[nb + k] = idx[b + k];
+    }
+}
+
+static int ensure_apply_bufs(dfpr_graph *g, uint64_t B)
+{
+    ApplyBufs &ap = g->ap;
+    if (B <= ap.cap) return DFPR_OK;
+    const uint64_t cap = std::max<uint64_t>(B, 4096);
+    for (int o = 0; o < 2; o++) {
+        for (int k = 0; k < 2; k++) {
+            (void)hipFree(ap.keys[o][k]);
+            ap.keys[o][k] = nullptr;
+            DFPR_HIP(hipMalloc(&ap.keys[o][k], cap * 8));
+        }
+        uint32_t **lists[3] = {&ap.small_list[o], &ap.big_list[o], &ap.ovf_list[o]};
+        for (auto l : lists) {
+            (void)hipFree(*l);
+            *l = nullptr;
+            DFPR_HIP(hipMalloc(l, cap * 4));
+        }
+        (void)hipFree(ap.ovf_need[o]);
+        ap.ovf_need[o] = nullptr;
+        DFPR_HIP(hipMalloc(&ap.ovf_need[o], cap * 4));
+    }
+    ap.cap = cap;
+    return DFPR_OK;
+}
+
+static int ensure_slab(dfpr_graph *g)
+{
+    const uint64_t stride = std::max(g->csr[0].max_cap, g->csr[1].max_cap);
+    const uint64_t need = stride * kBigGrid * 2;
+    if (need <= g->ap.slab_ints && g->ap.slab) return DFPR_OK;
+    (void)hipFree(g->ap.slab);
+    g->ap.slab = nullptr;
+    DFPR_HIP(hipMalloc(&g->ap.slab, std::max<uint64_t>(need, 1) * 4));
+    g->ap.slab_ints = need;
+    return DFPR_OK;
+}
+
+static inline unsigned grid_for(uint64_t items, unsigned per = kBlock)
+{
+    return (unsigned)std::max<uint64_t>(1, (items + per - 1) / per);
+}
+
+int stage_batch(dfpr_graph *g, int64_t n_del, const int32_t *ds, const int32_t *dd,
+                int64_t n_ins, const int32_t *is, const int32_t *id, const int32_t **dds,
+                const int32_t **ddd, const int32_t **dis, const int32_t **did)
+{
+    ApplyBufs &ap = g->ap;
+    const uint64_t need = 2 * (uint64_t)(n_del + n_ins);
+    if (need > ap.batch_cap || !ap.batch_dev) {
+        (void)hipFree(ap.batch_dev);
+        ap.batch_dev = nullptr;
+        const uint64_t cap = std::max<uint64_t>(need, 8192);
+        DFPR_HIP(hipMalloc(&ap.batch_dev, cap * 4));
+        ap.batch_cap = cap;
+    }
+    int32_t *p = ap.batch_dev;
+    *dds = p;
+    *ddd = p + n_del;
+    *dis = p + 2 * n_del;
+    *did = p + 2 * n_del + n_ins;
+    hipStream_t s = g->stream;
+    if (n_del) {
+        DFPR_HIP(hipMemcpyAsync(p, ds, n_del * 4, hipMemcpyHostToDevice, s));
+        DFPR_HIP(hipMemcpyAsync(p + n_del, dd, n_del * 4, hipMemcpyHostToDevice, s));
+    }
+    if (n_ins) {
+        DFPR_HIP(hipMemcpyAsync(p + 2 * n_del, is, n_ins * 4, hipMemcpyHostToDevice, s));
+        DFPR_HIP(hipMemcpyAsync(p + 2 * n_del + n_ins, id, n_ins * 4, hipMemcpyHostToDevice, s));
+    }
+    return DFPR_OK;
+}
+
+static ApplyArgs apply_args(dfpr_graph *g)
+{
+    ApplyArgs a{};
+    a.n = g->n;
+    for (int o = 0; o < 2; o++) {
+        a.small_list[o] = g->ap.small_list[o];
+        a.big_list[o] = g->ap.big_list[o];
+        a.ovf_list[o] = g->ap.ovf_list[o];
+        a.ovf_need[o] = g->ap.ovf_need[o];
+        a.beg[o] = g->csr[o].beg;
+        a.cnt[o] = g->csr[o].cnt;
+        a.idx[o] = g->csr[o].idx;
+    }
+    a.R0 = g->R[0];
+    a.R1 = g->R[1];
+    a.C0 = g->C[0];
+    a.C1 = g->C[1];
+    a.slab = g->ap.slab;
+    a.slab_stride = std::max(g->csr[0].max_cap, g->csr[1].max_cap);
+    a.ctl = g->ctl;
+    return a;
+}
+
+// Grow the rows of orientation o listed in the overflow list and move every
+// row to a freshly laid out index array.
+static int relayout(dfpr_graph *g, int o, uint32_t novf, const uint64_t *sorted_keys)
+{
+    hipStream_t s = g->stream;
+    const int32_t n = g->n;
+    Csr &c = g->csr[o];
+    uint64_t *caps = nullptr, *sums = nullptr;
+    const uint64_t len = (uint64_t)n + 1;
+    const uint32_t nb = (uint32_t)((len + kScanTile - 1) / kScanTile);
+    DFPR_HIP(hipMalloc(&caps, len * 8));
+    DFPR_HIP(hipMalloc(&sums, (uint64_t)nb * 8));
+    k_caps<<<grid_for(len), kBlock, 0, s>>>(n, c.beg, caps);
+    k_ovf_caps<<<grid_for(novf), kBlock, 0, s>>>(novf, g->ap.ovf_list[o], g->ap.ovf_need[o],
+                                                 sorted_keys, caps);
+    std::vector<int32_t> need(novf);
+    DFPR_HIP(hipMemcpyAsync(need.data(), g->ap.ovf_need[o], (size_t)novf * 4,
+                            hipMemcpyDeviceToHost, s));
+    k_scan_sums<<<nb, kBlock, 0, s>>>(caps, len, sums);
+    k_scan_top<<<1, kBlock, 0, s>>>(sums, nb);
+    k_scan_apply<<<nb, kBlock, 0, s>>>(caps, len, sums);
+    uint64_t total = 0;
+    DFPR_HIP(hipMemcpyAsync(&total, caps + n, 8, hipMemcpyDeviceToHost, s));
+    DFPR_HIP(hipStreamSynchronize(s));
+    if (total > 0xFFFFFFFFull) {
+        (void)hipFree(caps);
+        (void)hipFree(sums);
+        return set_error(DFPR_E_LIMIT, "graph needs more than 2^32-1 edge slots");
+    }
+    int32_t *nidx = nullptr;
+    uint32_t *nbeg = nullptr;
+    DFPR_HIP(hipMalloc(&nidx, std::max<uint64_t>(total, 1) * 4));
+    DFPR_HIP(hipMalloc(&nbeg, len * 4));
+    k_move_rows<<<4096, kBlock, 0, s>>>(n, c.beg, c.cnt, c.idx, caps, nidx, nbeg);
+    DFPR_HIP(hipGetLastError());
+    DFPR_HIP(hipStreamSynchronize(s));
+    (void)hipFree(c.idx);
+    (void)hipFree(c.beg);
+    (void)hipFree(caps);
+    (void)hipFree(sums);
+    c.idx = nidx;
+    c.beg = nbeg;
+    c.slots = total;
+    for (int32_t d : need) {
+        uint64_t cap = (uint64_t)d + std::max<uint64_t>(2, (uint64_t)d / 8);
+        c.max_cap = std::max<uint32_t>(c.max_cap, (uint32_t)cap);
+    }
+    return DFPR_OK;
+}
+
+int apply_batch_impl(dfpr_graph *g, int64_t n_del, const int32_t *ds, const int32_t *dd,
+                     int64_t n_ins, const int32_t *is, const int32_t *id, int on_device,
+                     int64_t applied[2])
+{
+    if (n_del < 0 || n_ins < 0 || (n_del && (!ds || !dd)) || (n_ins && (!is || !id)))
+        return set_error(DFPR_E_ARG, "bad batch arrays");
+    if (n_del + n_ins >= (1ll << 31)) return set_error(DFPR_E_ARG, "batch too large");
+    if (!on_device) {
+        int rc = check_ids_host(g->n, n_del, ds, dd);
+        if (!rc) rc = check_ids_host(g->n, n_ins, is, id);
+        if (rc) return rc;
+    }
+    if (applied) applied[0] = applied[1] = 0;
+    const uint32_t B = (uint32_t)(n_del + n_ins);
+    if (B == 0) return DFPR_OK;
+    int rc = ensure_apply_bufs(g, B);
+    if (!rc) rc = ensure_slab(g);
+    if (rc) return rc;
+    hipStream_t s = g->stream;
+    if (!on_device) {
+        rc = stage_batch(g, n_del, ds, dd, n_ins, is, id, &ds, &dd, &is, &id);
+        if (rc) return rc;
+    }
+    ApplyArgs a = apply_args(g);
+    a.nd = n_del;
+    a.ni = n_ins;
+    a.ds = ds;
+    a.dd = dd;
+    a.is = is;
+    a.id = id;
+    a.keys[0] = g->ap.keys[0][0];
+    a.keys[1] = g->ap.keys[1][0];
+    k_apply_reset<<<1, 1, 0, s>>>(g->ctl);
+    k_apply_keys<<<grid_for(B), kBlock, 0, s>>>(a);
+    const unsigned tiles = (B + kTile - 1) / kTile;
+    k_tile_sort<<<dim3(tiles, 2), kBlock, 0, s>>>(a.keys[0], a.keys[1], B);
+    int pp = 0;
+    for (uint32_t w = kTile; w < B; w *= 2) {
+        k_merge_pass<<<dim3(grid_for(B), 2), kBlock, 0, s>>>(
+            g->ap.keys[0][pp], g->ap.keys[0][pp ^ 1], g->ap.keys[1][pp], g->ap.keys[1][pp ^ 1], B,
+            w);
+        pp ^= 1;
+    }
+    a.keys[0] = g->ap.keys[0][pp];
+    a.keys[1] = g->ap.keys[1][pp];
+    k_heads<<<dim3(grid_for(B), 2), kBlock, 0, s>>>(a, B);
+    k_apply_rows<false><<<dim3(std::min<unsigned>(B, 8192), 2), kBlock, 0, s>>>(a, B, -1);
+    k_apply_rows<true><<<dim3(kBigGrid, 2), kBlock, 0, s>>>(a, B, -1);
+    DFPR_HIP(hipGetLastError());
+    DFPR_HIP(hipMemcpyAsync(g->ctl_host, g->ctl, sizeof(Ctl), hipMemcpyDeviceToHost, s));
+    DFPR_HIP(hipStreamSynchronize(s));
+    if (g->ctl_host->err) return set_error(DFPR_E_RANGE, "vertex id outside [0, n) in the batch");
+    for (int o = 0; o < 2; o++) {
+        const uint32_t novf = g->ctl_host->novf[o];
+        if (!novf) continue;
+        rc = relayout(g, o, novf, a.keys[o]);
+        if (!rc) rc = ensure_slab(g);
+        if (rc) return rc;
+        // run the merge again for the grown rows only, as "big" rows
+        ApplyArgs b = apply_args(g);
+        b.nd = a.nd;
+        b.ni = a.ni;
+        b.keys[0] = a.keys[0];
+        b.keys[1] = a.keys[1];
+        DFPR_HIP(hipMemcpyAsync(g->ap.big_list[o], g->ap.ovf_list[o], (size_t)novf * 4,
+                                hipMemcpyDeviceToDevice, s));
+        DFPR_HIP(hipMemcpyAsync(&g->ctl->nbig[o], &g->ctl->novf[o], 4, hipMemcpyDeviceToDevice, s));
+        k_apply_rows<true><<<dim3(kBigGrid, 1), kBlock, 0, s>>>(b, B, o);
+        DFPR_HIP(hipGetLastError());
+        DFPR_HIP(hipMemcpyAsync(g->ctl_host, g->ctl, sizeof(Ctl), hipMemcpyDeviceToHost, s));
+        DFPR_HIP(hipStreamSynchronize(s));
+        if (g->ctl_host->novf[o] != novf)
+            return set_error(DFPR_E_DEVICE, "row still overflows after re-layout");
+    }
+    const int64_t eff_del = (int64_t)g->ctl_host->applied[0];
+    const int64_t eff_ins = (int64_t)g->ctl_host->applied[1];
+    g->m += eff_ins - eff_del;
+    if (applied) {
+        applied[0] = eff_del;
+        applied[1] = eff_ins;
+    }
+    return DFPR_OK;
+}
+
+}  // namespace dfpr
+
+using namespace dfpr;
+
+extern "C" {
+
+int dfpr_apply_batch(dfpr_graph *g, int64_t n_del, const int32_t *del_src, const int32_t *del_dst,
+                     int64_t n_ins, const int32_t *ins_src, const int32_t *ins_dst,
+                     int64_t applied[2])
+{
+    if (!g) return set_error(DFPR_E_ARG, "graph is NULL");
+    if (__atomic_exchange_n(&g->busy, 1, __ATOMIC_ACQ_REL)) return set_error(DFPR_E_BUSY, "graph in use");
+    int rc = apply_batch_impl(g, n_del, del_src, del_dst, n_ins, ins_src, ins_dst, 0, applied);
+    __atomic_store_n(&g->busy, 0, __ATOMIC_RELEASE);
+    return rc;
+}
+
+int dfpr_apply_batch_device(dfpr_graph *g, int64_t n_del, const int32_t *del_src,
+                            const int32_t *del_dst, int64_t n_ins, const int32_t *ins_src,
+                            const int32_t *ins_dst, int64_t applied[2])
+{
+    if (!g) return set_error(DFPR_E_ARG, "graph is NULL");
+    if (__atomic_exchange_n(&g->busy, 1, __ATOMIC_ACQ_REL)) return set_error(DFPR_E_BUSY, "graph in use");
+    int rc = apply_batch_impl(g, n_del, del_src, del_dst, n_ins, ins_src, ins_dst, 1, applied);
+    __atomic_store_n(&g->busy, 0, __ATOMIC_RELEASE);
+    return rc;
+}
+
+}  // extern "C"

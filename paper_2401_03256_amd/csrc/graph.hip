@@ -1,0 +1,295 @@
+// Graph store: loading, freeing, export, resident ranks, errors.
+//
+// A graph lives in device memory as two CSRs with per-row slack:
+//   csr[0] (in-edges)  : row v lists G.in(v), used by the pull of Eq. 1;
+//   csr[1] (out-edges) : row u lists G.out(u); its live count is |out(u)|.
+// Loading (not timed by the paper, Section 5.1.5) is done on the host with
+// counting sorts and then copied up once.
+#include <algorithm>
+#include <cstring>
+#include <vector>
+
+#include "common.h"
+
+namespace dfpr {
+
+static thread_local std::string g_last_error;
+
+int set_error(int code, const std::string &msg)
+{
+    g_last_error = msg;
+    return code;
+}
+
+int hip_fail(hipError_t e, const char *what)
+{
+    return set_error(e == hipErrorOutOfMemory ? DFPR_E_NOMEM : DFPR_E_DEVICE,
+                     std::string(what) + ": " + hipGetErrorString(e));
+}
+
+int check_ids_host(int32_t n, int64_t len, const int32_t *a, const int32_t *b)
+{
+    for (int64_t i = 0; i < len; i++)
+        if (a[i] < 0 || a[i] >= n || b[i] < 0 || b[i] >= n)
+            return set_error(DFPR_E_RANGE, "vertex id outside [0, n) at batch entry " +
+                                                std::to_string(i));
+    return DFPR_OK;
+}
+
+// Slack given to a row of `deg` live entries.
+static inline uint64_t row_capacity(uint64_t deg)
+{
+    return deg + std::max<uint64_t>(2, deg / 8);
+}
+
+// Build one padded CSR on the host from sorted rows (off/idx, compacted)
+// and upload it.
+static int upload_csr(Csr &c, int32_t n, const std::vector<uint64_t> &off,
+                      const std::vector<int32_t> &idx)
+{
+    std::vector<uint32_t> beg(n + 1), cnt(n);
+    uint64_t pos = 0;
+    uint32_t max_cap = 0;
+    for (int32_t r = 0; r < n; r++) {
+        uint64_t d = off[r + 1] - off[r];
+        uint64_t cap = row_capacity(d);
+        beg[r] = (uint32_t)pos;
+        cnt[r] = (uint32_t)d;
+        max_cap = std::max<uint32_t>(max_cap, (uint32_t)cap);
+        pos += cap;
+        if (pos > 0xFFFFFFFFull)
+            return set_error(DFPR_E_LIMIT, "graph needs more than 2^32-1 edge slots");
+    }
+    beg[n] = (uint32_t)pos;
+    std::vector<int32_t> slots(pos, -1);
+    for (int32_t r = 0; r < n; r++)
+        std::memcpy(slots.data() + beg[r], idx.data() + off[r], (off[r + 1] - off[r]) * 4);
+    c.slots = pos;
+    c.max_cap = max_cap;
+    DFPR_HIP(hipMalloc(&c.beg, (size_t)(n + 1) * 4));
+    DFPR_HIP(hipMalloc(&c.cnt, (size_t)n * 4));
+    DFPR_HIP(hipMalloc(&c.idx, std::max<size_t>(pos, 1) * 4));
+    DFPR_HIP(hipMemcpy(c.beg, beg.data(), (size_t)(n + 1) * 4, hipMemcpyHostToDevice));
+    DFPR_HIP(hipMemcpy(c.cnt, cnt.data(), (size_t)n * 4, hipMemcpyHostToDevice));
+    DFPR_HIP(hipMemcpy(c.idx, slots.data(), pos * 4, hipMemcpyHostToDevice));
+    return DFPR_OK;
+}
+
+static void free_csr(Csr &c)
+{
+    (void)hipFree(c.beg);
+    (void)hipFree(c.cnt);
+    (void)hipFree(c.idx);
+    c = Csr{};
+}
+
+static int load_impl(int32_t n, int64_t m, const int32_t *src, const int32_t *dst,
+                     dfpr_graph *g)
+{
+    // out-rows: counting sort by source, self-loop included, then sort and
+    // drop repeats inside each row
+    std::vector<uint64_t> ooff(n + 1, 0);
+    for (int64_t i = 0; i < m; i++) ooff[src[i] + 1]++;
+    for (int32_t v = 0; v < n; v++) ooff[v + 1]++;
+    for (int32_t v = 0; v < n; v++) ooff[v + 1] += ooff[v];
+    std::vector<int32_t> oraw(ooff[n]);
+    {
+        std::vector<uint64_t> cur(ooff.begin(), ooff.end() - 1);
+        for (int64_t i = 0; i < m; i++) oraw[cur[src[i]]++] = dst[i];
+        for (int32_t v = 0; v < n; v++) oraw[cur[v]++] = v;
+    }
+    std::vector<uint64_t> oc(n + 1, 0);
+    std::vector<int32_t> oidx;
+    oidx.reserve(oraw.size());
+    for (int32_t u = 0; u < n; u++) {
+        auto b = oraw.begin() + ooff[u], e = oraw.begin() + ooff[u + 1];
+        std::sort(b, e);
+        auto ue = std::unique(b, e);
+        oidx.insert(oidx.end(), b, ue);
+        oc[u + 1] = oidx.size();
+    }
+    std::vector<int32_t>().swap(oraw);
+    g->m = (int64_t)oidx.size();
+    // in-rows: stable counting sort of the out-rows by destination; visiting
+    // sources in increasing order leaves every in-row sorted
+    std::vector<uint64_t> ic(n + 1, 0);
+    for (int32_t v : oidx) ic[v + 1]++;
+    for (int32_t v = 0; v < n; v++) ic[v + 1] += ic[v];
+    std::vector<int32_t> iidx(oidx.size());
+    {
+        std::vector<uint64_t> cur(ic.begin(), ic.end() - 1);
+        for (int32_t u = 0; u < n; u++)
+            for (uint64_t k = oc[u]; k < oc[u + 1]; k++) iidx[cur[oidx[k]]++] = u;
+    }
+    int rc = upload_csr(g->csr[1], n, oc, oidx);
+    if (rc) return rc;
+    return upload_csr(g->csr[0], n, ic, iidx);
+}
+
+}  // namespace dfpr
+
+using namespace dfpr;
+
+extern "C" {
+
+const char *dfpr_last_error(void) { return g_last_error.c_str(); }
+
+void dfpr_params_default(dfpr_params *p)
+{
+    if (!p) return;
+    p->alpha = 0.85;
+    p->tol = 1e-10;
+    p->frontier_tol = 1e-10 / 1e5;
+    p->max_iters = 500;
+    p->precision = DFPR_FP64;
+}
+
+void dfpr_free_graph(dfpr_graph *g)
+{
+    if (!g) return;
+    if (g->stream) (void)hipStreamSynchronize(g->stream);
+    free_csr(g->csr[0]);
+    free_csr(g->csr[1]);
+    for (int b = 0; b < 2; b++) {
+        (void)hipFree(g->R[b]);
+        (void)hipFree(g->C[b]);
+        (void)hipFree(g->C32[b]);
+    }
+    (void)hipFree(g->flags);
+    (void)hipFree(g->bins);
+    (void)hipFree(g->ctl);
+    (void)hipFree(g->scratch_sum);
+    if (g->ctl_host) (void)hipHostFree(g->ctl_host);
+    (void)hipFree(g->it.dr_part);
+    (void)hipFree(g->it.edges_part);
+    (void)hipFree(g->it.verts_part);
+    for (int o = 0; o < 2; o++) {
+        for (int k = 0; k < 2; k++) (void)hipFree(g->ap.keys[o][k]);
+        (void)hipFree(g->ap.small_list[o]);
+        (void)hipFree(g->ap.big_list[o]);
+        (void)hipFree(g->ap.ovf_list[o]);
+        (void)hipFree(g->ap.ovf_need[o]);
+    }
+    (void)hipFree(g->ap.slab);
+    (void)hipFree(g->ap.batch_dev);
+    if (g->ev0) (void)hipEventDestroy(g->ev0);
+    if (g->ev1) (void)hipEventDestroy(g->ev1);
+    if (g->own_stream) (void)hipStreamDestroy(g->own_stream);
+    delete g;
+}
+
+int dfpr_load_graph(int32_t n, int64_t m, const int32_t *src, const int32_t *dst,
+                    dfpr_graph **out)
+{
+    if (!out) return set_error(DFPR_E_ARG, "out is NULL");
+    *out = nullptr;
+    if (n <= 0 || m < 0 || (m > 0 && (!src || !dst)))
+        return set_error(DFPR_E_ARG, "need n >= 1, m >= 0 and non-NULL edge arrays");
+    int rc = check_ids_host(n, m, src, dst);
+    if (rc) return rc;
+    dfpr_graph *g = new dfpr_graph();
+    g->n = n;
+    rc = load_impl(n, m, src, dst, g);
+    if (!rc) {
+        auto al = [&](void **p, size_t bytes) -> int {
+            hipError_t e = hipMalloc(p, std::max<size_t>(bytes, 4));
+            return e == hipSuccess ? 0 : hip_fail(e, "hipMalloc");
+        };
+        size_t nd = (size_t)n * 8;
+        for (int b = 0; b < 2 && !rc; b++) {
+            rc = al((void **)&g->R[b], nd);
+            if (!rc) rc = al((void **)&g->C[b], nd);
+        }
+        if (!rc) rc = al((void **)&g->flags, ((size_t)n + 3) / 4 * 4);
+        if (!rc) rc = al((void **)&g->bins, (size_t)kBins * n * 4);
+        if (!rc) rc = al((void **)&g->ctl, sizeof(Ctl));
+        if (!rc) rc = al((void **)&g->it.dr_part, kMaxGrid * 8);
+        if (!rc) rc = al((void **)&g->it.edges_part, kMaxGrid * 8);
+        if (!rc) rc = al((void **)&g->it.verts_part, kMaxGrid * 8);
+        if (!rc) rc = al((void **)&g->scratch_sum, 4096 * 8);
+    }
+    if (!rc) {
+        hipError_t e = hipHostMalloc((void **)&g->ctl_host, sizeof(Ctl), hipHostMallocDefault);
+        if (e != hipSuccess) rc = hip_fail(e, "hipHostMalloc");
+    }
+    if (!rc) {
+        hipError_t e = hipStreamCreateWithFlags(&g->own_stream, hipStreamNonBlocking);
+        if (e == hipSuccess) e = hipEventCreate(&g->ev0);
+        if (e == hipSuccess) e = hipEventCreate(&g->ev1);
+        if (e != hipSuccess) rc = hip_fail(e, "stream/event");
+        g->stream = g->own_stream;
+    }
+    if (!rc) {
+        hipDeviceProp_t prop;
+        if (hipGetDeviceProperties(&prop, 0) == hipSuccess && prop.multiProcessorCount > 0)
+            g->grid = std::min(kMaxGrid, prop.multiProcessorCount * 4);
+    }
+    if (!rc) {
+        hipError_t e = hipMemsetAsync(g->ctl, 0, sizeof(Ctl), g->stream);
+        if (e != hipSuccess) rc = hip_fail(e, "hipMemsetAsync");
+    }
+    if (!rc) rc = launch_fill_u8(g, g->flags, ((size_t)n + 3) / 4 * 4);
+    if (!rc) rc = dfpr_set_ranks(g, nullptr, 0);   // uniform 1/n
+    if (!rc) {
+        hipError_t e = hipStreamSynchronize(g->stream);
+        if (e != hipSuccess) rc = hip_fail(e, "hipStreamSynchronize");
+    }
+    if (rc) {
+        dfpr_free_graph(g);
+        return rc;
+    }
+    *out = g;
+    return DFPR_OK;
+}
+
+int dfpr_set_stream(dfpr_graph *g, void *hip_stream)
+{
+    if (!g) return set_error(DFPR_E_ARG, "graph is NULL");
+    DFPR_HIP(hipStreamSynchronize(g->stream));
+    g->stream = hip_stream ? (hipStream_t)hip_stream : g->own_stream;
+    return DFPR_OK;
+}
+
+int dfpr_graph_info(const dfpr_graph *g, int32_t *n, int64_t *m)
+{
+    if (!g) return set_error(DFPR_E_ARG, "graph is NULL");
+    if (n) *n = g->n;
+    if (m) *m = g->m;
+    return DFPR_OK;
+}
+
+int dfpr_export_csr(const dfpr_graph *g, int out_orientation, int64_t *offsets, int32_t *idx)
+{
+    if (!g || !offsets || !idx) return set_error(DFPR_E_ARG, "NULL argument");
+    const Csr &c = g->csr[out_orientation ? 1 : 0];
+    int32_t n = g->n;
+    std::vector<uint32_t> beg(n + 1), cnt(n);
+    std::vector<int32_t> slots(c.slots);
+    DFPR_HIP(hipStreamSynchronize(g->stream));
+    DFPR_HIP(hipMemcpy(beg.data(), c.beg, (size_t)(n + 1) * 4, hipMemcpyDeviceToHost));
+    DFPR_HIP(hipMemcpy(cnt.data(), c.cnt, (size_t)n * 4, hipMemcpyDeviceToHost));
+    DFPR_HIP(hipMemcpy(slots.data(), c.idx, c.slots * 4, hipMemcpyDeviceToHost));
+    int64_t pos = 0;
+    for (int32_t r = 0; r < n; r++) {
+        offsets[r] = pos;
+        if (pos + cnt[r] > g->m)
+            return set_error(DFPR_E_DEVICE, "device CSR holds more entries than m");
+        std::memcpy(idx + pos, slots.data() + beg[r], (size_t)cnt[r] * 4);
+        pos += cnt[r];
+    }
+    offsets[n] = pos;
+    if (pos != g->m) return set_error(DFPR_E_DEVICE, "device CSR entry count differs from m");
+    return DFPR_OK;
+}
+
+int dfpr_get_ranks(const dfpr_graph *g, double *ranks, int on_device)
+{
+    if (!g || !ranks) return set_error(DFPR_E_ARG, "NULL argument");
+    DFPR_HIP(hipMemcpyAsync(ranks, g->R[g->cur], (size_t)g->n * 8,
+                            on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost,
+                            g->stream));
+    DFPR_HIP(hipStreamSynchronize(g->stream));
+    return DFPR_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,286 @@
+"""Thin Python binding of libdfpr.so (``include/dfpr.h``).
+
+Argument marshalling only: every step of the method runs in the library's
+HIP kernels.  Host arrays are numpy arrays; device arrays are torch tensors
+on the current HIP device, whose pointers and stream are handed over as
+plain integers.  If the library is missing this module raises; there is no
+fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libdfpr.so")
+
+DFPR_OK = 0
+DFPR_E_ARG = -1
+DFPR_E_RANGE = -2
+DFPR_E_NOMEM = -3
+DFPR_E_DEVICE = -4
+DFPR_E_BUSY = -5
+DFPR_E_LIMIT = -6
+FP64 = 0
+FP32_KAHAN = 1
+
+EXPORTED = [
+    "dfpr_params_default", "dfpr_load_graph", "dfpr_free_graph", "dfpr_set_stream",
+    "dfpr_graph_info", "dfpr_apply_batch", "dfpr_apply_batch_device",
+    "dfpr_pagerank_static", "dfpr_pagerank_naive_dynamic",
+    "dfpr_pagerank_dynamic_frontier", "dfpr_pagerank_dynamic_frontier_device",
+    "dfpr_mark_affected", "dfpr_get_affected", "dfpr_get_ranks", "dfpr_set_ranks",
+    "dfpr_export_csr", "dfpr_last_error",
+]
+
+
+class DfprError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"dfpr error {code}: {msg}")
+        self.code = code
+
+
+class Params(ctypes.Structure):
+    _fields_ = [("alpha", ctypes.c_double), ("tol", ctypes.c_double),
+                ("frontier_tol", ctypes.c_double), ("max_iters", ctypes.c_int32),
+                ("precision", ctypes.c_int32)]
+
+
+class _Stats(ctypes.Structure):
+    _fields_ = [("iterations", ctypes.c_int32), ("converged", ctypes.c_int32),
+                ("refine_sweeps", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("final_linf", ctypes.c_double), ("ms_device", ctypes.c_double),
+                ("affected_initial", ctypes.c_int64), ("affected_final", ctypes.c_int64),
+                ("vertices_processed", ctypes.c_int64), ("edges_processed", ctypes.c_int64)]
+
+
+@dataclass
+class Stats:
+    iterations: int
+    converged: bool
+    refine_sweeps: int
+    final_linf: float
+    ms_device: float
+    affected_initial: int
+    affected_final: int
+    vertices_processed: int
+    edges_processed: int
+
+
+def _stats(s):
+    return Stats(s.iterations, bool(s.converged), s.refine_sweeps, s.final_linf, s.ms_device,
+                 s.affected_initial, s.affected_final, s.vertices_processed, s.edges_processed)
+
+
+_lib = None
+_P = ctypes.c_void_p
+_I32 = ctypes.c_int32
+_I64 = ctypes.c_int64
+
+
+def lib():
+    """Open libdfpr.so.  torch is imported first so that the process holds a
+    single HIP runtime, shared by torch tensors and the library."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is not built; run __graft_entry__.build()")
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
+    L = ctypes.CDLL(LIB_PATH)
+    L.dfpr_params_default.argtypes = [_P]
+    L.dfpr_params_default.restype = None
+    L.dfpr_load_graph.argtypes = [_I32, _I64, _P, _P, ctypes.POINTER(_P)]
+    L.dfpr_free_graph.argtypes = [_P]
+    L.dfpr_free_graph.restype = None
+    L.dfpr_set_stream.argtypes = [_P, _P]
+    L.dfpr_graph_info.argtypes = [_P, _P, _P]
+    batch = [_I64, _P, _P, _I64, _P, _P]
+    L.dfpr_apply_batch.argtypes = [_P, *batch, _P]
+    L.dfpr_apply_batch_device.argtypes = [_P, *batch, _P]
+    L.dfpr_pagerank_static.argtypes = [_P, _P, _P, _P]
+    L.dfpr_pagerank_naive_dynamic.argtypes = [_P, _P, _P, _P, _P]
+    L.dfpr_pagerank_dynamic_frontier.argtypes = [_P, _P, *batch, _P, _P, _P]
+    L.dfpr_pagerank_dynamic_frontier_device.argtypes = [_P, _P, *batch, _P, _P, _P]
+    L.dfpr_mark_affected.argtypes = [_P, *batch, _P]
+    L.dfpr_get_affected.argtypes = [_P, _P]
+    L.dfpr_get_ranks.argtypes = [_P, _P, ctypes.c_int]
+    L.dfpr_set_ranks.argtypes = [_P, _P, ctypes.c_int]
+    L.dfpr_export_csr.argtypes = [_P, ctypes.c_int, _P, _P]
+    L.dfpr_last_error.argtypes = []
+    L.dfpr_last_error.restype = ctypes.c_char_p
+    _lib = L
+    return L
+
+
+def _check(rc):
+    if rc != DFPR_OK:
+        raise DfprError(rc, lib().dfpr_last_error().decode())
+
+
+def _hp(a):
+    return None if a is None else a.ctypes.data_as(_P)
+
+
+def _i32(a):
+    return np.ascontiguousarray(a, dtype=np.int32)
+
+
+def params(alpha=None, tol=None, frontier_tol=None, max_iters=None, precision=None) -> Params:
+    p = Params()
+    lib().dfpr_params_default(ctypes.byref(p))
+    if alpha is not None:
+        p.alpha = alpha
+    if tol is not None:
+        p.tol = tol
+        if frontier_tol is None:
+            p.frontier_tol = tol / 1e5
+    if frontier_tol is not None:
+        p.frontier_tol = frontier_tol
+    if max_iters is not None:
+        p.max_iters = max_iters
+    if precision is not None:
+        p.precision = precision
+    return p
+
+
+def _dev_ptr(t):
+    if t is None:
+        return None
+    if not t.is_cuda or not t.is_contiguous():
+        raise ValueError("device arguments must be contiguous tensors on the GPU")
+    return _P(t.data_ptr())
+
+
+class Graph:
+    """A graph resident on the GPU (both CSRs, ranks, work lists)."""
+
+    def __init__(self, n, src, dst):
+        src, dst = _i32(src), _i32(dst)
+        if src.shape != dst.shape:
+            raise ValueError("src/dst length mismatch")
+        h = _P()
+        _check(lib().dfpr_load_graph(int(n), int(src.size), _hp(src), _hp(dst), ctypes.byref(h)))
+        self._h = h
+        self.n = int(n)
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            lib().dfpr_free_graph(self._h)
+        self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def handle(self):
+        return self._h
+
+    @property
+    def m(self) -> int:
+        m = _I64()
+        _check(lib().dfpr_graph_info(self._h, None, ctypes.byref(m)))
+        return int(m.value)
+
+    def set_stream(self, stream_ptr):
+        _check(lib().dfpr_set_stream(self._h, _P(stream_ptr) if stream_ptr else None))
+
+    def use_torch_stream(self):
+        import torch
+        self.set_stream(torch.cuda.current_stream().cuda_stream)
+
+    # -- graph updates ----------------------------------------------------
+    def apply_batch(self, batch):
+        ds, dd, is_, id_ = (_i32(batch.del_src), _i32(batch.del_dst), _i32(batch.ins_src),
+                            _i32(batch.ins_dst))
+        applied = np.zeros(2, np.int64)
+        _check(lib().dfpr_apply_batch(self._h, ds.size, _hp(ds), _hp(dd), is_.size, _hp(is_),
+                                      _hp(id_), _hp(applied)))
+        return int(applied[0]), int(applied[1])
+
+    def apply_batch_device(self, ds, dd, is_, id_):
+        """Torch int32 tensors on the GPU."""
+        applied = np.zeros(2, np.int64)
+        _check(lib().dfpr_apply_batch_device(self._h, ds.numel(), _dev_ptr(ds), _dev_ptr(dd),
+                                             is_.numel(), _dev_ptr(is_), _dev_ptr(id_),
+                                             _hp(applied)))
+        return int(applied[0]), int(applied[1])
+
+    # -- rank engines -----------------------------------------------------
+    def static(self, p: Params | None = None, out=True):
+        st = _Stats()
+        R = np.empty(self.n, np.float64) if out else None
+        _check(lib().dfpr_pagerank_static(self._h, ctypes.byref(p) if p else None, _hp(R),
+                                          ctypes.byref(st)))
+        return R, _stats(st)
+
+    def naive_dynamic(self, prev=None, p: Params | None = None, out=True):
+        st = _Stats()
+        prev = None if prev is None else np.ascontiguousarray(prev, np.float64)
+        R = np.empty(self.n, np.float64) if out else None
+        _check(lib().dfpr_pagerank_naive_dynamic(self._h, ctypes.byref(p) if p else None,
+                                                 _hp(prev), _hp(R), ctypes.byref(st)))
+        return R, _stats(st)
+
+    def dynamic_frontier(self, batch, prev=None, p: Params | None = None, out=True):
+        ds, dd, is_, id_ = (_i32(batch.del_src), _i32(batch.del_dst), _i32(batch.ins_src),
+                            _i32(batch.ins_dst))
+        prev = None if prev is None else np.ascontiguousarray(prev, np.float64)
+        R = np.empty(self.n, np.float64) if out else None
+        st = _Stats()
+        _check(lib().dfpr_pagerank_dynamic_frontier(
+            self._h, ctypes.byref(p) if p else None, ds.size, _hp(ds), _hp(dd), is_.size,
+            _hp(is_), _hp(id_), _hp(prev), _hp(R), ctypes.byref(st)))
+        return R, _stats(st)
+
+    def dynamic_frontier_device(self, ds, dd, is_, id_, prev=None, out=None,
+                                p: Params | None = None):
+        """Batch as torch int32 GPU tensors; prev/out optional float64 GPU tensors."""
+        st = _Stats()
+        _check(lib().dfpr_pagerank_dynamic_frontier_device(
+            self._h, ctypes.byref(p) if p else None, ds.numel(), _dev_ptr(ds), _dev_ptr(dd),
+            is_.numel(), _dev_ptr(is_), _dev_ptr(id_), _dev_ptr(prev), _dev_ptr(out),
+            ctypes.byref(st)))
+        return _stats(st)
+
+    # -- inspection ---------------------------------------------------------
+    def mark_affected(self, batch):
+        ds, dd, is_, id_ = (_i32(batch.del_src), _i32(batch.del_dst), _i32(batch.ins_src),
+                            _i32(batch.ins_dst))
+        flags = np.zeros(self.n, np.uint8)
+        _check(lib().dfpr_mark_affected(self._h, ds.size, _hp(ds), _hp(dd), is_.size, _hp(is_),
+                                        _hp(id_), _hp(flags)))
+        return flags
+
+    def affected(self):
+        flags = np.zeros(self.n, np.uint8)
+        _check(lib().dfpr_get_affected(self._h, _hp(flags)))
+        return flags
+
+    def ranks(self):
+        R = np.empty(self.n, np.float64)
+        _check(lib().dfpr_get_ranks(self._h, _hp(R), 0))
+        return R
+
+    def ranks_device(self, out):
+        _check(lib().dfpr_get_ranks(self._h, _dev_ptr(out), 1))
+        return out
+
+    def set_ranks(self, R=None):
+        R = None if R is None else np.ascontiguousarray(R, np.float64)
+        _check(lib().dfpr_set_ranks(self._h, _hp(R), 0))
+
+    def csr(self, out: bool):
+        off = np.zeros(self.n + 1, np.int64)
+        idx = np.zeros(max(self.m, 1), np.int32)
+        _check(lib().dfpr_export_csr(self._h, 1 if out else 0, _hp(off), _hp(idx)))
+        return off, idx[: self.m]

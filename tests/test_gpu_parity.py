@@ -1,0 +1,321 @@
+"""GPU parity: the HIP library against the CPU oracle on the same seeded
+inputs.  Integer results (CSRs, applied counts, initial marks) must be
+bit-exact; FP64 ranks must agree within 1e-9 in L-inf."""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle import brute
+from paper_2401_03256_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+TOL_RANK = 1e-9       # FP64 ranks, L-inf
+
+
+@pytest.fixture(scope="module")
+def dfpr():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_2401_03256_amd import dfpr as mod
+    mod.lib()
+    return mod
+
+
+def _say(msg):
+    sys.stdout.write(f"\n[case] {msg}\n")
+    sys.stdout.flush()
+
+
+def _pair(dfpr, n, src, dst):
+    return dfpr.Graph(n, src, dst), oracle.OracleGraph(n, src, dst)
+
+
+def _same_csr(g, o):
+    for out in (True, False):
+        a_off, a_idx = g.csr(out)
+        b_off, b_idx = o.csr(out)
+        assert np.array_equal(a_off, b_off), f"offsets differ (out={out})"
+        assert np.array_equal(a_idx, b_idx), f"indices differ (out={out})"
+
+
+def _arr(pairs):
+    if not pairs:
+        return np.zeros(0, np.int32), np.zeros(0, np.int32)
+    a = np.array(pairs, dtype=np.int32)
+    return a[:, 0].copy(), a[:, 1].copy()
+
+
+def _batch(dels, ins):
+    return synth.Batch(*_arr(dels), *_arr(ins))
+
+
+# ---------------------------------------------------------------------------
+# graph store and batch applier (bit-exact)
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("case", ["gnm", "rmat12", "grid", "single"])
+def test_load_matches_oracle(dfpr, case):
+    _say(f"load {case}")
+    if case == "gnm":
+        n = 3000
+        src, dst = synth.gnm(n, 20000, seed=1)
+    elif case == "rmat12":
+        n, src, dst = synth.rmat(12, 16, seed=2)
+        # repeated edges and ids in any order are accepted
+        src = np.concatenate([src, src[:500]])[::-1].copy()
+        dst = np.concatenate([dst, dst[:500]])[::-1].copy()
+    elif case == "grid":
+        n, src, dst = synth.grid2d(40, 0.05, seed=3)
+    else:
+        n, src, dst = 1, np.zeros(0, np.int32), np.zeros(0, np.int32)
+    g, o = _pair(dfpr, n, src, dst)
+    assert g.m == o.m
+    _same_csr(g, o)
+
+
+def test_apply_messy_batches_match_oracle(dfpr):
+    rng = np.random.default_rng(7)
+    n = 500
+    src, dst = synth.gnm(n, 4000, seed=5)
+    g, o = _pair(dfpr, n, src, dst)
+    for step in range(12):
+        _say(f"messy batch {step}")
+        k = int(rng.integers(0, 300))
+        # deletions: mostly existing edges, some absent, some self-loops, repeats
+        off, idx = o.csr(True)
+        rows = np.repeat(np.arange(n), np.diff(off))
+        pick = rng.integers(0, idx.size, k)
+        ds, dd = rows[pick], idx[pick]
+        ds = np.concatenate([ds, rng.integers(0, n, 20), np.arange(5)])
+        dd = np.concatenate([dd, rng.integers(0, n, 20), np.arange(5)])
+        is_ = rng.integers(0, n, k + 30)
+        id_ = rng.integers(0, n, k + 30)
+        is_ = np.concatenate([is_, is_[:10], ds[:5]])   # repeats, present edges, re-inserts
+        id_ = np.concatenate([id_, id_[:10], dd[:5]])
+        b = synth.Batch(ds.astype(np.int32), dd.astype(np.int32), is_.astype(np.int32),
+                        id_.astype(np.int32))
+        assert g.apply_batch(b) == o.apply_batch(b)
+        assert g.m == o.m
+        _same_csr(g, o)
+
+
+def test_apply_forces_overflow_and_big_rows(dfpr):
+    # a hub with a long in-row and out-row (beyond the LDS copy), then batches
+    # far larger than the slack of the touched rows
+    n = 12000
+    leaves = np.arange(1, 9001, dtype=np.int32)
+    src = np.concatenate([leaves, np.zeros(9000, np.int32), np.arange(9001, n - 1)])
+    dst = np.concatenate([np.zeros(9000, np.int32), leaves, np.arange(9002, n)])
+    g, o = _pair(dfpr, n, src, dst)
+    _same_csr(g, o)
+    rng = np.random.default_rng(3)
+    for step in range(4):
+        _say(f"overflow batch {step}")
+        hub_del = rng.choice(leaves, 700, replace=False)
+        new = rng.integers(9001, n, 3000).astype(np.int32)
+        b = synth.Batch(
+            np.concatenate([hub_del, np.zeros(300, np.int32)]).astype(np.int32),
+            np.concatenate([np.zeros(700, np.int32), rng.choice(leaves, 300)]).astype(np.int32),
+            np.concatenate([new, np.full(2500, 9005, np.int32)]),
+            np.concatenate([np.zeros(3000, np.int32), rng.integers(0, n, 2500).astype(np.int32)]))
+        assert g.apply_batch(b) == o.apply_batch(b)
+        _same_csr(g, o)
+
+
+def test_apply_rejects_out_of_range_unchanged(dfpr):
+    n = 100
+    src, dst = synth.gnm(n, 400, seed=1)
+    g, o = _pair(dfpr, n, src, dst)
+    before = g.csr(True)
+    with pytest.raises(dfpr.DfprError) as e:
+        g.apply_batch(_batch([(0, 1)], [(3, n)]))
+    assert e.value.code == dfpr.DFPR_E_RANGE
+    after = g.csr(True)
+    assert np.array_equal(before[1], after[1])
+    _same_csr(g, o)
+
+
+def test_apply_device_arrays(dfpr):
+    import torch
+    n = 2000
+    src, dst = synth.gnm(n, 12000, seed=9)
+    g, o = _pair(dfpr, n, src, dst)
+    b = synth.random_batch(src, dst, n, 40, 160, seed=4)
+    t = [torch.from_numpy(np.ascontiguousarray(x)).cuda() for x in
+         (b.del_src, b.del_dst, b.ins_src, b.ins_dst)]
+    torch.cuda.synchronize()
+    assert g.apply_batch_device(*t) == o.apply_batch(b) == (40, 160)
+    _same_csr(g, o)
+
+
+# ---------------------------------------------------------------------------
+# marking (bit-exact)
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("seed", [1, 2, 3])
+def test_initial_marking_bit_exact(dfpr, seed):
+    _say(f"marking seed {seed}")
+    n, src, dst = synth.rmat(11, 8, seed=seed)
+    g, o = _pair(dfpr, n, src, dst)
+    b = synth.random_batch(src, dst, n, 25, 100, seed=seed + 10)
+    g.apply_batch(b)
+    o.apply_batch(b)
+    f_gpu = g.mark_affected(b)
+    f_ref = o.mark_initial(b)
+    assert np.array_equal(f_gpu, f_ref)
+    # marks are cleared afterwards: marking twice gives the same set
+    assert np.array_equal(g.mark_affected(b), f_ref)
+
+
+# ---------------------------------------------------------------------------
+# ranks (FP64, 1e-9 L-inf)
+# ---------------------------------------------------------------------------
+
+def test_closed_form_star_on_gpu(dfpr):
+    n, k = 5000, 1200      # the centre's rows exceed the per-group sizes
+    leaves = np.arange(1, k + 1, dtype=np.int32)
+    src = np.concatenate([np.zeros(k, np.int32), leaves])
+    dst = np.concatenate([leaves, np.zeros(k, np.int32)])
+    g = dfpr.Graph(n, src, dst)
+    R, st = g.static(dfpr.params(tol=1e-15))
+    D = 2 * (k + 1) + 0.85 * (k - 1)
+    assert abs(R[0] - (k + 1) / n * (2 + 0.85 * (k - 1)) / D) < 1e-14
+    assert np.max(np.abs(R[1:k + 1] - (k + 1) / n * 2 / D)) < 1e-14
+    assert np.max(np.abs(R[k + 1:] - 1.0 / n)) < 1e-15
+
+
+@pytest.mark.parametrize("case", ["c0", "rmat13", "grid"])
+def test_static_and_naive_match_oracle(dfpr, case):
+    _say(f"static {case}")
+    if case == "c0":
+        n = 10000
+        src, dst = synth.gnm(n, 80000, seed=1)
+    elif case == "rmat13":
+        n, src, dst = synth.rmat(13, 16, seed=1)
+    else:
+        n, src, dst = synth.grid2d(60, 0.05, seed=2)
+    g, o = _pair(dfpr, n, src, dst)
+    R, st = g.static()
+    Ro, sto = o.static()
+    assert st.converged
+    assert np.max(np.abs(R - Ro)) < TOL_RANK
+    assert abs(st.iterations - sto.iterations) <= 1
+    assert abs(math.fsum(R) - 1.0) < 1e-9
+    b = synth.random_batch(src, dst, n, 20, 80, seed=3)
+    g.apply_batch(b)
+    o.apply_batch(b)
+    Rn, stn = g.naive_dynamic()
+    Rno, _ = o.naive_dynamic(Ro)
+    assert stn.converged
+    assert np.max(np.abs(Rn - Rno)) < TOL_RANK
+    Rref, _ = o.reference()
+    assert np.max(np.abs(Rn - Rref)) < TOL_RANK
+
+
+def test_dynamic_frontier_config0(dfpr):
+    # 10,000 vertices, 80,000 uniform edges + self-loops; one batch of 80
+    # (64 new pairs, 16 deleted edges); alpha 0.85, tol 1e-10, tau_f 1e-13
+    n = 10000
+    src, dst = synth.gnm(n, 80000, seed=1)
+    g, o = _pair(dfpr, n, src, dst)
+    p = dfpr.params(tol=1e-10, frontier_tol=1e-13)
+    R0, _ = g.static(p)
+    R0o, _ = o.static()
+    nd, ni = synth.batch_counts(80 / o.m, o.m)
+    assert (nd, ni) == (16, 64)
+    b = synth.random_batch(src, dst, n, nd, ni, seed=1)
+    assert g.apply_batch(b) == o.apply_batch(b) == (16, 64)
+    assert np.array_equal(g.mark_affected(b), o.mark_initial(b))
+    R, st = g.dynamic_frontier(b, p=p)
+    Ro, sto, f0, f1 = o.dynamic_frontier(b, R0o, frontier_tol=1e-13, return_flags=True)
+    assert st.converged and sto.converged
+    assert st.affected_initial == sto.affected_initial == int(f0.sum())
+    assert np.max(np.abs(R - Ro)) < TOL_RANK
+    Rref, _ = o.reference()
+    assert np.max(np.abs(R - Rref)) < TOL_RANK
+    fg = g.affected()
+    assert fg.sum() > 0 and np.all(fg >= f0)       # marks only grow
+    assert abs(int(fg.sum()) - int(f1.sum())) <= max(5, f1.sum() // 100)
+    # same work as the oracle up to marks that flip near tau_f
+    assert abs(st.iterations - sto.iterations) <= 1
+    assert abs(st.vertices_processed - sto.vertices_processed) <= 0.02 * sto.vertices_processed
+
+
+def test_dynamic_frontier_sequence_rmat(dfpr):
+    n, src, dst = synth.rmat(13, 16, seed=4)
+    g, o = _pair(dfpr, n, src, dst)
+    R0, _ = g.static()
+    Ro, _ = o.static()
+    m = o.m
+    counts = [synth.batch_counts(f, m) for f in (1e-4, 1e-3, 1e-2, 1e-4, 1e-3)]
+    seq = synth.batch_sequence(src, dst, n, counts, seed=11)
+    for i, b in enumerate(seq):
+        _say(f"df sequence step {i}, batch {b.size}")
+        assert g.apply_batch(b) == o.apply_batch(b)
+        R, st = g.dynamic_frontier(b)
+        Ro, sto = o.dynamic_frontier(b, Ro)
+        assert st.converged
+        assert np.max(np.abs(R - Ro)) < TOL_RANK
+    Rref, _ = o.reference()
+    assert np.max(np.abs(R - Rref)) < TOL_RANK
+    _same_csr(g, o)
+
+
+def test_dynamic_frontier_special_cases(dfpr):
+    n = 3000
+    src, dst = synth.gnm(n, 20000, seed=8)
+    g = dfpr.Graph(n, src, dst)
+    R0, _ = g.static()
+    # empty batch: previous ranks come back unchanged after one iteration
+    R, st = g.dynamic_frontier(synth.Batch.empty())
+    assert np.array_equal(R, R0) and st.iterations == 1 and st.converged
+    # out-of-range id: error, ranks untouched
+    with pytest.raises(dfpr.DfprError):
+        g.dynamic_frontier(_batch([], [(0, n)]))
+    assert np.array_equal(g.ranks(), R0)
+    # tau_f = inf: the final marks are the initial marks
+    b = synth.random_batch(src, dst, n, 3, 9, seed=2)
+    g.apply_batch(b)
+    R1, st = g.dynamic_frontier(b, p=dfpr.params(frontier_tol=math.inf))
+    assert st.affected_final == st.affected_initial
+    # determinism: same start, same batch -> bitwise equal ranks
+    Ra, _ = g.dynamic_frontier(b, prev=R0)
+    Rb, _ = g.dynamic_frontier(b, prev=R0)
+    assert np.array_equal(Ra, Rb)
+
+
+def test_untouched_component_bitwise(dfpr):
+    nA, nB = 3000, 2000
+    sa, da = synth.gnm(nA, 20000, seed=1)
+    sb, db = synth.gnm(nB, 12000, seed=2)
+    n = nA + nB
+    g = dfpr.Graph(n, np.concatenate([sa, sb + nA]), np.concatenate([da, db + nA]))
+    R0, _ = g.static()
+    b = synth.random_batch(sa, da, nA, 5, 20, seed=3)
+    g.apply_batch(b)
+    R, st = g.dynamic_frontier(b)
+    assert np.array_equal(R[nA:], R0[nA:])
+    assert not g.affected()[nA:].any()
+
+
+def test_dynamic_frontier_device_entry(dfpr):
+    import torch
+    n, src, dst = synth.rmat(12, 16, seed=6)
+    g, o = _pair(dfpr, n, src, dst)
+    g.use_torch_stream()
+    R0, _ = g.static()
+    Ro, _ = o.static()
+    b = synth.random_batch(src, dst, n, 10, 40, seed=5)
+    t = [torch.from_numpy(np.ascontiguousarray(x)).cuda() for x in
+         (b.del_src, b.del_dst, b.ins_src, b.ins_dst)]
+    assert g.apply_batch_device(*t) == o.apply_batch(b)
+    out = torch.empty(n, dtype=torch.float64, device="cuda")
+    st = g.dynamic_frontier_device(*t, out=out)
+    torch.cuda.synchronize()
+    Ro, _ = o.dynamic_frontier(b, Ro)
+    assert np.max(np.abs(out.cpu().numpy() - Ro)) < TOL_RANK
+    assert st.converged
