@@ -1,0 +1,240 @@
+#!/usr/bin/env python3
+"""Benchmark: Dynamic Frontier PageRank updates on one MI355X.
+
+Workload (default): R-MAT scale 22 (4,194,304 vertices), edge factor 16,
+a=0.57 b=0.19 c=0.19 d=0.05, duplicates removed, a self-loop on every vertex,
+FP64 ranks, alpha 0.85, tol 1e-10 (L-inf), frontier tolerance 1e-13.  A
+sequence of uniformly random batches (80% insertions of new pairs, 20%
+deletions of existing edges) cycling through 1e-7, 1e-5 and 1e-3 of |E|,
+every batch distinct, with the ranks carried from one batch to the next.
+
+One step = apply the batch to both device CSRs + one Dynamic Frontier
+update (initial marking, iterations to convergence), with the batch already
+in device memory.  value = in-edges gathered by all timed updates divided by
+the wall time of the timed steps (GTEPS).  Latency p50/p99 are over the
+timed steps.
+
+Prints one JSON line on stdout; progress goes to stderr.
+"""
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "GTEPS (edges/s) + update latency p50/p99 per batch; FP32 vs FP64 at 1e-9 L∞"
+HBM_PEAK_GBS = 8000.0
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_iter_traffic.json")
+KERNEL_SRC = os.path.join(ROOT, "paper_2401_03256_amd", "csrc", "rank.hip")
+
+
+def log(*a):
+    print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+def pct(xs, q):
+    xs = sorted(xs)
+    if not xs:
+        return None
+    k = (len(xs) - 1) * q / 100.0
+    lo, hi = math.floor(k), math.ceil(k)
+    return xs[lo] + (xs[hi] - xs[lo]) * (k - lo)
+
+
+def kernel_hash():
+    with open(KERNEL_SRC, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def measured_traffic(workload):
+    """HBM bytes per iteration launch from committed rocprofv3 counter runs,
+    if they were taken on the current kernel source for this workload."""
+    try:
+        with open(TRAFFIC_FILE) as f:
+            t = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if t.get("kernel_sha") != kernel_hash() or t.get("workload") != workload:
+        return None
+    return t.get("bytes_per_launch")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=15)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--scale", type=int, default=22)
+    ap.add_argument("--edge-factor", type=int, default=16)
+    ap.add_argument("--fracs", default="1e-7,1e-5,1e-3")
+    ap.add_argument("--frontier-tol", type=float, default=1e-13)
+    ap.add_argument("--cpu-seconds", type=float, default=20.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: this build runs the whole update on a "
+              "single MI355X (see DESIGN.md for how it would shard); use --gpus 1",
+              file=sys.stderr)
+        sys.exit(2)
+    if int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py is single-process", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2401_03256_amd import dfpr, synth
+
+    assert torch.cuda.is_available(), "no GPU"
+    torch.cuda.set_device(0)
+    dfpr.lib()
+    fracs = [float(x) for x in args.fracs.split(",")]
+    workload = f"rmat{args.scale}_ef{args.edge_factor}_df_fp64"
+
+    t = time.time()
+    n, src, dst = synth.rmat(args.scale, args.edge_factor, seed=1)
+    log(f"R-MAT scale {args.scale}: n={n} edges={src.size} ({time.time() - t:.1f}s)")
+    t = time.time()
+    g = dfpr.Graph(n, src, dst)
+    g.use_torch_stream()
+    m = g.m
+    log(f"loaded on GPU: m={m} incl. self-loops ({time.time() - t:.1f}s)")
+
+    total = args.warmup + args.steps
+    counts = [synth.batch_counts(fracs[i % len(fracs)], m) for i in range(total)]
+    seq = synth.batch_sequence(src, dst, n, counts, seed=2)
+    dev = [[torch.from_numpy(np.ascontiguousarray(x)).cuda()
+            for x in (b.del_src, b.del_dst, b.ins_src, b.ins_dst)] for b in seq]
+    torch.cuda.synchronize()
+    p = dfpr.params(frontier_tol=args.frontier_tol)
+
+    t = time.time()
+    R0, st0 = g.static(p)
+    log(f"static: {st0.iterations} it, {st0.ms_device:.2f} ms device "
+        f"({st0.edges_processed / st0.ms_device / 1e6:.1f} GTEPS)")
+
+    def step(i):
+        g.apply_batch_device(*dev[i])
+        return g.dynamic_frontier_device(*dev[i], p=p)
+
+    warm_ranks = []
+    for i in range(args.warmup):
+        st = step(i)
+        warm_ranks.append(g.ranks())
+        log(f"warmup {i}: batch {seq[i].size}, {st.iterations} it, "
+            f"affected {st.affected_final}, {st.ms_device:.2f} ms")
+
+    g.profile_reset(True)
+    lat, edges, per = [], 0, {}
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.warmup, total):
+        ts = time.perf_counter()
+        st = step(i)
+        dt = time.perf_counter() - ts
+        lat.append(dt * 1e3)
+        edges += st.edges_processed
+        f = fracs[i % len(fracs)]
+        per.setdefault(f, []).append((dt * 1e3, st.iterations, st.affected_final,
+                                      st.edges_processed))
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    prof = g.profile()
+    g.profile_reset(False)
+    elapsed = t1 - t0
+    value = edges / elapsed / 1e9
+    log(f"timed: {args.steps} steps in {elapsed * 1e3:.1f} ms, {value:.2f} GTEPS")
+
+    # comparators on the final graph (not timed): Static and Naive-dynamic
+    Rn, stn = g.naive_dynamic(p=p)
+    _, sts = g.static(p)
+    comparators = {
+        "static_ms": round(sts.ms_device, 3), "static_iterations": sts.iterations,
+        "naive_dynamic_ms": round(stn.ms_device, 3),
+        "naive_dynamic_iterations": stn.iterations,
+        "df_ms_mean_by_frac": {str(f): round(float(np.mean([x[0] for x in v])), 3)
+                               for f, v in sorted(per.items())},
+        "df_iterations_by_frac": {str(f): round(float(np.mean([x[1] for x in v])), 1)
+                                  for f, v in sorted(per.items())},
+        "df_affected_by_frac": {str(f): int(np.mean([x[2] for x in v]))
+                                for f, v in sorted(per.items())},
+    }
+    comparators["speedup_vs_static_by_frac"] = {
+        k: round(sts.ms_device / v, 2) for k, v in comparators["df_ms_mean_by_frac"].items()}
+    comparators["speedup_vs_naive_by_frac"] = {
+        k: round(stn.ms_device / v, 2) for k, v in comparators["df_ms_mean_by_frac"].items()}
+
+    achieved = prof.bytes / (prof.ms / 1e3) / 1e9 if prof.ms > 0 else 0.0
+    tb = measured_traffic(workload)
+    roofline = {
+        "bound": "hbm", "kernel": "k_iter<true> (pull + Delta r + L-inf + expand)",
+        "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+        "frac": round(achieved / HBM_PEAK_GBS, 4),
+        "traffic": None if tb is None else round(tb, 1),
+        "launches": prof.launches, "avg_launch_us": round(prof.ms * 1e3 / max(prof.launches, 1), 2),
+        "algorithmic_bytes_per_launch": round(prof.bytes / max(prof.launches, 1), 1),
+    }
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline(n, src, dst, seq, R0, warm_ranks, args, log)
+
+    out = {
+        "metric": METRIC, "value": round(value, 3), "unit": "GTEPS", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(elapsed * 1e3 / args.steps, 3),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": workload, "graph": f"R-MAT scale {args.scale}", "n": n, "m": m,
+                   "edge_factor": args.edge_factor, "rmat_abcd": [0.57, 0.19, 0.19, 0.05],
+                   "batch_fracs": fracs, "insert_frac": 0.8, "alpha": 0.85, "tol": 1e-10,
+                   "frontier_tol": args.frontier_tol, "parallelism": "single GPU"},
+        "latency_ms": {"p50": round(pct(lat, 50), 3), "p99": round(pct(lat, 99), 3),
+                       "by_frac_p50": {str(f): round(pct([x[0] for x in v], 50), 3)
+                                       for f, v in sorted(per.items())}},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "comparators": comparators,
+    }
+    print(json.dumps(out), flush=True)
+
+
+def cpu_baseline(n, src, dst, seq, R0, warm_ranks, args, log):
+    """The oracle (plain C, OpenMP) on the host cores, timed over marking +
+    iterations (Section 5.1.5 excludes the graph update), on the first
+    batches of the same sequence until about --cpu-seconds have been spent.
+    Also reports how far the GPU's ranks for those batches are from the
+    oracle's."""
+    import oracle
+    oracle.build(force=False)
+    t = time.time()
+    o = oracle.OracleGraph(n, src, dst)
+    log(f"oracle loaded ({time.time() - t:.1f}s, {oracle.num_threads()} threads)")
+    R = R0
+    spent, edges, used, linf = 0.0, 0, 0, 0.0
+    for i, b in enumerate(seq[: len(warm_ranks)]):
+        o.apply_batch(b)
+        t = time.perf_counter()
+        R, st = o.dynamic_frontier(b, R, frontier_tol=args.frontier_tol)
+        dt = time.perf_counter() - t
+        spent += dt
+        edges += st.edges_processed
+        used += 1
+        linf = max(linf, float(np.max(np.abs(R - warm_ranks[i]))))
+        log(f"oracle batch {i}: {b.size} edges, {st.iterations} it, {dt:.2f}s")
+        if spent >= args.cpu_seconds:
+            break
+    return {"value": round(edges / spent / 1e9, 4), "unit": "GTEPS",
+            "cores": oracle.num_threads(), "kind": "oracle",
+            "sample": f"Dynamic Frontier (mark + iterate) on the first {used} batches of the "
+                      f"same sequence and graph, {spent:.1f}s of CPU time",
+            "gpu_vs_oracle_linf": linf}
+
+
+if __name__ == "__main__":
+    main()

@@ -199,6 +199,32 @@ int dfpr_set_ranks(dfpr_graph *g, const double *ranks, int on_device);
 int dfpr_export_csr(const dfpr_graph *g, int out_orientation, int64_t *offsets,
                     int32_t *idx);
 
+/* Profile of the iteration kernel (the pull, Delta r, L-inf and expansion
+ * of one iteration), summed over every call made while profiling is on.
+ * ms is measured with HIP events recorded on the graph's stream around each
+ * chunk of back-to-back iteration launches, so it includes the short gaps
+ * between those launches.  bytes is the algorithmic traffic of those
+ * launches: per processed row 40 bytes (list entry, row start and length,
+ * R[v], |out(v)|, the two written values) plus 12 per in-edge (index and
+ * gathered FP64 contribution); per expanding row 8 bytes plus 5 per
+ * out-edge (index and mark); per newly marked vertex 8 bytes. */
+typedef struct {
+    int64_t launches;        /* iteration-kernel launches                  */
+    double ms;               /* their device time                          */
+    double bytes;            /* their algorithmic bytes                    */
+    int64_t rows;            /* rank updates                               */
+    int64_t edges;           /* in-edges gathered                          */
+    int64_t expanded_rows;   /* rows whose change exceeded frontier_tol     */
+    int64_t expanded_edges;  /* out-edges those rows scanned               */
+    int64_t marked;          /* vertices newly marked by expansion          */
+} dfpr_profile;
+
+/* Zero the profile and switch profiling on (enable != 0) or off. */
+int dfpr_profile_reset(dfpr_graph *g, int enable);
+
+/* Read the profile accumulated since the last dfpr_profile_reset. */
+int dfpr_profile_read(const dfpr_graph *g, dfpr_profile *out);
+
 /* Message for the last non-OK status returned on this thread. */
 const char *dfpr_last_error(void);
 

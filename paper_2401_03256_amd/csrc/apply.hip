@@ -17,10 +17,12 @@
 //      new entry straight to its final slot (positions from prefix counts
 //      and binary searches), keeping the row sorted.  The out-orientation
 //      pass also refreshes the row's contribution R/|out|.
-//   5. a row whose slack is too small is left for a re-layout: new
-//      capacities, a prefix sum, a copy of every row to its new place, and
-//      the merge is run again for those rows (a no-op for the parts already
-//      applied).
+//   5. a row whose slots are too few is written instead to fresh slots
+//      taken from the free space at the end of the index array (one atomic
+//      add on the array's top).  Only when that space is used up is the row
+//      left for a re-layout: new capacities, a prefix sum, a copy of every
+//      row to its new place with fresh free space, and the merge is run
+//      again from the round that did not fit.
 #include <algorithm>
 #include <vector>
 
@@ -67,8 +69,9 @@ struct ApplyArgs {
     uint64_t *keys[2];          // unsorted / sorted keys per orientation
     uint32_t *small_list[2], *big_list[2], *ovf_list[2];
     int32_t *ovf_need[2];
-    uint32_t *beg[2], *cnt[2];
+    uint32_t *beg[2], *cnt[2], *cap[2];
     int32_t *idx[2];
+    uint64_t slots[2];
     double *R0, *R1, *C0, *C1;
     int32_t *slab;
     uint64_t slab_stride;
@@ -166,7 +169,7 @@ __global__ void k_heads(ApplyArgs a, uint32_t len)
         if (k != kSentinel) {
             const uint32_t r = key_row(k);
             head = i == 0 || key_row(keys[i - 1]) != r;
-            if (head) big = (a.beg[o][r + 1] - a.beg[o][r]) > (uint32_t)kRowLds;
+            if (head) big = a.cap[o][r] > (uint32_t)kRowLds;
         }
     }
     const int lane = __lane_id();
@@ -226,6 +229,8 @@ __global__ __launch_bounds__(kBlock) void k_apply_rows(ApplyArgs a, uint32_t len
     __shared__ uint32_t s_pi[kOpsLds + 1];
     __shared__ uint32_t s_tmp[kBlock];
     __shared__ int32_t s_row[BIG ? 1 : kRowLds];
+    __shared__ uint32_t s_dest, s_ncap;
+    __shared__ int s_ok;
 
     const int o = only_o >= 0 ? only_o : blockIdx.y;
     if (only_o >= 0 && blockIdx.y > 0) return;
@@ -234,7 +239,7 @@ __global__ __launch_bounds__(kBlock) void k_apply_rows(ApplyArgs a, uint32_t len
     const uint32_t count = BIG ? ctl->nbig[o] : ctl->nsmall[o];
     const uint32_t *list = BIG ? a.big_list[o] : a.small_list[o];
     const uint64_t *keys = a.keys[o];
-    uint32_t *beg_a = a.beg[o], *cnt_a = a.cnt[o];
+    uint32_t *beg_a = a.beg[o], *cnt_a = a.cnt[o], *cap_a = a.cap[o];
     int32_t *idx = a.idx[o];
     // one slab per (workgroup, orientation): both orientations run at once
     int32_t *buf = BIG ? a.slab + ((uint64_t)blockIdx.y * kBigGrid + blockIdx.x) * a.slab_stride
@@ -248,8 +253,8 @@ __global__ __launch_bounds__(kBlock) void k_apply_rows(ApplyArgs a, uint32_t len
         const uint32_t row = key_row(keys[start]);
         const uint32_t end =
             start + lower_bound_dev(keys + start, len - start, (uint64_t)(row + 1) << 33);
-        const uint32_t beg = beg_a[row], cap = beg_a[row + 1] - beg;
         for (uint32_t j0 = start; j0 < end; j0 += kOpsLds) {
+            const uint32_t beg = beg_a[row], cap = cap_a[row];
             const uint32_t nops = min((uint32_t)kOpsLds, end - j0);
             // distinct deletions / insertions of this round (keys are sorted
             // by col then type, so repeats are adjacent)
@@ -275,6 +280,16 @@ __global__ __launch_bounds__(kBlock) void k_apply_rows(ApplyArgs a, uint32_t len
             }
             const uint32_t nd = s_pd[nops], ni = s_pi[nops];
             const uint32_t c = cnt_a[row];
+            if (BIG && c > a.slab_stride) {
+                // the slab cannot hold this row: leave it to a re-layout
+                if (threadIdx.x == 0) {
+                    const uint32_t slot = atomicAdd(&ctl->novf[o], 1u);
+                    a.ovf_list[o][slot] = j0;
+                    a.ovf_need[o][slot] = (int32_t)(c + (end - j0));
+                }
+                __syncthreads();
+                break;
+            }
             for (uint32_t p = threadIdx.x; p < c; p += kBlock) buf[p] = idx[beg + p];
             __syncthreads();
             // which entries take effect
@@ -295,32 +310,48 @@ __global__ __launch_bounds__(kBlock) void k_apply_rows(ApplyArgs a, uint32_t len
             block_scan_u8(s_fi, ni, s_pi, s_tmp);
             const uint32_t ndel = s_pd[nd], nins = s_pi[ni];
             const uint32_t nc = c - ndel + nins;
-            if (nc > cap) {
-                if (threadIdx.x == 0) {
-                    const uint32_t slot = atomicAdd(&ctl->novf[o], 1u);
-                    a.ovf_list[o][slot] = j0;
-                    a.ovf_need[o][slot] = (int32_t)(c + (end - j0));
+            if (threadIdx.x == 0) {
+                s_dest = beg;
+                s_ncap = cap;
+                s_ok = 1;
+                if (nc > cap) {
+                    // move the row to fresh slots at the top of the array
+                    const uint64_t want = (uint64_t)nc + (nc / 8 > 2 ? nc / 8 : 2);
+                    const uint64_t at = atomicAdd(&ctl->top[o], (unsigned long long)want);
+                    if (want <= 0xFFFFFFFFull && at + want <= a.slots[o]) {
+                        s_dest = (uint32_t)at;
+                        s_ncap = (uint32_t)want;
+                        atomicMax(&ctl->max_cap[o], (uint32_t)want);
+                    } else {
+                        s_ok = 0;
+                        const uint32_t slot = atomicAdd(&ctl->novf[o], 1u);
+                        a.ovf_list[o][slot] = j0;
+                        a.ovf_need[o][slot] = (int32_t)(c + (end - j0));
+                    }
                 }
-                __syncthreads();
-                break;
             }
+            __syncthreads();
+            if (!s_ok) break;
+            const uint32_t dest = s_dest;
             // surviving entries shift left past deletions, right past insertions
             for (uint32_t p = threadIdx.x; p < c; p += kBlock) {
                 const int32_t e = buf[p];
                 const uint32_t kd = lower_bound_dev(s_d, nd, e);
                 if (kd < nd && s_d[kd] == e) continue;
                 const uint32_t ki = lower_bound_dev(s_i, ni, e);
-                idx[beg + p - s_pd[kd] + s_pi[ki]] = e;
+                idx[dest + p - s_pd[kd] + s_pi[ki]] = e;
             }
             for (uint32_t q = threadIdx.x; q < ni; q += kBlock) {
                 if (!s_fi[q]) continue;
                 const int32_t col = s_i[q];
                 const uint32_t below = lower_bound_dev(buf, c, col) - s_pd[lower_bound_dev(s_d, nd, col)];
-                idx[beg + s_pi[q] + below] = col;
+                idx[dest + s_pi[q] + below] = col;
             }
             __syncthreads();
             if (threadIdx.x == 0) {
                 cnt_a[row] = nc;
+                beg_a[row] = dest;
+                cap_a[row] = s_ncap;
                 if (o == 1) {
                     atomicAdd(&ctl->applied[0], (unsigned long long)ndel);
                     atomicAdd(&ctl->applied[1], (unsigned long long)nins);
@@ -336,19 +367,23 @@ __global__ __launch_bounds__(kBlock) void k_apply_rows(ApplyArgs a, uint32_t len
 
 // ---- re-layout of one orientation after slack overflow --------------------
 
-__global__ void k_caps(int32_t n, const uint32_t *beg, uint64_t *caps)
+__global__ void k_caps(int32_t n, const uint32_t *cap, uint64_t *caps)
 {
     for (int32_t r = blockIdx.x * blockDim.x + threadIdx.x; r <= n; r += gridDim.x * blockDim.x)
-        caps[r] = r < n ? (uint64_t)(beg[r + 1] - beg[r]) : 0;
+        caps[r] = r < n ? (uint64_t)cap[r] : 0;
 }
 
+// Grown capacity for each row left for the re-layout (in both tables).
 __global__ void k_ovf_caps(uint32_t count, const uint32_t *list, const int32_t *need,
-                           const uint64_t *keys, uint64_t *caps)
+                           const uint64_t *keys, uint64_t *caps, uint32_t *cap)
 {
     const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= count) return;
     const uint64_t d = (uint64_t)need[i];
-    caps[key_row(keys[list[i]])] = d + (d / 8 > 2 ? d / 8 : 2);
+    const uint32_t r = key_row(keys[list[i]]);
+    const uint64_t c = d + (d / 8 > 2 ? d / 8 : 2);
+    caps[r] = c;
+    cap[r] = (uint32_t)c;
 }
 
 // exclusive scan of caps[0 .. len) in place, 3 phases, 2048 per workgroup
@@ -422,19 +457,17 @@ __global__ __launch_bounds__(kBlock) void k_scan_apply(uint64_t *x, uint64_t len
 }
 
 // copy every row's live entries to its new place (one wave per row)
-__global__ __launch_bounds__(kBlock) void k_move_rows(int32_t n, const uint32_t *beg,
+__global__ __launch_bounds__(kBlock) void k_move_rows(int32_t n, uint32_t *beg,
                                                       const uint32_t *cnt, const int32_t *idx,
-                                                      const uint64_t *nbeg, int32_t *nidx,
-                                                      uint32_t *nbeg32)
+                                                      const uint64_t *nbeg, int32_t *nidx)
 {
     const int lane = __lane_id();
     const int64_t waves = (int64_t)gridDim.x * (kBlock / kWave);
-    for (int64_t r = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) / kWave; r <= n; r += waves) {
-        if (lane == 0) nbeg32[r] = (uint32_t)nbeg[r];
-        if (r == n) continue;
+    for (int64_t r = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) / kWave; r < n; r += waves) {
         const uint32_t b = beg[r], c = cnt[r];
         const uint64_t nb = nbeg[r];
         for (uint32_t k = lane; k < c; k += kWave) nidx[nb + k] = idx[b + k];
+        if (lane == 0) beg[r] = (uint32_t)nb;
     }
 }
 
@@ -467,11 +500,15 @@ static int ensure_slab(dfpr_graph *g)
 {
     const uint64_t stride = std::max(g->csr[0].max_cap, g->csr[1].max_cap);
     const uint64_t need = stride * kBigGrid * 2;
-    if (need <= g->ap.slab_ints && g->ap.slab) return DFPR_OK;
+    if (need <= g->ap.slab_ints && g->ap.slab) {
+        g->ap.slab_stride = g->ap.slab_ints / (kBigGrid * 2);
+        return DFPR_OK;
+    }
     (void)hipFree(g->ap.slab);
     g->ap.slab = nullptr;
     DFPR_HIP(hipMalloc(&g->ap.slab, std::max<uint64_t>(need, 1) * 4));
     g->ap.slab_ints = need;
+    g->ap.slab_stride = stride;
     return DFPR_OK;
 }
 
@@ -521,20 +558,22 @@ static ApplyArgs apply_args(dfpr_graph *g)
         a.ovf_need[o] = g->ap.ovf_need[o];
         a.beg[o] = g->csr[o].beg;
         a.cnt[o] = g->csr[o].cnt;
+        a.cap[o] = g->csr[o].cap;
         a.idx[o] = g->csr[o].idx;
+        a.slots[o] = g->csr[o].slots;
     }
     a.R0 = g->R[0];
     a.R1 = g->R[1];
     a.C0 = g->C[0];
     a.C1 = g->C[1];
     a.slab = g->ap.slab;
-    a.slab_stride = std::max(g->csr[0].max_cap, g->csr[1].max_cap);
+    a.slab_stride = g->ap.slab_stride;
     a.ctl = g->ctl;
     return a;
 }
 
 // Grow the rows of orientation o listed in the overflow list and move every
-// row to a freshly laid out index array.
+// row to a freshly laid out index array (with new free space at its end).
 static int relayout(dfpr_graph *g, int o, uint32_t novf, const uint64_t *sorted_keys)
 {
     hipStream_t s = g->stream;
@@ -545,39 +584,38 @@ static int relayout(dfpr_graph *g, int o, uint32_t novf, const uint64_t *sorted_
     const uint32_t nb = (uint32_t)((len + kScanTile - 1) / kScanTile);
     DFPR_HIP(hipMalloc(&caps, len * 8));
     DFPR_HIP(hipMalloc(&sums, (uint64_t)nb * 8));
-    k_caps<<<grid_for(len), kBlock, 0, s>>>(n, c.beg, caps);
+    k_caps<<<grid_for(len), kBlock, 0, s>>>(n, c.cap, caps);
     k_ovf_caps<<<grid_for(novf), kBlock, 0, s>>>(novf, g->ap.ovf_list[o], g->ap.ovf_need[o],
-                                                 sorted_keys, caps);
+                                                 sorted_keys, caps, c.cap);
     std::vector<int32_t> need(novf);
     DFPR_HIP(hipMemcpyAsync(need.data(), g->ap.ovf_need[o], (size_t)novf * 4,
                             hipMemcpyDeviceToHost, s));
     k_scan_sums<<<nb, kBlock, 0, s>>>(caps, len, sums);
     k_scan_top<<<1, kBlock, 0, s>>>(sums, nb);
     k_scan_apply<<<nb, kBlock, 0, s>>>(caps, len, sums);
-    uint64_t total = 0;
-    DFPR_HIP(hipMemcpyAsync(&total, caps + n, 8, hipMemcpyDeviceToHost, s));
+    uint64_t packed = 0;
+    DFPR_HIP(hipMemcpyAsync(&packed, caps + n, 8, hipMemcpyDeviceToHost, s));
     DFPR_HIP(hipStreamSynchronize(s));
-    if (total > 0xFFFFFFFFull) {
+    const uint64_t slots = packed + std::max<uint64_t>(packed / 16, 1 << 16);
+    if (slots > 0xFFFFFFFFull) {
         (void)hipFree(caps);
         (void)hipFree(sums);
         return set_error(DFPR_E_LIMIT, "graph needs more than 2^32-1 edge slots");
     }
     int32_t *nidx = nullptr;
-    uint32_t *nbeg = nullptr;
-    DFPR_HIP(hipMalloc(&nidx, std::max<uint64_t>(total, 1) * 4));
-    DFPR_HIP(hipMalloc(&nbeg, len * 4));
-    k_move_rows<<<4096, kBlock, 0, s>>>(n, c.beg, c.cnt, c.idx, caps, nidx, nbeg);
+    DFPR_HIP(hipMalloc(&nidx, slots * 4));
+    k_move_rows<<<4096, kBlock, 0, s>>>(n, c.beg, c.cnt, c.idx, caps, nidx);
     DFPR_HIP(hipGetLastError());
+    const unsigned long long top = packed;
+    DFPR_HIP(hipMemcpyAsync(&g->ctl->top[o], &top, 8, hipMemcpyHostToDevice, s));
     DFPR_HIP(hipStreamSynchronize(s));
     (void)hipFree(c.idx);
-    (void)hipFree(c.beg);
     (void)hipFree(caps);
     (void)hipFree(sums);
     c.idx = nidx;
-    c.beg = nbeg;
-    c.slots = total;
+    c.slots = slots;
     for (int32_t d : need) {
-        uint64_t cap = (uint64_t)d + std::max<uint64_t>(2, (uint64_t)d / 8);
+        const uint64_t cap = (uint64_t)d + std::max<uint64_t>(2, (uint64_t)d / 8);
         c.max_cap = std::max<uint32_t>(c.max_cap, (uint32_t)cap);
     }
     return DFPR_OK;
@@ -635,6 +673,9 @@ int apply_batch_impl(dfpr_graph *g, int64_t n_del, const int32_t *ds, const int3
     DFPR_HIP(hipMemcpyAsync(g->ctl_host, g->ctl, sizeof(Ctl), hipMemcpyDeviceToHost, s));
     DFPR_HIP(hipStreamSynchronize(s));
     if (g->ctl_host->err) return set_error(DFPR_E_RANGE, "vertex id outside [0, n) in the batch");
+    g->sched_dirty = 1;
+    for (int o = 0; o < 2; o++)
+        g->csr[o].max_cap = std::max(g->csr[o].max_cap, g->ctl_host->max_cap[o]);
     for (int o = 0; o < 2; o++) {
         const uint32_t novf = g->ctl_host->novf[o];
         if (!novf) continue;

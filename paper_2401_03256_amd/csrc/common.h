@@ -10,64 +10,89 @@
 
 namespace dfpr {
 
-constexpr int kBlock = 256;          // threads per workgroup (4 wave64)
+constexpr int kBlock = 256;            // threads per workgroup (4 wave64)
 constexpr int kWave = 64;
-constexpr int kBins = 6;             // in-degree classes of the pull
-constexpr int kMaxGrid = 4096;       // upper bound on iteration-kernel grids
+constexpr int kWavesPerBlock = kBlock / kWave;
+constexpr int kBins = 7;               // in-degree classes of the pull
+constexpr int kMaxGrid = 8192;         // upper bound on iteration-kernel grids
 constexpr uint64_t kSentinel = ~0ull;  // batch key of an entry that changes nothing
+constexpr int kCounters = 4;           // rows, in-edges, expanded rows, their out-edges
 
-// In-degree classes.  A row of class b is reduced by a group of
-// kGroup[b] lanes; class 5 rows take a whole workgroup.
+// In-degree classes.  A row of class b < 6 is reduced by a group of
+// group_of(b) lanes of one wave; class 6 rows take a whole workgroup.
 __host__ __device__ inline int bin_of(uint32_t deg)
 {
-    return deg <= 4 ? 0 : deg <= 8 ? 1 : deg <= 16 ? 2 : deg <= 32 ? 3 : deg <= 1024 ? 4 : 5;
+    return deg <= 4 ? 0 : deg <= 8 ? 1 : deg <= 16 ? 2 : deg <= 32 ? 3 : deg <= 128 ? 4
+           : deg <= 1024 ? 5 : 6;
+}
+__host__ __device__ constexpr int group_of(int bin)
+{
+    return bin == 0 ? 1 : bin == 1 ? 2 : bin == 2 ? 4 : bin == 3 ? 8 : bin == 4 ? 32
+           : bin == 5 ? 64 : kBlock;
 }
 
 // Device control block of a graph (zeroed at creation).
 struct Ctl {
-    uint32_t live[kBins];       // entries appended to each class list
+    uint32_t live[kBins];       // entries appended to each class list (sparse mode)
     uint32_t snap[2][kBins];    // entries iteration i processes: snap[i & 1]
     uint32_t ticket;            // workgroups finished in the current iteration
     uint32_t done;              // iteration loop finished (or aborted)
+    uint32_t dense;             // iterations walk the full schedule
     int32_t iterations;
     int32_t converged;
     double final_linf;
     unsigned long long edges;   // in-edges gathered, all iterations
     unsigned long long verts;   // rank updates, all iterations
+    unsigned long long xverts;  // rows that expanded (Delta r > frontier_tol)
+    unsigned long long xedges;  // out-edges scanned by those expansions
+    unsigned long long marked;  // vertices newly marked (sparse mode count)
+    unsigned long long affected0;   // marks after the initial marking
+    unsigned long long affected;    // marks when the call ended
     uint32_t err;               // an id outside [0, n) was seen
     uint32_t nsmall[2];         // batch applier: touched rows per orientation
     uint32_t nbig[2];           //   ... rows whose capacity exceeds the LDS copy
-    uint32_t novf[2];           //   ... rows whose slack was too small
-    uint32_t pad0;
+    uint32_t novf[2];           //   ... rows that need a re-layout
+    uint32_t max_cap[2];        //   largest row capacity
+    unsigned long long top[2];  //   first free slot of each index array
     unsigned long long applied[2];  // effective deletions, insertions
-    unsigned long long affected0;   // marks after the initial marking
 };
 
 // One orientation of the graph: row r holds cnt[r] sorted ids in
-// idx[beg[r] .. beg[r] + cnt[r]) and owns the slots up to beg[r+1].
+// idx[beg[r] .. beg[r] + cnt[r]) and owns cap[r] slots from beg[r].  Rows
+// that outgrow their slots move to free space at ctl->top.
 struct Csr {
-    uint32_t *beg = nullptr;    // n + 1 capacity offsets
+    uint32_t *beg = nullptr;    // n
     uint32_t *cnt = nullptr;    // n live counts
-    int32_t *idx = nullptr;     // beg[n] slots
+    uint32_t *cap = nullptr;    // n capacities
+    int32_t *idx = nullptr;     // `slots` entries
     uint64_t slots = 0;
-    uint32_t max_cap = 0;       // largest row capacity
+    uint32_t max_cap = 0;       // largest row capacity (host copy)
 };
 
 struct IterBufs {
-    double *dr_part = nullptr;                 // per-workgroup L-inf partials
-    unsigned long long *edges_part = nullptr;  // per-workgroup edge counts
-    unsigned long long *verts_part = nullptr;
+    double *dr_part = nullptr;                // per-workgroup L-inf partials
+    unsigned long long *cnt_part = nullptr;   // per-workgroup counters (kCounters each)
+};
+
+// Host-side profile of the iteration kernel (see dfpr_profile in dfpr.h).
+struct Profile {
+    int enabled = 0;
+    int64_t launches = 0;
+    double ms = 0.0;
+    double bytes = 0.0;
+    int64_t rows = 0, edges = 0, exp_rows = 0, exp_edges = 0, marked = 0;
 };
 
 struct ApplyBufs {
     uint64_t cap = 0;               // batch entries the buffers hold
     uint64_t *keys[2][2] = {};      // [orientation][ping-pong]
-    uint32_t *small_list[2] = {};   // op-start index of touched rows
+    uint32_t *small_list[2] = {};   // op index where each touched row starts
     uint32_t *big_list[2] = {};
     uint32_t *ovf_list[2] = {};
     int32_t *ovf_need[2] = {};      // capacity an overflowed row needs
     int32_t *slab = nullptr;        // row copies of big rows
     uint64_t slab_ints = 0;
+    uint64_t slab_stride = 0;
     int32_t *batch_dev = nullptr;   // staging for host batches (4 arrays)
     uint64_t batch_cap = 0;
 };
@@ -81,8 +106,16 @@ struct dfpr_graph {
     double *R[2] = {};                // rank double buffer
     double *C[2] = {};                // contribution R[v] / |out(v)|
     int cur = 0;                      // buffer holding the resident ranks
-    uint8_t *flags = nullptr;         // affected marks (n rounded up to 4)
-    int32_t *bins = nullptr;          // kBins lists of n entries each
+    uint32_t *stamp = nullptr;        // iteration a vertex was marked (see rank.hip)
+    uint32_t *xstamp = nullptr;       // call in which a vertex expanded
+    uint32_t next_base = 1;           // stamp base of the next call
+    uint32_t last_base = 0;           // stamp base and iterations of the last
+    int32_t last_iters = -1;          //   Dynamic Frontier call
+    int32_t *bins = nullptr;          // kBins appended lists of n entries (sparse mode)
+    int32_t *sched = nullptr;         // all vertices by class, sorted (dense mode)
+    uint32_t *sched_off = nullptr;    // kBins + 1 offsets into sched (device)
+    uint32_t *sched_tmp = nullptr;    // per-workgroup class counts for the build
+    int sched_dirty = 1;              // in-degrees changed since the build
     dfpr::Ctl *ctl = nullptr;         // device
     dfpr::Ctl *ctl_host = nullptr;    // pinned mirror
     dfpr::IterBufs it;
@@ -92,8 +125,11 @@ struct dfpr_graph {
     hipStream_t stream = nullptr;
     hipStream_t own_stream = nullptr;
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    hipEvent_t evk0 = nullptr, evk1 = nullptr;   // around chunks of iteration launches
+    dfpr::Profile prof;
     int busy = 0;
     int grid = 1024;                  // iteration-kernel workgroups
+    uint32_t sparse_limit = 0;        // frontier size that switches to the schedule
 };
 
 namespace dfpr {
@@ -101,9 +137,9 @@ namespace dfpr {
 int set_error(int code, const std::string &msg);
 int hip_fail(hipError_t e, const char *what);
 
-#define DFPR_HIP(call)                                      \
-    do {                                                    \
-        hipError_t e_ = (call);                             \
+#define DFPR_HIP(call)                                          \
+    do {                                                        \
+        hipError_t e_ = (call);                                 \
         if (e_ != hipSuccess) return dfpr::hip_fail(e_, #call); \
     } while (0)
 
@@ -118,7 +154,6 @@ int stage_batch(dfpr_graph *g, int64_t n_del, const int32_t *ds, const int32_t *
 int check_ids_host(int32_t n, int64_t len, const int32_t *a, const int32_t *b);
 
 // device helpers (rank.hip)
-int launch_fill_u8(dfpr_graph *g, uint8_t *p, uint64_t len);
-int recompute_contrib(dfpr_graph *g);
+int launch_fill_u32(dfpr_graph *g, uint32_t *p, uint64_t len, uint32_t value);
 
 }  // namespace dfpr

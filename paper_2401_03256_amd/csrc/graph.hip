@@ -42,36 +42,46 @@ static inline uint64_t row_capacity(uint64_t deg)
     return deg + std::max<uint64_t>(2, deg / 8);
 }
 
-// Build one padded CSR on the host from sorted rows (off/idx, compacted)
-// and upload it.
-static int upload_csr(Csr &c, int32_t n, const std::vector<uint64_t> &off,
-                      const std::vector<int32_t> &idx)
+// Free slots kept after the packed rows for rows that outgrow their slack.
+static inline uint64_t spill_reserve(uint64_t packed)
 {
-    std::vector<uint32_t> beg(n + 1), cnt(n);
+    return std::max<uint64_t>(packed / 16, 1 << 16);
+}
+
+// Build one padded CSR on the host from sorted rows (off/idx, compacted)
+// and upload it.  *top receives the first free slot.
+static int upload_csr(Csr &c, int32_t n, const std::vector<uint64_t> &off,
+                      const std::vector<int32_t> &idx, uint32_t *top)
+{
+    std::vector<uint32_t> beg(n), cnt(n), cap(n);
     uint64_t pos = 0;
     uint32_t max_cap = 0;
     for (int32_t r = 0; r < n; r++) {
         uint64_t d = off[r + 1] - off[r];
-        uint64_t cap = row_capacity(d);
+        uint64_t cp = row_capacity(d);
         beg[r] = (uint32_t)pos;
         cnt[r] = (uint32_t)d;
-        max_cap = std::max<uint32_t>(max_cap, (uint32_t)cap);
-        pos += cap;
-        if (pos > 0xFFFFFFFFull)
-            return set_error(DFPR_E_LIMIT, "graph needs more than 2^32-1 edge slots");
+        cap[r] = (uint32_t)cp;
+        max_cap = std::max<uint32_t>(max_cap, (uint32_t)cp);
+        pos += cp;
     }
-    beg[n] = (uint32_t)pos;
-    std::vector<int32_t> slots(pos, -1);
+    const uint64_t slots = pos + spill_reserve(pos);
+    if (slots > 0xFFFFFFFFull)
+        return set_error(DFPR_E_LIMIT, "graph needs more than 2^32-1 edge slots");
+    std::vector<int32_t> packed(pos, -1);
     for (int32_t r = 0; r < n; r++)
-        std::memcpy(slots.data() + beg[r], idx.data() + off[r], (off[r + 1] - off[r]) * 4);
-    c.slots = pos;
+        std::memcpy(packed.data() + beg[r], idx.data() + off[r], (off[r + 1] - off[r]) * 4);
+    c.slots = slots;
     c.max_cap = max_cap;
-    DFPR_HIP(hipMalloc(&c.beg, (size_t)(n + 1) * 4));
+    *top = (uint32_t)pos;
+    DFPR_HIP(hipMalloc(&c.beg, (size_t)n * 4));
     DFPR_HIP(hipMalloc(&c.cnt, (size_t)n * 4));
-    DFPR_HIP(hipMalloc(&c.idx, std::max<size_t>(pos, 1) * 4));
-    DFPR_HIP(hipMemcpy(c.beg, beg.data(), (size_t)(n + 1) * 4, hipMemcpyHostToDevice));
+    DFPR_HIP(hipMalloc(&c.cap, (size_t)n * 4));
+    DFPR_HIP(hipMalloc(&c.idx, slots * 4));
+    DFPR_HIP(hipMemcpy(c.beg, beg.data(), (size_t)n * 4, hipMemcpyHostToDevice));
     DFPR_HIP(hipMemcpy(c.cnt, cnt.data(), (size_t)n * 4, hipMemcpyHostToDevice));
-    DFPR_HIP(hipMemcpy(c.idx, slots.data(), pos * 4, hipMemcpyHostToDevice));
+    DFPR_HIP(hipMemcpy(c.cap, cap.data(), (size_t)n * 4, hipMemcpyHostToDevice));
+    if (pos) DFPR_HIP(hipMemcpy(c.idx, packed.data(), pos * 4, hipMemcpyHostToDevice));
     return DFPR_OK;
 }
 
@@ -79,12 +89,13 @@ static void free_csr(Csr &c)
 {
     (void)hipFree(c.beg);
     (void)hipFree(c.cnt);
+    (void)hipFree(c.cap);
     (void)hipFree(c.idx);
     c = Csr{};
 }
 
 static int load_impl(int32_t n, int64_t m, const int32_t *src, const int32_t *dst,
-                     dfpr_graph *g)
+                     dfpr_graph *g, uint32_t top[2])
 {
     // out-rows: counting sort by source, self-loop included, then sort and
     // drop repeats inside each row
@@ -121,9 +132,9 @@ static int load_impl(int32_t n, int64_t m, const int32_t *src, const int32_t *ds
         for (int32_t u = 0; u < n; u++)
             for (uint64_t k = oc[u]; k < oc[u + 1]; k++) iidx[cur[oidx[k]]++] = u;
     }
-    int rc = upload_csr(g->csr[1], n, oc, oidx);
+    int rc = upload_csr(g->csr[1], n, oc, oidx, &top[1]);
     if (rc) return rc;
-    return upload_csr(g->csr[0], n, ic, iidx);
+    return upload_csr(g->csr[0], n, ic, iidx, &top[0]);
 }
 
 }  // namespace dfpr
@@ -155,14 +166,17 @@ void dfpr_free_graph(dfpr_graph *g)
         (void)hipFree(g->C[b]);
         (void)hipFree(g->C32[b]);
     }
-    (void)hipFree(g->flags);
+    (void)hipFree(g->stamp);
+    (void)hipFree(g->xstamp);
     (void)hipFree(g->bins);
+    (void)hipFree(g->sched);
+    (void)hipFree(g->sched_off);
+    (void)hipFree(g->sched_tmp);
     (void)hipFree(g->ctl);
     (void)hipFree(g->scratch_sum);
     if (g->ctl_host) (void)hipHostFree(g->ctl_host);
     (void)hipFree(g->it.dr_part);
-    (void)hipFree(g->it.edges_part);
-    (void)hipFree(g->it.verts_part);
+    (void)hipFree(g->it.cnt_part);
     for (int o = 0; o < 2; o++) {
         for (int k = 0; k < 2; k++) (void)hipFree(g->ap.keys[o][k]);
         (void)hipFree(g->ap.small_list[o]);
@@ -174,6 +188,8 @@ void dfpr_free_graph(dfpr_graph *g)
     (void)hipFree(g->ap.batch_dev);
     if (g->ev0) (void)hipEventDestroy(g->ev0);
     if (g->ev1) (void)hipEventDestroy(g->ev1);
+    if (g->evk0) (void)hipEventDestroy(g->evk0);
+    if (g->evk1) (void)hipEventDestroy(g->evk1);
     if (g->own_stream) (void)hipStreamDestroy(g->own_stream);
     delete g;
 }
@@ -189,7 +205,8 @@ int dfpr_load_graph(int32_t n, int64_t m, const int32_t *src, const int32_t *dst
     if (rc) return rc;
     dfpr_graph *g = new dfpr_graph();
     g->n = n;
-    rc = load_impl(n, m, src, dst, g);
+    uint32_t top[2] = {0, 0};
+    rc = load_impl(n, m, src, dst, g, top);
     if (!rc) {
         auto al = [&](void **p, size_t bytes) -> int {
             hipError_t e = hipMalloc(p, std::max<size_t>(bytes, 4));
@@ -200,12 +217,15 @@ int dfpr_load_graph(int32_t n, int64_t m, const int32_t *src, const int32_t *dst
             rc = al((void **)&g->R[b], nd);
             if (!rc) rc = al((void **)&g->C[b], nd);
         }
-        if (!rc) rc = al((void **)&g->flags, ((size_t)n + 3) / 4 * 4);
+        if (!rc) rc = al((void **)&g->stamp, (size_t)n * 4);
+        if (!rc) rc = al((void **)&g->xstamp, (size_t)n * 4);
         if (!rc) rc = al((void **)&g->bins, (size_t)kBins * n * 4);
+        if (!rc) rc = al((void **)&g->sched, (size_t)n * 4);
+        if (!rc) rc = al((void **)&g->sched_off, (kBins + 1) * 4);
+        if (!rc) rc = al((void **)&g->sched_tmp, ((size_t)n / 4096 + 1) * kBins * 4);
         if (!rc) rc = al((void **)&g->ctl, sizeof(Ctl));
         if (!rc) rc = al((void **)&g->it.dr_part, kMaxGrid * 8);
-        if (!rc) rc = al((void **)&g->it.edges_part, kMaxGrid * 8);
-        if (!rc) rc = al((void **)&g->it.verts_part, kMaxGrid * 8);
+        if (!rc) rc = al((void **)&g->it.cnt_part, (size_t)kMaxGrid * kCounters * 8);
         if (!rc) rc = al((void **)&g->scratch_sum, 4096 * 8);
     }
     if (!rc) {
@@ -216,19 +236,29 @@ int dfpr_load_graph(int32_t n, int64_t m, const int32_t *src, const int32_t *dst
         hipError_t e = hipStreamCreateWithFlags(&g->own_stream, hipStreamNonBlocking);
         if (e == hipSuccess) e = hipEventCreate(&g->ev0);
         if (e == hipSuccess) e = hipEventCreate(&g->ev1);
+        if (e == hipSuccess) e = hipEventCreate(&g->evk0);
+        if (e == hipSuccess) e = hipEventCreate(&g->evk1);
         if (e != hipSuccess) rc = hip_fail(e, "stream/event");
         g->stream = g->own_stream;
     }
     if (!rc) {
         hipDeviceProp_t prop;
         if (hipGetDeviceProperties(&prop, 0) == hipSuccess && prop.multiProcessorCount > 0)
-            g->grid = std::min(kMaxGrid, prop.multiProcessorCount * 4);
+            g->grid = std::min(kMaxGrid, prop.multiProcessorCount * 8);
     }
     if (!rc) {
-        hipError_t e = hipMemsetAsync(g->ctl, 0, sizeof(Ctl), g->stream);
-        if (e != hipSuccess) rc = hip_fail(e, "hipMemsetAsync");
+        Ctl c0;
+        std::memset(&c0, 0, sizeof(c0));
+        for (int o = 0; o < 2; o++) {
+            c0.top[o] = top[o];
+            c0.max_cap[o] = g->csr[o].max_cap;
+        }
+        hipError_t e = hipMemcpy(g->ctl, &c0, sizeof(Ctl), hipMemcpyHostToDevice);
+        if (e != hipSuccess) rc = hip_fail(e, "hipMemcpy");
+        g->sparse_limit = (uint32_t)std::max<int64_t>(4096, n / 64);
     }
-    if (!rc) rc = launch_fill_u8(g, g->flags, ((size_t)n + 3) / 4 * 4);
+    if (!rc) rc = launch_fill_u32(g, g->stamp, (uint64_t)n, 0);
+    if (!rc) rc = launch_fill_u32(g, g->xstamp, (uint64_t)n, 0);
     if (!rc) rc = dfpr_set_ranks(g, nullptr, 0);   // uniform 1/n
     if (!rc) {
         hipError_t e = hipStreamSynchronize(g->stream);
@@ -263,10 +293,10 @@ int dfpr_export_csr(const dfpr_graph *g, int out_orientation, int64_t *offsets, 
     if (!g || !offsets || !idx) return set_error(DFPR_E_ARG, "NULL argument");
     const Csr &c = g->csr[out_orientation ? 1 : 0];
     int32_t n = g->n;
-    std::vector<uint32_t> beg(n + 1), cnt(n);
+    std::vector<uint32_t> beg(n), cnt(n);
     std::vector<int32_t> slots(c.slots);
     DFPR_HIP(hipStreamSynchronize(g->stream));
-    DFPR_HIP(hipMemcpy(beg.data(), c.beg, (size_t)(n + 1) * 4, hipMemcpyDeviceToHost));
+    DFPR_HIP(hipMemcpy(beg.data(), c.beg, (size_t)n * 4, hipMemcpyDeviceToHost));
     DFPR_HIP(hipMemcpy(cnt.data(), c.cnt, (size_t)n * 4, hipMemcpyDeviceToHost));
     DFPR_HIP(hipMemcpy(slots.data(), c.idx, c.slots * 4, hipMemcpyDeviceToHost));
     int64_t pos = 0;

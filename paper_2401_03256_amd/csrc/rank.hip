@@ -1,35 +1,57 @@
 // Rank engines: Static, Naive-dynamic and Dynamic Frontier PageRank.
 //
 // One iteration of every engine is one launch of k_iter, which
-//   - pulls Eq. 1 for the rows in the class lists (the affected vertices of
-//     Algorithm 1, or every vertex for Static / Naive-dynamic), a row being
-//     reduced by a group of 4..64 lanes or a whole workgroup according to its
-//     in-degree class;
-//   - computes Delta r = |r - R[v]| and the block's L-inf maximum;
+//   - pulls Eq. 1 for the rows of the iteration: every vertex (Static,
+//     Naive-dynamic) or the affected vertices (Dynamic Frontier);
+//   - computes Delta r = |r - R[v]| and the L-inf maximum;
 //   - (Dynamic Frontier) marks the out-neighbours of every row whose rank
-//     moved by more than frontier_tol and appends newly marked vertices to
-//     their class lists, for the next iteration;
-//   - has its last workgroup reduce the per-workgroup partials and decide
+//     moved by more than frontier_tol;
+//   - has its last workgroup fold the per-workgroup partials and decide
 //     convergence (Delta R <= tol) or the iteration cap.
 // The host enqueues iterations in chunks and reads the stop flag between
 // chunks; launches issued after the stop flag is set return at once.
 //
+// Work layout.  Rows are split by in-degree into classes; a class-b row is
+// reduced by group_of(b) lanes of one wave (1, 2, 4, 8, 32 or 64 lanes) or,
+// above 1024 in-edges, by a whole workgroup.  Each lane loads kUnroll
+// indices and then kUnroll contributions per round, so that many loads are
+// in flight per wave.  Each lane sums its strided share of a row in order
+// and the group folds the partial sums with a fixed butterfly, so the sum
+// of a row depends on nothing but the row and its class.
+//
+// Marks.  stamp[v] holds the iteration, offset by a per-call base, from
+// which v is affected: v is processed in iteration i iff
+// base <= stamp[v] <= base + i.  Marks made in iteration i carry base+i+1,
+// so they take effect from the next iteration (synchronous form), and a
+// plain store suffices to make them.  Marks never go away within a call
+// (Algorithm 1 has no unmarking step), and a vertex whose out-neighbours
+// are all marked gains nothing from marking them again, so each vertex
+// scans its out-row at most once per call (xstamp[v] == base afterwards).
+//
+// Two ways to walk the affected rows.  While few vertices are marked, the
+// marking appends new vertices to per-class lists (sparse mode).  Once the
+// lists pass a size limit, iterations walk the whole class schedule built
+// from all vertices (sorted by id inside each class) and skip rows whose
+// stamp is out of range (dense mode); marks are then plain stores.
+//
 // Ranks are double-buffered (synchronous form, Section 4.2).  Both buffers
-// hold identical values for every vertex between calls; an iteration reads
-// one and writes only its processed rows into the other.  Because the
-// marks only grow within a call, a row that is not processed in iteration i
-// was not processed earlier either, so the two buffers still agree there.
-// The contribution C[v] = R[v] / |out(v)| is stored beside each rank so the
-// pull gathers one value per in-edge.
+// hold identical values between calls; an iteration reads one and writes
+// only its processed rows into the other.  Because marks only grow within a
+// call, a row not processed in iteration i was not processed earlier in the
+// call either, so the two buffers still agree there.  The contribution
+// C[v] = R[v] / |out(v)| is stored beside each rank so the pull gathers one
+// value per in-edge.
 #include <algorithm>
 #include <cmath>
+#include <cstring>
 #include <vector>
 
 #include "common.h"
 
 namespace dfpr {
 
-__device__ __constant__ int kRowsPerUnit[kBins] = {64, 32, 16, 8, 4, 1};
+constexpr int kUnroll = 4;
+constexpr int kSchedChunk = 4096;   // vertices per workgroup in the schedule build
 
 struct IterArgs {
     int32_t n;
@@ -39,31 +61,30 @@ struct IterArgs {
     const int32_t *out_idx;
     const double *Rc, *Cc;      // read
     double *Rn, *Cn;            // written
-    uint8_t *flags;
-    int32_t *bins;
-    uint32_t stride;            // entries per class list (= n)
+    uint32_t *stamp, *xstamp;
+    int32_t *bins;              // class lists (sparse mode), n entries each
+    const int32_t *sched;       // class schedule of all vertices
+    const uint32_t *sched_off;  // kBins + 1 offsets
     Ctl *ctl;
     double *dr_part;
-    unsigned long long *edges_part, *verts_part;
-    double base;                // (1 - alpha) / n
+    unsigned long long *cnt_part;   // kCounters per workgroup
+    double base_rank;           // (1 - alpha) / n
     double alpha, tol, ftol;
+    uint32_t sbase;             // stamp base of the call
+    uint32_t sparse_limit;
     int32_t it, max_iters;
+    int32_t n_stride;
 };
 
 __device__ inline int lane_id() { return __lane_id(); }
 
-// Set the mark of x; true if this call set it (0 -> 1).  Marks are bytes;
-// the atomic works on the aligned 32-bit word that holds the byte.
-__device__ inline bool mark_vertex(uint8_t *flags, int32_t x)
-{
-    if (flags[x]) return false;
-    uint32_t *w = reinterpret_cast<uint32_t *>(flags + (x & ~3));
-    uint32_t bit = 1u << ((x & 3) * 8);
-    uint32_t old = atomicOr(w, bit);
-    return (old & bit) == 0;
-}
+struct Acc {
+    double dr_max = 0.0;
+    unsigned long long c[kCounters] = {0, 0, 0, 0};   // rows, edges, xrows, xedges
+};
 
 // Wave-aggregated append of the lanes with `take` set to the class lists.
+// Every lane of the wave calls it.
 __device__ inline void append_to_bins(bool take, int32_t x, int cls, Ctl *ctl, int32_t *bins,
                                       uint32_t stride)
 {
@@ -71,254 +92,326 @@ __device__ inline void append_to_bins(bool take, int32_t x, int cls, Ctl *ctl, i
     const int lane = lane_id();
     const unsigned long long below = (1ull << lane) - 1ull;
     while (pend) {
-        int leader = __ffsll((long long)pend) - 1;
-        int c = __shfl(cls, leader);
-        unsigned long long mine = __ballot(take && cls == c);
+        const int leader = __ffsll((long long)pend) - 1;
+        const int c = __shfl(cls, leader);
+        const unsigned long long mine = __ballot(take && cls == c);
         uint32_t base = 0;
         if (lane == leader) base = atomicAdd(&ctl->live[c], (uint32_t)__popcll(mine));
         base = __shfl(base, leader);
-        if (take && cls == c)
-            bins[(size_t)c * stride + base + __popcll(mine & below)] = x;
+        if (take && cls == c) bins[(size_t)c * stride + base + __popcll(mine & below)] = x;
         pend &= ~mine;
     }
 }
 
-// Mark every out-neighbour of w; all lanes of the wave take part.
-__device__ inline void expand_vertex_wave(const IterArgs &a, int32_t w)
+// Mark the out-neighbours of w with stamp `sv`.  The calling lanes take
+// positions lane0, lane0 + step, ... (lane0 < step); every lane of every
+// calling wave runs the same number of rounds.
+template <bool SPARSE>
+__device__ inline void mark_out_row(const IterArgs &a, int32_t w, uint32_t lane0, uint32_t step,
+                                    uint32_t sv)
 {
     const uint32_t ob = a.out_beg[w], oc = a.out_cnt[w];
-    const int lane = lane_id();
-    for (uint32_t base = 0; base < oc; base += kWave) {
-        uint32_t k = base + lane;
-        int32_t x = k < oc ? a.out_idx[ob + k] : 0;
-        bool nw = k < oc && mark_vertex(a.flags, x);
-        int cls = nw ? bin_of(a.in_cnt[x]) : 0;
-        append_to_bins(nw, x, cls, a.ctl, a.bins, a.stride);
+    for (uint32_t k0 = 0; k0 < oc; k0 += step * kUnroll) {
+        int32_t x[kUnroll];
+#pragma unroll
+        for (int j = 0; j < kUnroll; j++) {
+            const uint32_t k = k0 + lane0 + j * step;
+            x[j] = k < oc ? a.out_idx[ob + k] : -1;
+        }
+        uint32_t st[kUnroll];
+#pragma unroll
+        for (int j = 0; j < kUnroll; j++) st[j] = x[j] >= 0 ? a.stamp[x[j]] : 0xFFFFFFFFu;
+#pragma unroll
+        for (int j = 0; j < kUnroll; j++) {
+            bool nw = false;
+            if (st[j] < a.sbase) {
+                if (SPARSE) nw = atomicMax(&a.stamp[x[j]], sv) < a.sbase;
+                else a.stamp[x[j]] = sv;
+            }
+            if (SPARSE) {
+                const int cls = nw ? bin_of(a.in_cnt[x[j]]) : 0;
+                append_to_bins(nw, x[j], cls, a.ctl, a.bins, a.n_stride);
+            }
+        }
     }
 }
 
-// Same, with the whole workgroup striding over one long out-row.
-__device__ inline void expand_vertex_block(const IterArgs &a, int32_t w)
+// Finish one row: Eq. 1, Delta r, writes; returns whether it must expand.
+template <bool DF>
+__device__ inline bool finish_row(const IterArgs &a, int32_t v, uint32_t cnt, double s, double rc,
+                                  uint32_t oc, Acc &acc)
 {
-    const uint32_t ob = a.out_beg[w], oc = a.out_cnt[w];
-    for (uint32_t base = 0; base < oc; base += kBlock) {
-        uint32_t k = base + threadIdx.x;
-        int32_t x = k < oc ? a.out_idx[ob + k] : 0;
-        bool nw = k < oc && mark_vertex(a.flags, x);
-        int cls = nw ? bin_of(a.in_cnt[x]) : 0;
-        append_to_bins(nw, x, cls, a.ctl, a.bins, a.stride);
-    }
-}
-
-struct Acc {
-    double dr_max = 0.0;
-    unsigned long long edges = 0, verts = 0;
-};
-
-// Finish one row: Eq. 1, Delta r, writes, and the expansion decision.
-template <bool EXPAND>
-__device__ inline void finish_row(const IterArgs &a, int32_t v, uint32_t cnt, double s, Acc &acc,
-                                  int32_t *q, uint32_t *qn)
-{
-    double r = a.base + a.alpha * s;
-    double dr = fabs(r - a.Rc[v]);
+    const double r = a.base_rank + a.alpha * s;
+    const double dr = fabs(r - rc);
     a.Rn[v] = r;
-    a.Cn[v] = r / (double)a.out_cnt[v];
+    a.Cn[v] = r / (double)oc;
     acc.dr_max = fmax(acc.dr_max, dr);
-    acc.edges += cnt;
-    acc.verts += 1;
-    if (EXPAND && dr > a.ftol) q[atomicAdd(qn, 1u)] = v;
+    acc.c[0] += 1;
+    acc.c[1] += cnt;
+    if (DF && dr > a.ftol && a.xstamp[v] != a.sbase) {
+        a.xstamp[v] = a.sbase;
+        acc.c[2] += 1;
+        acc.c[3] += oc;
+        return true;
+    }
+    return false;
 }
 
-// Rows first .. first + kBlock/G - 1 of a class list, G lanes per row.
-// Each lane sums its strided share of the in-row in order, then the group
-// folds the partial sums with a fixed butterfly; the order is a function of
-// the row alone, so results are reproducible.
-template <int G, bool EXPAND>
-__device__ inline void pull_group(const IterArgs &a, const int32_t *list, uint32_t count,
-                                  uint32_t first, Acc &acc, int32_t *q, uint32_t *qn)
+// One wave unit: 64/G rows of a class list, G lanes per row.
+template <int G, bool DF>
+__device__ inline void wave_unit(const IterArgs &a, const int32_t *list, uint32_t count,
+                                 uint32_t first, bool check, bool sparse, Acc &acc)
 {
-    const int sub = threadIdx.x & (G - 1);
-    const uint32_t pos = first + threadIdx.x / G;
-    double s = 0.0;
+    const int lane = lane_id();
+    const int sub = lane & (G - 1);
+    const uint32_t pos = first + lane / G;
+    bool active = false;
     int32_t v = 0;
-    uint32_t cnt = 0;
+    uint32_t beg = 0, cnt = 0, oc = 1;
+    double rc = 0.0;
     if (pos < count) {
         v = list[pos];
-        const uint32_t beg = a.in_beg[v];
+        beg = a.in_beg[v];
         cnt = a.in_cnt[v];
-        const int32_t *idx = a.in_idx + beg;
-        uint32_t k = sub;
-        for (; k + 3 * G < cnt; k += 4 * G) {
-            int32_t i0 = idx[k], i1 = idx[k + G], i2 = idx[k + 2 * G], i3 = idx[k + 3 * G];
-            double c0 = a.Cc[i0], c1 = a.Cc[i1], c2 = a.Cc[i2], c3 = a.Cc[i3];
-            s += c0;
-            s += c1;
-            s += c2;
-            s += c3;
+        if (sub == 0) {
+            rc = a.Rc[v];
+            oc = a.out_cnt[v];
         }
-        for (; k < cnt; k += G) s += a.Cc[idx[k]];
+        active = true;
+        if (DF && check) {
+            const uint32_t st = a.stamp[v];
+            active = st >= a.sbase && st <= a.sbase + (uint32_t)a.it;
+        }
+    }
+    double s = 0.0;
+    if (active) {
+        if (cnt == 1) {
+            // the self-loop is the only in-edge
+            if (sub == 0) s = a.Cc[v];
+        } else {
+            const int32_t *idx = a.in_idx + beg;
+            for (uint32_t k0 = sub; k0 < cnt; k0 += G * kUnroll) {
+                int32_t i[kUnroll];
+#pragma unroll
+                for (int j = 0; j < kUnroll; j++) {
+                    const uint32_t k = k0 + j * G;
+                    i[j] = k < cnt ? idx[k] : -1;
+                }
+                double c[kUnroll];
+#pragma unroll
+                for (int j = 0; j < kUnroll; j++) c[j] = i[j] >= 0 ? a.Cc[i[j]] : 0.0;
+#pragma unroll
+                for (int j = 0; j < kUnroll; j++)
+                    if (i[j] >= 0) s += c[j];
+            }
+        }
     }
 #pragma unroll
     for (int off = G / 2; off > 0; off >>= 1) s += __shfl_xor(s, off, G);
-    if (pos < count && sub == 0) finish_row<EXPAND>(a, v, cnt, s, acc, q, qn);
+    bool expand = false;
+    if (active && sub == 0) expand = finish_row<DF>(a, v, cnt, s, rc, oc, acc);
+    if (DF) {
+        unsigned long long q = __ballot(expand);
+        const uint32_t sv = a.sbase + (uint32_t)a.it + 1;
+        while (q) {
+            const int l = __ffsll((long long)q) - 1;
+            const int32_t w = __shfl(v, l);
+            if (sparse) mark_out_row<true>(a, w, lane, kWave, sv);
+            else mark_out_row<false>(a, w, lane, kWave, sv);
+            q &= q - 1;
+        }
+    }
 }
 
-// One heavy row, the whole workgroup.
-template <bool EXPAND>
-__device__ inline void pull_block(const IterArgs &a, int32_t v, Acc &acc, double *red, int32_t *q,
-                                  uint32_t *qn)
+// One row of more than 1024 in-edges, the whole workgroup.  All threads
+// call it with the same v.
+template <bool DF>
+__device__ inline void block_row(const IterArgs &a, int32_t v, bool check, bool sparse, Acc &acc,
+                                 double *red, int *flag)
 {
+    if (DF && check) {
+        const uint32_t st = a.stamp[v];
+        if (!(st >= a.sbase && st <= a.sbase + (uint32_t)a.it)) return;   // uniform
+    }
     const uint32_t beg = a.in_beg[v], cnt = a.in_cnt[v];
     const int32_t *idx = a.in_idx + beg;
     double s = 0.0;
-    uint32_t k = threadIdx.x;
-    for (; k + 3 * kBlock < cnt; k += 4 * kBlock) {
-        int32_t i0 = idx[k], i1 = idx[k + kBlock], i2 = idx[k + 2 * kBlock],
-                i3 = idx[k + 3 * kBlock];
-        double c0 = a.Cc[i0], c1 = a.Cc[i1], c2 = a.Cc[i2], c3 = a.Cc[i3];
-        s += c0;
-        s += c1;
-        s += c2;
-        s += c3;
+    for (uint32_t k0 = threadIdx.x; k0 < cnt; k0 += kBlock * kUnroll) {
+        int32_t i[kUnroll];
+#pragma unroll
+        for (int j = 0; j < kUnroll; j++) {
+            const uint32_t k = k0 + j * kBlock;
+            i[j] = k < cnt ? idx[k] : -1;
+        }
+        double c[kUnroll];
+#pragma unroll
+        for (int j = 0; j < kUnroll; j++) c[j] = i[j] >= 0 ? a.Cc[i[j]] : 0.0;
+#pragma unroll
+        for (int j = 0; j < kUnroll; j++)
+            if (i[j] >= 0) s += c[j];
     }
-    for (; k < cnt; k += kBlock) s += a.Cc[idx[k]];
 #pragma unroll
     for (int off = kWave / 2; off > 0; off >>= 1) s += __shfl_xor(s, off, kWave);
     if (lane_id() == 0) red[threadIdx.x / kWave] = s;
     __syncthreads();
     if (threadIdx.x == 0) {
-        double t = ((red[0] + red[1]) + red[2]) + red[3];
-        finish_row<EXPAND>(a, v, cnt, t, acc, q, qn);
+        const double t = ((red[0] + red[1]) + red[2]) + red[3];
+        *flag = finish_row<DF>(a, v, cnt, t, a.Rc[v], a.out_cnt[v], acc) ? 1 : 0;
+    }
+    __syncthreads();
+    if (DF && *flag) {
+        const uint32_t sv = a.sbase + (uint32_t)a.it + 1;
+        if (sparse) mark_out_row<true>(a, v, threadIdx.x, kBlock, sv);
+        else mark_out_row<false>(a, v, threadIdx.x, kBlock, sv);
     }
     __syncthreads();
 }
 
-template <bool EXPAND>
+// Fold a max and kCounters sums over the workgroup; thread 0 gets the
+// result.  Waves fold with shuffles, then the four wave results are
+// combined in a fixed order.
+__device__ inline void block_fold(double &dr, unsigned long long (&c)[kCounters], double *wdr,
+                                  unsigned long long (*wc)[kCounters])
+{
+#pragma unroll
+    for (int off = kWave / 2; off > 0; off >>= 1) {
+        dr = fmax(dr, __shfl_xor(dr, off, kWave));
+#pragma unroll
+        for (int j = 0; j < kCounters; j++) c[j] += __shfl_xor(c[j], off, kWave);
+    }
+    const int wave = threadIdx.x / kWave;
+    if (lane_id() == 0) {
+        wdr[wave] = dr;
+#pragma unroll
+        for (int j = 0; j < kCounters; j++) wc[wave][j] = c[j];
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int w = 1; w < kWavesPerBlock; w++) {
+            dr = fmax(dr, wdr[w]);
+#pragma unroll
+            for (int j = 0; j < kCounters; j++) c[j] += wc[w][j];
+        }
+    }
+    __syncthreads();
+}
+
+template <bool DF>
 __global__ __launch_bounds__(kBlock) void k_iter(IterArgs a)
 {
     __shared__ uint32_t s_cnt[kBins];
-    __shared__ uint32_t s_ustart[kBins + 1];   // unit prefix, classes 5,4,...,0
-    __shared__ double s_red[kBlock / kWave];
-    __shared__ int32_t s_q[kBlock];
-    __shared__ uint32_t s_qn;
+    __shared__ const int32_t *s_list[kBins];
+    __shared__ uint32_t s_ustart[kBins];   // wave-unit prefix, classes 5,4,...,0
+    __shared__ uint32_t s_nwu;
+    __shared__ double s_red[kWavesPerBlock];
+    __shared__ int s_flag;
     __shared__ int s_last;
-    __shared__ double s_fdr[kBlock];
-    __shared__ unsigned long long s_fe[kBlock], s_fv[kBlock];
+    __shared__ double s_wdr[kWavesPerBlock];
+    __shared__ unsigned long long s_wc[kWavesPerBlock][kCounters];
 
     Ctl *ctl = a.ctl;
     if (ctl->done) return;
     const int par = a.it & 1;
+    const bool sparse = DF && !ctl->dense;
+    const bool check = DF && !sparse;
     if (threadIdx.x == 0) {
-        uint32_t acc = 0;
-        s_ustart[0] = 0;
-        for (int k = 0; k < kBins; k++) {
-            int b = kBins - 1 - k;
-            uint32_t c = ctl->snap[par][b];
-            s_cnt[b] = c;
-            acc += (c + kRowsPerUnit[b] - 1) / kRowsPerUnit[b];
-            s_ustart[k + 1] = acc;
+        for (int b = 0; b < kBins; b++) {
+            if (sparse) {
+                s_cnt[b] = ctl->snap[par][b];
+                s_list[b] = a.bins + (size_t)b * a.n_stride;
+            } else {
+                s_cnt[b] = a.sched_off[b + 1] - a.sched_off[b];
+                s_list[b] = a.sched + a.sched_off[b];
+            }
         }
-        s_qn = 0;
+        uint32_t acc = 0;
+        for (int k = 0; k < kBins - 1; k++) {
+            const int b = kBins - 2 - k;
+            const uint32_t rows = kWave / group_of(b);
+            s_ustart[k] = acc;
+            acc += (s_cnt[b] + rows - 1) / rows;
+        }
+        s_nwu = acc;
     }
     __syncthreads();
-    const uint32_t total = s_ustart[kBins];
-    // workgroups past the work take no part; with no work at all, workgroup
-    // 0 alone records the (empty) iteration
-    const uint32_t active = max(1u, min((uint32_t)gridDim.x, total));
+    const uint32_t nbu = s_cnt[kBins - 1], nwu = s_nwu;
+    const uint32_t G = gridDim.x;
+    const uint32_t wblocks = (nwu + kWavesPerBlock - 1) / kWavesPerBlock;
+    // workgroups past the work take no part; with no work at all,
+    // workgroup 0 alone records the (empty) iteration
+    const uint32_t active = max(1u, max(min(G, nbu), min(G, wblocks)));
     if (blockIdx.x >= active) return;
 
     Acc acc;
-    for (uint32_t u = blockIdx.x; u < total; u += gridDim.x) {
+    for (uint32_t u = blockIdx.x; u < nbu; u += G)
+        block_row<DF>(a, s_list[kBins - 1][u], check, sparse, acc, s_red, &s_flag);
+
+    const int wave = threadIdx.x / kWave;
+    for (uint32_t u = blockIdx.x * kWavesPerBlock + wave; u < nwu; u += G * kWavesPerBlock) {
         int k = 0;
-        while (u >= s_ustart[k + 1]) k++;
-        const int b = kBins - 1 - k;
-        const uint32_t first = (u - s_ustart[k]) * kRowsPerUnit[b];
-        const int32_t *list = a.bins + (size_t)b * a.stride;
+        while (k + 1 < kBins - 1 && u >= s_ustart[k + 1]) k++;
+        const int b = kBins - 2 - k;
+        const uint32_t first = (u - s_ustart[k]) * (kWave / group_of(b));
         switch (b) {
-        case 0: pull_group<4, EXPAND>(a, list, s_cnt[0], first, acc, s_q, &s_qn); break;
-        case 1: pull_group<8, EXPAND>(a, list, s_cnt[1], first, acc, s_q, &s_qn); break;
-        case 2: pull_group<16, EXPAND>(a, list, s_cnt[2], first, acc, s_q, &s_qn); break;
-        case 3: pull_group<32, EXPAND>(a, list, s_cnt[3], first, acc, s_q, &s_qn); break;
-        case 4: pull_group<64, EXPAND>(a, list, s_cnt[4], first, acc, s_q, &s_qn); break;
-        default: pull_block<EXPAND>(a, list[first], acc, s_red, s_q, &s_qn); break;
-        }
-        if (EXPAND) {
-            __syncthreads();
-            const uint32_t nq = s_qn;
-            if (nq) {
-                const int wave = threadIdx.x / kWave;
-                for (uint32_t i = wave; i < nq; i += kBlock / kWave) {
-                    int32_t w = s_q[i];
-                    if (a.out_cnt[w] <= 4096) expand_vertex_wave(a, w);
-                }
-                for (uint32_t i = 0; i < nq; i++) {
-                    int32_t w = s_q[i];
-                    if (a.out_cnt[w] > 4096) expand_vertex_block(a, w);
-                }
-                __syncthreads();
-                if (threadIdx.x == 0) s_qn = 0;
-            }
-            __syncthreads();
+        case 0: wave_unit<1, DF>(a, s_list[0], s_cnt[0], first, check, sparse, acc); break;
+        case 1: wave_unit<2, DF>(a, s_list[1], s_cnt[1], first, check, sparse, acc); break;
+        case 2: wave_unit<4, DF>(a, s_list[2], s_cnt[2], first, check, sparse, acc); break;
+        case 3: wave_unit<8, DF>(a, s_list[3], s_cnt[3], first, check, sparse, acc); break;
+        case 4: wave_unit<32, DF>(a, s_list[4], s_cnt[4], first, check, sparse, acc); break;
+        default: wave_unit<64, DF>(a, s_list[5], s_cnt[5], first, check, sparse, acc); break;
         }
     }
 
-    // workgroup partials
-    s_fdr[threadIdx.x] = acc.dr_max;
-    s_fe[threadIdx.x] = acc.edges;
-    s_fv[threadIdx.x] = acc.verts;
-    __syncthreads();
-    for (int st = kBlock / 2; st > 0; st >>= 1) {
-        if (threadIdx.x < st) {
-            s_fdr[threadIdx.x] = fmax(s_fdr[threadIdx.x], s_fdr[threadIdx.x + st]);
-            s_fe[threadIdx.x] += s_fe[threadIdx.x + st];
-            s_fv[threadIdx.x] += s_fv[threadIdx.x + st];
-        }
-        __syncthreads();
-    }
+    double dr = acc.dr_max;
+    unsigned long long c[kCounters];
+#pragma unroll
+    for (int j = 0; j < kCounters; j++) c[j] = acc.c[j];
+    block_fold(dr, c, s_wdr, s_wc);
     if (threadIdx.x == 0) {
-        a.dr_part[blockIdx.x] = s_fdr[0];
-        a.edges_part[blockIdx.x] = s_fe[0];
-        a.verts_part[blockIdx.x] = s_fv[0];
-        uint32_t t = __hip_atomic_fetch_add(&ctl->ticket, 1u, __ATOMIC_ACQ_REL,
-                                            __HIP_MEMORY_SCOPE_AGENT);
+        a.dr_part[blockIdx.x] = dr;
+#pragma unroll
+        for (int j = 0; j < kCounters; j++) a.cnt_part[blockIdx.x * kCounters + j] = c[j];
+        const uint32_t t = __hip_atomic_fetch_add(&ctl->ticket, 1u, __ATOMIC_ACQ_REL,
+                                                  __HIP_MEMORY_SCOPE_AGENT);
         s_last = (t == active - 1);
     }
     __syncthreads();
     if (!s_last) return;
 
-    // last workgroup: reduce all partials, decide, prepare the next snapshot
+    // last workgroup: fold all partials, decide, prepare the next iteration
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-    double dr = 0.0;
-    unsigned long long e = 0, vv = 0;
+    dr = 0.0;
+#pragma unroll
+    for (int j = 0; j < kCounters; j++) c[j] = 0;
     for (uint32_t i = threadIdx.x; i < active; i += kBlock) {
         dr = fmax(dr, __hip_atomic_load(&a.dr_part[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
-        e += __hip_atomic_load(&a.edges_part[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        vv += __hip_atomic_load(&a.verts_part[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+#pragma unroll
+        for (int j = 0; j < kCounters; j++)
+            c[j] += __hip_atomic_load(&a.cnt_part[i * kCounters + j], __ATOMIC_RELAXED,
+                                      __HIP_MEMORY_SCOPE_AGENT);
     }
-    s_fdr[threadIdx.x] = dr;
-    s_fe[threadIdx.x] = e;
-    s_fv[threadIdx.x] = vv;
-    __syncthreads();
-    for (int st = kBlock / 2; st > 0; st >>= 1) {
-        if (threadIdx.x < st) {
-            s_fdr[threadIdx.x] = fmax(s_fdr[threadIdx.x], s_fdr[threadIdx.x + st]);
-            s_fe[threadIdx.x] += s_fe[threadIdx.x + st];
-            s_fv[threadIdx.x] += s_fv[threadIdx.x + st];
-        }
-        __syncthreads();
-    }
+    block_fold(dr, c, s_wdr, s_wc);
     if (threadIdx.x == 0) {
-        const double dR = s_fdr[0];
-        ctl->edges += s_fe[0];
-        ctl->verts += s_fv[0];
+        ctl->verts += c[0];
+        ctl->edges += c[1];
+        ctl->xverts += c[2];
+        ctl->xedges += c[3];
         ctl->iterations = a.it + 1;
-        ctl->final_linf = dR;
-        const bool conv = dR <= a.tol;
+        ctl->final_linf = dr;
+        const bool conv = dr <= a.tol;
         if (conv) ctl->converged = 1;
-        for (int b = 0; b < kBins; b++)
-            ctl->snap[par ^ 1][b] =
-                __hip_atomic_load(&ctl->live[b], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (sparse) {
+            unsigned long long before = 0, after = 0;
+            for (int b = 0; b < kBins; b++) {
+                const uint32_t l =
+                    __hip_atomic_load(&ctl->live[b], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                before += ctl->snap[par][b];
+                after += l;
+                ctl->snap[par ^ 1][b] = l;
+            }
+            ctl->marked += after - before;
+            if (after > a.sparse_limit) ctl->dense = 1;
+        }
         ctl->ticket = 0;
         if (conv || a.it + 1 >= a.max_iters) ctl->done = 1;
     }
@@ -338,17 +431,20 @@ __global__ void k_reset(Ctl *ctl)
         }
         ctl->ticket = 0;
         ctl->done = 0;
+        ctl->dense = 0;
         ctl->iterations = 0;
         ctl->converged = 0;
         ctl->final_linf = 0.0;
         ctl->edges = ctl->verts = 0;
+        ctl->xverts = ctl->xedges = ctl->marked = 0;
+        ctl->affected0 = ctl->affected = 0;
         ctl->err = 0;
-        ctl->affected0 = 0;
     }
 }
 
-// Freeze the lists built by the marking as iteration 0's snapshot.
-__global__ void k_snap(Ctl *ctl, int32_t max_iters)
+// Freeze the lists built by the marking as iteration 0's snapshot and pick
+// the walk of the first iteration.
+__global__ void k_snap(Ctl *ctl, int32_t max_iters, uint32_t sparse_limit, int dense)
 {
     if (threadIdx.x == 0 && blockIdx.x == 0) {
         unsigned long long tot = 0;
@@ -356,17 +452,17 @@ __global__ void k_snap(Ctl *ctl, int32_t max_iters)
             ctl->snap[0][b] = ctl->live[b];
             tot += ctl->live[b];
         }
-        ctl->affected0 = tot;
         ctl->ticket = 0;
+        ctl->dense = (dense || tot > sparse_limit) ? 1 : 0;
         ctl->done = (ctl->err || max_iters <= 0) ? 1 : 0;
     }
 }
 
-__global__ void k_fill_u8(uint8_t *p, uint64_t len)
+__global__ void k_fill_u32(uint32_t *p, uint64_t len, uint32_t value)
 {
     for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < len;
          i += (uint64_t)gridDim.x * blockDim.x)
-        p[i] = 0;
+        p[i] = value;
 }
 
 // R[b][v] = (src ? src[v] : 1/n) and C[b][v] = R[b][v] / |out(v)|, b = 0, 1.
@@ -374,8 +470,8 @@ __global__ void k_init_ranks(int32_t n, const double *src, double *R0, double *R
                              double *C1, const uint32_t *out_cnt)
 {
     for (int32_t v = blockIdx.x * blockDim.x + threadIdx.x; v < n; v += gridDim.x * blockDim.x) {
-        double r = src ? src[v] : 1.0 / (double)n;
-        double c = r / (double)out_cnt[v];
+        const double r = src ? src[v] : 1.0 / (double)n;
+        const double c = r / (double)out_cnt[v];
         R0[v] = r;
         R1[v] = r;
         C0[v] = c;
@@ -391,24 +487,108 @@ __global__ void k_copy2(int32_t n, const double *a, double *a2, const double *b,
     }
 }
 
-// Every vertex into its class list (Static and Naive-dynamic).
-__global__ void k_mark_all(int32_t n, const uint32_t *in_cnt, Ctl *ctl, int32_t *bins,
-                           uint32_t stride)
+// Class schedule of all vertices: a stable counting sort by class, in three
+// passes (per-workgroup class counts, one scan, scatter).  Thread t of
+// workgroup w owns the kSchedChunk/kBlock consecutive vertices starting at
+// w * kSchedChunk + t * (kSchedChunk / kBlock).
+__device__ inline void sched_thread_counts(int32_t n, const uint32_t *in_cnt, uint32_t v0,
+                                           uint32_t (&cnt)[kBins])
 {
-    int32_t v = blockIdx.x * blockDim.x + threadIdx.x;
-    bool take = v < n;
-    int cls = take ? bin_of(in_cnt[v]) : 0;
-    append_to_bins(take, v, cls, ctl, bins, stride);
+#pragma unroll
+    for (int b = 0; b < kBins; b++) cnt[b] = 0;
+    for (int j = 0; j < kSchedChunk / kBlock; j++) {
+        const uint32_t v = v0 + j;
+        if (v < (uint32_t)n) cnt[bin_of(in_cnt[v])]++;
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_sched_count(int32_t n, const uint32_t *in_cnt,
+                                                        uint32_t *tmp, uint32_t nblocks)
+{
+    __shared__ uint32_t s[kBins][kBlock];
+    uint32_t cnt[kBins];
+    sched_thread_counts(n, in_cnt, blockIdx.x * kSchedChunk + threadIdx.x * (kSchedChunk / kBlock),
+                        cnt);
+#pragma unroll
+    for (int b = 0; b < kBins; b++) s[b][threadIdx.x] = cnt[b];
+    __syncthreads();
+    if (threadIdx.x < kBins) {
+        uint32_t t = 0;
+        for (int i = 0; i < kBlock; i++) t += s[threadIdx.x][i];
+        tmp[threadIdx.x * nblocks + blockIdx.x] = t;
+    }
+}
+
+// Exclusive scan of the class-major count table; off[b] = start of class b.
+__global__ __launch_bounds__(kBlock) void k_sched_scan(uint32_t *tmp, uint32_t nblocks,
+                                                       uint32_t *off)
+{
+    __shared__ uint32_t s[kBlock];
+    const uint32_t len = nblocks * kBins;
+    uint32_t carry = 0;
+    for (uint32_t b0 = 0; b0 < len; b0 += kBlock) {
+        const uint32_t i = b0 + threadIdx.x;
+        const uint32_t v = i < len ? tmp[i] : 0;
+        s[threadIdx.x] = v;
+        __syncthreads();
+        for (int o = 1; o < kBlock; o <<= 1) {
+            const uint32_t t = threadIdx.x >= (uint32_t)o ? s[threadIdx.x - o] : 0;
+            __syncthreads();
+            s[threadIdx.x] += t;
+            __syncthreads();
+        }
+        if (i < len) {
+            const uint32_t ex = carry + s[threadIdx.x] - v;
+            tmp[i] = ex;
+            if (i % nblocks == 0) off[i / nblocks] = ex;
+        }
+        const uint32_t tot = s[kBlock - 1];
+        __syncthreads();
+        carry += tot;
+    }
+    if (threadIdx.x == 0) off[kBins] = carry;
+}
+
+__global__ __launch_bounds__(kBlock) void k_sched_scatter(int32_t n, const uint32_t *in_cnt,
+                                                          const uint32_t *tmp, uint32_t nblocks,
+                                                          int32_t *sched)
+{
+    __shared__ uint32_t s[kBins][kBlock];
+    const uint32_t v0 = blockIdx.x * kSchedChunk + threadIdx.x * (kSchedChunk / kBlock);
+    uint32_t cnt[kBins];
+    sched_thread_counts(n, in_cnt, v0, cnt);
+#pragma unroll
+    for (int b = 0; b < kBins; b++) s[b][threadIdx.x] = cnt[b];
+    __syncthreads();
+    // inclusive scan per class over the threads of the workgroup
+    for (int o = 1; o < kBlock; o <<= 1) {
+        uint32_t t[kBins];
+#pragma unroll
+        for (int b = 0; b < kBins; b++)
+            t[b] = threadIdx.x >= (uint32_t)o ? s[b][threadIdx.x - o] : 0;
+        __syncthreads();
+#pragma unroll
+        for (int b = 0; b < kBins; b++) s[b][threadIdx.x] += t[b];
+        __syncthreads();
+    }
+    uint32_t pos[kBins];
+#pragma unroll
+    for (int b = 0; b < kBins; b++)
+        pos[b] = tmp[b * nblocks + blockIdx.x] + s[b][threadIdx.x] - cnt[b];
+    for (int j = 0; j < kSchedChunk / kBlock; j++) {
+        const uint32_t v = v0 + j;
+        if (v < (uint32_t)n) sched[pos[bin_of(in_cnt[v])]++] = (int32_t)v;
+    }
 }
 
 // Flag (and abort the loop) if a batch id lies outside [0, n).
 __global__ void k_validate(int32_t n, int64_t nd, const int32_t *ds, const int32_t *dd,
                            int64_t ni, const int32_t *is, const int32_t *id, Ctl *ctl)
 {
-    int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (i >= nd + ni) return;
-    int32_t s = i < nd ? ds[i] : is[i - nd];
-    int32_t d = i < nd ? dd[i] : id[i - nd];
+    const int32_t s = i < nd ? ds[i] : is[i - nd];
+    const int32_t d = i < nd ? dd[i] : id[i - nd];
     if (s < 0 || s >= n || d < 0 || d >= n) {
         atomicOr(&ctl->err, 1u);
         ctl->done = 1;
@@ -417,66 +597,81 @@ __global__ void k_validate(int32_t n, int64_t nd, const int32_t *ds, const int32
 
 // Initial marking (Section 4.1.1, Algorithm 1): one wave per batch edge
 // (u, v) marks G^t.out(u), and for a deletion also v, which was in
-// G^{t-1}.out(u).  The union is (G^{t-1} U G^t).out(u).
-__global__ __launch_bounds__(kBlock) void k_mark_initial(int32_t n, int64_t nd, const int32_t *ds,
+// G^{t-1}.out(u); the union is (G^{t-1} U G^t).out(u).  The marks carry
+// stamp base, i.e. they are processed from iteration 0.  u's out-row is now
+// fully marked, so u never needs to scan it again in this call.  With
+// `append`, newly marked vertices also go to the class lists.
+__global__ __launch_bounds__(kBlock) void k_mark_initial(IterArgs a, int64_t nd, const int32_t *ds,
                                                          const int32_t *dd, int64_t ni,
-                                                         const int32_t *is, const uint32_t *out_beg,
-                                                         const uint32_t *out_cnt,
-                                                         const int32_t *out_idx,
-                                                         const uint32_t *in_cnt, uint8_t *flags,
-                                                         Ctl *ctl, int32_t *bins, uint32_t stride)
+                                                         const int32_t *is, int append)
 {
-    if (ctl->err) return;
-    const int64_t w = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) / kWave;
-    if (w >= nd + ni) return;
+    __shared__ unsigned long long s_new;
+    if (a.ctl->err) return;
+    if (threadIdx.x == 0) s_new = 0;
+    __syncthreads();
     const int lane = lane_id();
-    const int32_t u = w < nd ? ds[w] : is[w - nd];
-    const uint32_t ob = out_beg[u], oc = out_cnt[u];
-    for (uint32_t base = 0; base < oc; base += kWave) {
-        uint32_t k = base + lane;
-        int32_t x = k < oc ? out_idx[ob + k] : 0;
-        bool nw = k < oc && mark_vertex(flags, x);
-        int cls = nw ? bin_of(in_cnt[x]) : 0;
-        append_to_bins(nw, x, cls, ctl, bins, stride);
+    const int64_t waves = (int64_t)gridDim.x * kWavesPerBlock;
+    unsigned long long mine = 0;
+    for (int64_t w = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) / kWave; w < nd + ni;
+         w += waves) {
+        const int32_t u = w < nd ? ds[w] : is[w - nd];
+        const uint32_t ob = a.out_beg[u], oc = a.out_cnt[u];
+        const uint32_t len = oc + (w < nd ? 1u : 0u);
+        for (uint32_t kb = 0; kb < len; kb += kWave) {
+            const uint32_t k = kb + lane;
+            int32_t x = -1;
+            if (k < oc) x = a.out_idx[ob + k];
+            else if (k < len) x = dd[w];
+            bool nw = false;
+            if (x >= 0 && a.stamp[x] < a.sbase) nw = atomicMax(&a.stamp[x], a.sbase) < a.sbase;
+            const unsigned long long m = __ballot(nw);
+            if (lane == 0) mine += __popcll(m);
+            if (append) {
+                const int cls = nw ? bin_of(a.in_cnt[x]) : 0;
+                append_to_bins(nw, x, cls, a.ctl, a.bins, a.n_stride);
+            }
+        }
+        if (lane == 0) a.xstamp[u] = a.sbase;
     }
-    if (w < nd) {
-        int32_t x = dd[w];
-        bool nw = lane == 0 && mark_vertex(flags, x);
-        int cls = nw ? bin_of(in_cnt[x]) : 0;
-        append_to_bins(nw, x, cls, ctl, bins, stride);
-    }
+    if (lane == 0 && mine) atomicAdd(&s_new, mine);
+    __syncthreads();
+    if (threadIdx.x == 0 && s_new) atomicAdd(&a.ctl->affected0, s_new);
 }
 
-// End of a Dynamic Frontier call: copy the processed rows of the result
-// buffer into the other buffer and clear their marks.
-__global__ void k_finish_listed(const Ctl *ctl, const int32_t *bins, uint32_t stride,
-                                const double *Rres, double *Roth, const double *Cres, double *Coth,
-                                uint8_t *flags, int copy_ranks)
+// End of a Dynamic Frontier call: copy the rows processed in this call from
+// the result buffer into the other buffer and count the marked vertices.
+__global__ __launch_bounds__(kBlock) void k_finish(int32_t n, const uint32_t *stamp, uint32_t lo,
+                                                   uint32_t hi, const double *Rres, double *Roth,
+                                                   const double *Cres, double *Coth, Ctl *ctl)
 {
-    for (int b = 0; b < kBins; b++) {
-        const uint32_t cnt = ctl->live[b];
-        const int32_t *list = bins + (size_t)b * stride;
-        for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < cnt;
-             i += gridDim.x * blockDim.x) {
-            int32_t v = list[i];
-            if (copy_ranks) {
-                Roth[v] = Rres[v];
-                Coth[v] = Cres[v];
-            }
-            flags[v] = 0;
+    __shared__ unsigned long long s_cnt;
+    if (threadIdx.x == 0) s_cnt = 0;
+    __syncthreads();
+    unsigned long long mine = 0;
+    for (int32_t v = blockIdx.x * blockDim.x + threadIdx.x; v < n; v += gridDim.x * blockDim.x) {
+        const uint32_t st = stamp[v];
+        if (st >= lo && st <= hi) {
+            mine++;
+            Roth[v] = Rres[v];
+            Coth[v] = Cres[v];
         }
     }
+    for (int off = kWave / 2; off > 0; off >>= 1) mine += __shfl_xor(mine, off, kWave);
+    if (lane_id() == 0 && mine) atomicAdd(&s_cnt, mine);
+    __syncthreads();
+    if (threadIdx.x == 0 && s_cnt) atomicAdd(&ctl->affected, s_cnt);
 }
 
 static inline int blocks_for(int64_t items, int per_block = kBlock)
 {
-    int64_t b = (items + per_block - 1) / per_block;
+    const int64_t b = (items + per_block - 1) / per_block;
     return (int)std::max<int64_t>(1, std::min<int64_t>(b, 65535 * 16));
 }
 
-int launch_fill_u8(dfpr_graph *g, uint8_t *p, uint64_t len)
+int launch_fill_u32(dfpr_graph *g, uint32_t *p, uint64_t len, uint32_t value)
 {
-    k_fill_u8<<<std::min<int>(blocks_for(len), 4096), kBlock, 0, g->stream>>>(p, len);
+    k_fill_u32<<<std::min<int>(blocks_for((int64_t)len), 4096), kBlock, 0, g->stream>>>(p, len,
+                                                                                       value);
     DFPR_HIP(hipGetLastError());
     return DFPR_OK;
 }
@@ -488,7 +683,10 @@ int launch_fill_u8(dfpr_graph *g, uint8_t *p, uint64_t len)
 struct BusyGuard {
     dfpr_graph *g;
     bool ok;
-    explicit BusyGuard(dfpr_graph *g_) : g(g_) { ok = __atomic_exchange_n(&g->busy, 1, __ATOMIC_ACQ_REL) == 0; }
+    explicit BusyGuard(dfpr_graph *g_) : g(g_)
+    {
+        ok = __atomic_exchange_n(&g->busy, 1, __ATOMIC_ACQ_REL) == 0;
+    }
     ~BusyGuard()
     {
         if (ok) __atomic_store_n(&g->busy, 0, __ATOMIC_RELEASE);
@@ -500,13 +698,13 @@ static int check_params(const dfpr_params *p, dfpr_params &out)
     if (p) out = *p;
     else dfpr_params_default(&out);
     if (!(out.alpha >= 0.0 && out.alpha < 1.0) || !(out.tol >= 0.0) ||
-        !(out.frontier_tol >= 0.0) || out.max_iters < 0 ||
+        !(out.frontier_tol >= 0.0) || out.max_iters < 0 || out.max_iters > 100000 ||
         (out.precision != DFPR_FP64 && out.precision != DFPR_FP32_KAHAN))
         return set_error(DFPR_E_ARG, "invalid parameters");
     return DFPR_OK;
 }
 
-static IterArgs iter_args(dfpr_graph *g, const dfpr_params &p)
+static IterArgs iter_args(dfpr_graph *g, const dfpr_params &p, uint32_t sbase)
 {
     IterArgs a{};
     a.n = g->n;
@@ -516,31 +714,70 @@ static IterArgs iter_args(dfpr_graph *g, const dfpr_params &p)
     a.out_beg = g->csr[1].beg;
     a.out_cnt = g->csr[1].cnt;
     a.out_idx = g->csr[1].idx;
-    a.flags = g->flags;
+    a.stamp = g->stamp;
+    a.xstamp = g->xstamp;
     a.bins = g->bins;
-    a.stride = (uint32_t)g->n;
+    a.sched = g->sched;
+    a.sched_off = g->sched_off;
     a.ctl = g->ctl;
     a.dr_part = g->it.dr_part;
-    a.edges_part = g->it.edges_part;
-    a.verts_part = g->it.verts_part;
-    a.base = (1.0 - p.alpha) / (double)g->n;
+    a.cnt_part = g->it.cnt_part;
+    a.base_rank = (1.0 - p.alpha) / (double)g->n;
     a.alpha = p.alpha;
     a.tol = p.tol;
     a.ftol = p.frontier_tol;
+    a.sbase = sbase;
+    a.sparse_limit = g->sparse_limit;
     a.max_iters = p.max_iters;
+    a.n_stride = g->n;
     return a;
+}
+
+// Rebuild the class schedule if in-degrees changed since the last build.
+static int ensure_schedule(dfpr_graph *g)
+{
+    if (!g->sched_dirty) return DFPR_OK;
+    const uint32_t nb = (uint32_t)((g->n + kSchedChunk - 1) / kSchedChunk);
+    hipStream_t s = g->stream;
+    k_sched_count<<<nb, kBlock, 0, s>>>(g->n, g->csr[0].cnt, g->sched_tmp, nb);
+    k_sched_scan<<<1, kBlock, 0, s>>>(g->sched_tmp, nb, g->sched_off);
+    k_sched_scatter<<<nb, kBlock, 0, s>>>(g->n, g->csr[0].cnt, g->sched_tmp, nb, g->sched);
+    DFPR_HIP(hipGetLastError());
+    g->sched_dirty = 0;
+    return DFPR_OK;
+}
+
+// Take a stamp base for a new call; stamps of earlier calls are all below it.
+static int take_base(dfpr_graph *g, int32_t max_iters, uint32_t *base)
+{
+    const uint64_t span = (uint64_t)max_iters + 2;
+    if ((uint64_t)g->next_base + span >= 0xF0000000ull) {
+        int rc = launch_fill_u32(g, g->stamp, (uint64_t)g->n, 0);
+        if (!rc) rc = launch_fill_u32(g, g->xstamp, (uint64_t)g->n, 0);
+        if (rc) return rc;
+        g->next_base = 1;
+    }
+    *base = g->next_base;
+    g->next_base += (uint32_t)span;
+    return DFPR_OK;
 }
 
 // Run iterations until the device sets the stop flag.  Iteration i reads
 // buffer (base ^ (i & 1)); returns the buffer holding the result.
-static int run_loop(dfpr_graph *g, const dfpr_params &p, bool expand, int *res_buf)
+// Iterations are enqueued in chunks; between chunks the host reads the
+// control block once and sizes the next chunk from the observed geometric
+// decay of Delta R, so few launches run after convergence.
+static int run_loop(dfpr_graph *g, const dfpr_params &p, bool df, uint32_t sbase, int *res_buf)
 {
-    IterArgs a = iter_args(g, p);
+    IterArgs a = iter_args(g, p, sbase);
     const int base = g->cur;
     int it = 0, chunk = 4;
+    double prev_dr = -1.0;
+    int prev_it = 0;
     *res_buf = base;
     while (it < p.max_iters) {
         const int k = std::min(chunk, p.max_iters - it);
+        if (g->prof.enabled) DFPR_HIP(hipEventRecord(g->evk0, g->stream));
         for (int j = 0; j < k; j++) {
             const int i = it + j;
             const int src = base ^ (i & 1);
@@ -549,23 +786,54 @@ static int run_loop(dfpr_graph *g, const dfpr_params &p, bool expand, int *res_b
             a.Rn = g->R[src ^ 1];
             a.Cn = g->C[src ^ 1];
             a.it = i;
-            if (expand)
-                k_iter<true><<<g->grid, kBlock, 0, g->stream>>>(a);
-            else
-                k_iter<false><<<g->grid, kBlock, 0, g->stream>>>(a);
+            if (df) k_iter<true><<<g->grid, kBlock, 0, g->stream>>>(a);
+            else k_iter<false><<<g->grid, kBlock, 0, g->stream>>>(a);
         }
         DFPR_HIP(hipGetLastError());
+        if (g->prof.enabled) DFPR_HIP(hipEventRecord(g->evk1, g->stream));
         DFPR_HIP(hipMemcpyAsync(g->ctl_host, g->ctl, sizeof(Ctl), hipMemcpyDeviceToHost, g->stream));
         DFPR_HIP(hipStreamSynchronize(g->stream));
+        if (g->prof.enabled) {
+            float ms = 0.f;
+            DFPR_HIP(hipEventElapsedTime(&ms, g->evk0, g->evk1));
+            g->prof.ms += ms;
+            g->prof.launches += k;
+        }
         if (g->ctl_host->done) break;
         it += k;
-        chunk = std::min(chunk * 2, 32);
+        const double dr = g->ctl_host->final_linf;
+        const int its = g->ctl_host->iterations;
+        int next = std::min(chunk * 2, 32);
+        if (prev_dr > 0.0 && dr > 0.0 && dr < prev_dr && its > prev_it && p.tol > 0.0) {
+            const double rate = std::pow(dr / prev_dr, 1.0 / (its - prev_it));
+            const double need = std::ceil(std::log(p.tol / dr) / std::log(rate));
+            if (std::isfinite(need)) next = (int)std::min(64.0, std::max(1.0, need));
+        }
+        prev_dr = dr;
+        prev_it = its;
+        chunk = next;
     }
     if (p.max_iters == 0) {
         DFPR_HIP(hipMemcpyAsync(g->ctl_host, g->ctl, sizeof(Ctl), hipMemcpyDeviceToHost, g->stream));
         DFPR_HIP(hipStreamSynchronize(g->stream));
     }
     *res_buf = base ^ (g->ctl_host->iterations & 1);
+    if (g->prof.enabled) {
+        const Ctl &c = *g->ctl_host;
+        g->prof.rows += (int64_t)c.verts;
+        g->prof.edges += (int64_t)c.edges;
+        g->prof.exp_rows += (int64_t)c.xverts;
+        g->prof.exp_edges += (int64_t)c.xedges;
+        g->prof.marked += (int64_t)c.marked;
+        // per processed row: schedule entry 4 B, row start and length 8 B,
+        // R[v] 8 B, |out(v)| 4 B, R'[v] and C'[v] written 16 B (+ its mark
+        // 4 B and expansion stamp 4 B in Dynamic Frontier); per in-edge:
+        // index 4 B and gathered contribution 8 B; per expanding row:
+        // out-row start and length 8 B; per scanned out-edge: index 4 B and
+        // the target's mark 4 B
+        const double row_bytes = df ? 48.0 : 40.0;
+        g->prof.bytes += row_bytes * c.verts + 12.0 * c.edges + 8.0 * c.xverts + 8.0 * c.xedges;
+    }
     return DFPR_OK;
 }
 
@@ -581,16 +849,14 @@ static void fill_stats(dfpr_graph *g, dfpr_stats *st, bool df)
     float ms = 0.f;
     (void)hipEventElapsedTime(&ms, g->ev0, g->ev1);
     st->ms_device = ms;
-    unsigned long long fin = 0;
-    for (int b = 0; b < kBins; b++) fin += c.live[b];
     st->affected_initial = df ? (int64_t)c.affected0 : g->n;
-    st->affected_final = df ? (int64_t)fin : g->n;
+    st->affected_final = df ? (int64_t)c.affected : g->n;
     st->vertices_processed = (int64_t)c.verts;
     st->edges_processed = (int64_t)c.edges;
 }
 
-// Static (prev == NULL, uniform start) or Naive-dynamic (start from prev,
-// which may be the resident ranks).
+// Static (prev == NULL and !use_resident: uniform start) or Naive-dynamic
+// (start from prev, or from the resident ranks).
 static int full_sweeps(dfpr_graph *g, const dfpr_params *pp, const double *prev, int prev_dev,
                        bool use_resident, double *ranks_out, int out_dev, dfpr_stats *st)
 {
@@ -612,12 +878,13 @@ static int full_sweeps(dfpr_graph *g, const dfpr_params *pp, const double *prev,
         k_init_ranks<<<blocks_for(n), kBlock, 0, s>>>(n, nullptr, g->R[0], g->R[1], g->C[0],
                                                       g->C[1], g->csr[1].cnt);
     }
+    rc = ensure_schedule(g);
+    if (rc) return rc;
     k_reset<<<1, 1, 0, s>>>(g->ctl);
-    k_mark_all<<<blocks_for(n), kBlock, 0, s>>>(n, g->csr[0].cnt, g->ctl, g->bins, (uint32_t)n);
-    k_snap<<<1, 1, 0, s>>>(g->ctl, p.max_iters);
+    k_snap<<<1, 1, 0, s>>>(g->ctl, p.max_iters, g->sparse_limit, 1);
     DFPR_HIP(hipGetLastError());
     int res = cur;
-    rc = run_loop(g, p, false, &res);
+    rc = run_loop(g, p, false, 0, &res);
     if (rc) return rc;
     k_copy2<<<blocks_for(n), kBlock, 0, s>>>(n, g->R[res], g->R[res ^ 1], g->C[res],
                                              g->C[res ^ 1]);
@@ -662,29 +929,33 @@ static int df_impl(dfpr_graph *g, const dfpr_params *pp, int64_t nd, const int32
         k_init_ranks<<<blocks_for(n), kBlock, 0, s>>>(n, g->R[cur], g->R[0], g->R[1], g->C[0],
                                                       g->C[1], g->csr[1].cnt);
     }
+    rc = ensure_schedule(g);
+    uint32_t sbase = 0;
+    if (!rc) rc = take_base(g, p.max_iters, &sbase);
+    if (rc) return rc;
+    // a batch whose sources reach many vertices starts on the full schedule
+    const double reach = (double)(nd + ni) * ((double)g->m / (double)n);
+    const int dense = reach > (double)g->sparse_limit ? 1 : 0;
+    IterArgs a = iter_args(g, p, sbase);
     k_reset<<<1, 1, 0, s>>>(g->ctl);
     if (nd + ni > 0) {
         k_validate<<<blocks_for(nd + ni), kBlock, 0, s>>>(n, nd, bds, bdd, ni, bis, bid, g->ctl);
-        k_mark_initial<<<blocks_for((nd + ni) * kWave), kBlock, 0, s>>>(
-            n, nd, bds, bdd, ni, bis, g->csr[1].beg, g->csr[1].cnt, g->csr[1].idx, g->csr[0].cnt,
-            g->flags, g->ctl, g->bins, (uint32_t)n);
+        k_mark_initial<<<std::min(blocks_for((nd + ni) * kWave), 2048), kBlock, 0, s>>>(
+            a, nd, bds, bdd, ni, bis, dense ? 0 : 1);
     }
-    k_snap<<<1, 1, 0, s>>>(g->ctl, p.max_iters);
+    k_snap<<<1, 1, 0, s>>>(g->ctl, p.max_iters, g->sparse_limit, dense);
     DFPR_HIP(hipGetLastError());
     int res = cur;
-    rc = run_loop(g, p, true, &res);
+    rc = run_loop(g, p, true, sbase, &res);
     if (rc) return rc;
-    if (g->ctl_host->err) {
-        // nothing was marked or iterated; clear marks made before the check
-        k_finish_listed<<<256, kBlock, 0, s>>>(g->ctl, g->bins, (uint32_t)n, nullptr, nullptr,
-                                               nullptr, nullptr, g->flags, 0);
-        DFPR_HIP(hipStreamSynchronize(s));
-        return set_error(DFPR_E_RANGE, "vertex id outside [0, n) in the batch");
-    }
-    k_finish_listed<<<std::min(blocks_for(n), 2048), kBlock, 0, s>>>(
-        g->ctl, g->bins, (uint32_t)n, g->R[res], g->R[res ^ 1], g->C[res], g->C[res ^ 1],
-        g->flags, 1);
+    const int32_t iters = g->ctl_host->iterations;
+    if (g->ctl_host->err) return set_error(DFPR_E_RANGE, "vertex id outside [0, n) in the batch");
+    k_finish<<<std::min(blocks_for(n), 2048), kBlock, 0, s>>>(
+        n, g->stamp, sbase, sbase + (uint32_t)iters, g->R[res], g->R[res ^ 1], g->C[res],
+        g->C[res ^ 1], g->ctl);
     g->cur = res;
+    g->last_base = sbase;
+    g->last_iters = iters;
     DFPR_HIP(hipEventRecord(g->ev1, s));
     if (ranks_out)
         DFPR_HIP(hipMemcpyAsync(ranks_out, g->R[res], (size_t)n * 8,
@@ -766,35 +1037,56 @@ int dfpr_mark_affected(dfpr_graph *g, int64_t n_del, const int32_t *del_src,
     hipStream_t s = g->stream;
     const int32_t *bds, *bdd, *bis, *bid;
     rc = stage_batch(g, n_del, del_src, del_dst, n_ins, ins_src, ins_dst, &bds, &bdd, &bis, &bid);
+    dfpr_params p;
+    dfpr_params_default(&p);
+    uint32_t sbase = 0;
+    if (!rc) rc = take_base(g, 0, &sbase);
     if (rc) return rc;
+    IterArgs a = iter_args(g, p, sbase);
     k_reset<<<1, 1, 0, s>>>(g->ctl);
     if (n_del + n_ins > 0)
-        k_mark_initial<<<blocks_for((n_del + n_ins) * kWave), kBlock, 0, s>>>(
-            n, n_del, bds, bdd, n_ins, bis, g->csr[1].beg, g->csr[1].cnt, g->csr[1].idx,
-            g->csr[0].cnt, g->flags, g->ctl, g->bins, (uint32_t)n);
+        k_mark_initial<<<std::min(blocks_for((n_del + n_ins) * kWave), 2048), kBlock, 0, s>>>(
+            a, n_del, bds, bdd, n_ins, bis, 0);
     DFPR_HIP(hipGetLastError());
-    DFPR_HIP(hipMemcpyAsync(flags_out, g->flags, (size_t)n, hipMemcpyDeviceToHost, s));
-    k_finish_listed<<<std::min(blocks_for(n), 2048), kBlock, 0, s>>>(
-        g->ctl, g->bins, (uint32_t)n, nullptr, nullptr, nullptr, nullptr, g->flags, 0);
+    std::vector<uint32_t> st(n);
+    DFPR_HIP(hipMemcpyAsync(st.data(), g->stamp, (size_t)n * 4, hipMemcpyDeviceToHost, s));
     DFPR_HIP(hipStreamSynchronize(s));
+    for (int32_t v = 0; v < n; v++) flags_out[v] = st[v] == sbase ? 1 : 0;
     return DFPR_OK;
 }
 
 int dfpr_get_affected(const dfpr_graph *g, uint8_t *flags_out)
 {
     if (!g || !flags_out) return set_error(DFPR_E_ARG, "NULL argument");
+    const int32_t n = g->n;
+    std::vector<uint32_t> st(n);
     DFPR_HIP(hipStreamSynchronize(g->stream));
-    Ctl c;
-    DFPR_HIP(hipMemcpy(&c, g->ctl, sizeof(Ctl), hipMemcpyDeviceToHost));
-    std::fill(flags_out, flags_out + g->n, 0);
-    std::vector<int32_t> list;
-    for (int b = 0; b < kBins; b++) {
-        list.resize(c.live[b]);
-        if (c.live[b])
-            DFPR_HIP(hipMemcpy(list.data(), g->bins + (size_t)b * g->n, (size_t)c.live[b] * 4,
-                               hipMemcpyDeviceToHost));
-        for (int32_t v : list) flags_out[v] = 1;
-    }
+    DFPR_HIP(hipMemcpy(st.data(), g->stamp, (size_t)n * 4, hipMemcpyDeviceToHost));
+    const uint32_t lo = g->last_base, hi = g->last_base + (uint32_t)std::max(g->last_iters, 0);
+    for (int32_t v = 0; v < n; v++)
+        flags_out[v] = (g->last_iters >= 0 && st[v] >= lo && st[v] <= hi) ? 1 : 0;
+    return DFPR_OK;
+}
+
+int dfpr_profile_reset(dfpr_graph *g, int enable)
+{
+    if (!g) return set_error(DFPR_E_ARG, "graph is NULL");
+    g->prof = Profile{};
+    g->prof.enabled = enable ? 1 : 0;
+    return DFPR_OK;
+}
+
+int dfpr_profile_read(const dfpr_graph *g, dfpr_profile *out)
+{
+    if (!g || !out) return set_error(DFPR_E_ARG, "NULL argument");
+    out->launches = g->prof.launches;
+    out->ms = g->prof.ms;
+    out->bytes = g->prof.bytes;
+    out->rows = g->prof.rows;
+    out->edges = g->prof.edges;
+    out->expanded_rows = g->prof.exp_rows;
+    out->expanded_edges = g->prof.exp_edges;
+    out->marked = g->prof.marked;
     return DFPR_OK;
 }
 

@@ -33,7 +33,7 @@ EXPORTED = [
     "dfpr_pagerank_static", "dfpr_pagerank_naive_dynamic",
     "dfpr_pagerank_dynamic_frontier", "dfpr_pagerank_dynamic_frontier_device",
     "dfpr_mark_affected", "dfpr_get_affected", "dfpr_get_ranks", "dfpr_set_ranks",
-    "dfpr_export_csr", "dfpr_last_error",
+    "dfpr_export_csr", "dfpr_last_error", "dfpr_profile_reset", "dfpr_profile_read",
 ]
 
 
@@ -55,6 +55,16 @@ class _Stats(ctypes.Structure):
                 ("final_linf", ctypes.c_double), ("ms_device", ctypes.c_double),
                 ("affected_initial", ctypes.c_int64), ("affected_final", ctypes.c_int64),
                 ("vertices_processed", ctypes.c_int64), ("edges_processed", ctypes.c_int64)]
+
+
+class Profile(ctypes.Structure):
+    _fields_ = [("launches", ctypes.c_int64), ("ms", ctypes.c_double), ("bytes", ctypes.c_double),
+                ("rows", ctypes.c_int64), ("edges", ctypes.c_int64),
+                ("expanded_rows", ctypes.c_int64), ("expanded_edges", ctypes.c_int64),
+                ("marked", ctypes.c_int64)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
 
 
 @dataclass
@@ -113,6 +123,8 @@ def lib():
     L.dfpr_get_ranks.argtypes = [_P, _P, ctypes.c_int]
     L.dfpr_set_ranks.argtypes = [_P, _P, ctypes.c_int]
     L.dfpr_export_csr.argtypes = [_P, ctypes.c_int, _P, _P]
+    L.dfpr_profile_reset.argtypes = [_P, ctypes.c_int]
+    L.dfpr_profile_read.argtypes = [_P, _P]
     L.dfpr_last_error.argtypes = []
     L.dfpr_last_error.restype = ctypes.c_char_p
     _lib = L
@@ -278,6 +290,14 @@ class Graph:
     def set_ranks(self, R=None):
         R = None if R is None else np.ascontiguousarray(R, np.float64)
         _check(lib().dfpr_set_ranks(self._h, _hp(R), 0))
+
+    def profile_reset(self, enable=True):
+        _check(lib().dfpr_profile_reset(self._h, 1 if enable else 0))
+
+    def profile(self) -> Profile:
+        pr = Profile()
+        _check(lib().dfpr_profile_read(self._h, ctypes.byref(pr)))
+        return pr
 
     def csr(self, out: bool):
         off = np.zeros(self.n + 1, np.int64)
