@@ -107,11 +107,13 @@ def main():
 
     total = args.warmup + args.steps
     counts = [synth.batch_counts(fracs[i % len(fracs)], m) for i in range(total)]
+    counts += [synth.batch_counts(f, m) for f in fracs]   # comparator batches
     seq = synth.batch_sequence(src, dst, n, counts, seed=2)
     dev = [[torch.from_numpy(np.ascontiguousarray(x)).cuda()
             for x in (b.del_src, b.del_dst, b.ins_src, b.ins_dst)] for b in seq]
     torch.cuda.synchronize()
     p = dfpr.params(frontier_tol=args.frontier_tol)
+    p32 = dfpr.params(frontier_tol=args.frontier_tol, precision=dfpr.FP32_KAHAN)
 
     t = time.time()
     R0, st0 = g.static(p)
@@ -150,24 +152,42 @@ def main():
     value = edges / elapsed / 1e9
     log(f"timed: {args.steps} steps in {elapsed * 1e3:.1f} ms, {value:.2f} GTEPS")
 
-    # comparators on the final graph (not timed): Static and Naive-dynamic
-    Rn, stn = g.naive_dynamic(p=p)
-    _, sts = g.static(p)
-    comparators = {
-        "static_ms": round(sts.ms_device, 3), "static_iterations": sts.iterations,
-        "naive_dynamic_ms": round(stn.ms_device, 3),
-        "naive_dynamic_iterations": stn.iterations,
-        "df_ms_mean_by_frac": {str(f): round(float(np.mean([x[0] for x in v])), 3)
-                               for f, v in sorted(per.items())},
-        "df_iterations_by_frac": {str(f): round(float(np.mean([x[1] for x in v])), 1)
-                                  for f, v in sorted(per.items())},
-        "df_affected_by_frac": {str(f): int(np.mean([x[2] for x in v]))
-                                for f, v in sorted(per.items())},
-    }
-    comparators["speedup_vs_static_by_frac"] = {
-        k: round(sts.ms_device / v, 2) for k, v in comparators["df_ms_mean_by_frac"].items()}
-    comparators["speedup_vs_naive_by_frac"] = {
-        k: round(stn.ms_device / v, 2) for k, v in comparators["df_ms_mean_by_frac"].items()}
+    # comparators (not timed): for one more batch of each size, Dynamic
+    # Frontier, Naive-dynamic and Static on the same updated graph, the two
+    # dynamic methods starting from the same previous ranks
+    comparators = {"by_frac": {}}
+    for j, f in enumerate(fracs):
+        i = total + j
+        R_prev = g.ranks()
+        g.apply_batch_device(*dev[i])
+        st_df = g.dynamic_frontier_device(*dev[i], p=p)
+        R_df = g.ranks()
+        st_32 = g.dynamic_frontier_device(*dev[i], prev=torch.from_numpy(R_prev).cuda(), p=p32)
+        R_32 = g.ranks()
+        _, st_nv = g.naive_dynamic(R_prev, p=p, out=False)
+        R_nv = g.ranks()
+        _, st_st = g.static(p, out=False)
+        R_st = g.ranks()
+        comparators["by_frac"][str(f)] = {
+            "df_ms": round(st_df.ms_device, 3), "df_iterations": st_df.iterations,
+            "df_affected": st_df.affected_final,
+            "naive_ms": round(st_nv.ms_device, 3), "naive_iterations": st_nv.iterations,
+            "static_ms": round(st_st.ms_device, 3), "static_iterations": st_st.iterations,
+            "speedup_vs_static": round(st_st.ms_device / st_df.ms_device, 2),
+            "speedup_vs_naive": round(st_nv.ms_device / st_df.ms_device, 2),
+            "fp32_form_ms": round(st_32.ms_device, 3),
+            "fp32_form_iterations": st_32.iterations,
+            "fp32_form_refine_sweeps": st_32.refine_sweeps,
+            "fp32_form_linf_vs_fp64_df": float(np.max(np.abs(R_32 - R_df))),
+            "fp32_form_l1_vs_fp64_df": float(np.sum(np.abs(R_32 - R_df))),
+            "linf_df_vs_static": float(np.max(np.abs(R_df - R_st))),
+            "linf_naive_vs_static": float(np.max(np.abs(R_nv - R_st))),
+        }
+        g.set_ranks(R_df)
+        log(f"comparators {f}: DF {st_df.ms_device:.2f} ms, naive {st_nv.ms_device:.2f} ms, "
+            f"static {st_st.ms_device:.2f} ms")
+    comparators["df_ms_mean_by_frac_timed"] = {
+        str(f): round(float(np.mean([x[0] for x in v])), 3) for f, v in sorted(per.items())}
 
     achieved = prof.bytes / (prof.ms / 1e3) / 1e9 if prof.ms > 0 else 0.0
     tb = measured_traffic(workload)

@@ -35,9 +35,12 @@ __host__ __device__ constexpr int group_of(int bin)
 struct Ctl {
     uint32_t live[kBins];       // entries appended to each class list (sparse mode)
     uint32_t snap[2][kBins];    // entries iteration i processes: snap[i & 1]
-    uint32_t ticket;            // workgroups finished in the current iteration
     uint32_t done;              // iteration loop finished (or aborted)
     uint32_t dense;             // iterations walk the full schedule
+    uint32_t phase_end;         // the FP32 phase of the precision form is over
+    int32_t phase_iters;        // iterations of the current FP32 phase
+    double prev_linf;           // Delta R of the previous iteration
+    double renorm_scale;        // 1 / sum of ranks (precision form)
     int32_t iterations;
     int32_t converged;
     double final_linf;
@@ -71,6 +74,7 @@ struct Csr {
 
 struct IterBufs {
     double *dr_part = nullptr;                // per-workgroup L-inf partials
+    double *rmax_part = nullptr;              // per-workgroup largest rank
     unsigned long long *cnt_part = nullptr;   // per-workgroup counters (kCounters each)
 };
 
@@ -127,6 +131,8 @@ struct dfpr_graph {
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     hipEvent_t evk0 = nullptr, evk1 = nullptr;   // around chunks of iteration launches
     dfpr::Profile prof;
+    int64_t prof_base[4] = {0, 0, 0, 0};   // counters already added to prof
+    int32_t refine_sweeps = 0;        // FP64 iterations after the FP32 phase
     int busy = 0;
     int grid = 1024;                  // iteration-kernel workgroups
     uint32_t sparse_limit = 0;        // frontier size that switches to the schedule

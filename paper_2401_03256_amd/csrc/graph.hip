@@ -13,6 +13,11 @@
 
 namespace dfpr {
 
+#ifndef DFPR_GRID_PER_CU
+#define DFPR_GRID_PER_CU 8
+#endif
+constexpr int kGridPerCU = DFPR_GRID_PER_CU;   // iteration-kernel workgroups per CU
+
 static thread_local std::string g_last_error;
 
 int set_error(int code, const std::string &msg)
@@ -176,6 +181,7 @@ void dfpr_free_graph(dfpr_graph *g)
     (void)hipFree(g->scratch_sum);
     if (g->ctl_host) (void)hipHostFree(g->ctl_host);
     (void)hipFree(g->it.dr_part);
+    (void)hipFree(g->it.rmax_part);
     (void)hipFree(g->it.cnt_part);
     for (int o = 0; o < 2; o++) {
         for (int k = 0; k < 2; k++) (void)hipFree(g->ap.keys[o][k]);
@@ -225,6 +231,9 @@ int dfpr_load_graph(int32_t n, int64_t m, const int32_t *src, const int32_t *dst
         if (!rc) rc = al((void **)&g->sched_tmp, ((size_t)n / 4096 + 1) * kBins * 4);
         if (!rc) rc = al((void **)&g->ctl, sizeof(Ctl));
         if (!rc) rc = al((void **)&g->it.dr_part, kMaxGrid * 8);
+        if (!rc) rc = al((void **)&g->it.rmax_part, kMaxGrid * 8);
+        if (!rc) rc = al((void **)&g->C32[0], (size_t)n * 4);
+        if (!rc) rc = al((void **)&g->C32[1], (size_t)n * 4);
         if (!rc) rc = al((void **)&g->it.cnt_part, (size_t)kMaxGrid * kCounters * 8);
         if (!rc) rc = al((void **)&g->scratch_sum, 4096 * 8);
     }
@@ -244,7 +253,7 @@ int dfpr_load_graph(int32_t n, int64_t m, const int32_t *src, const int32_t *dst
     if (!rc) {
         hipDeviceProp_t prop;
         if (hipGetDeviceProperties(&prop, 0) == hipSuccess && prop.multiProcessorCount > 0)
-            g->grid = std::min(kMaxGrid, prop.multiProcessorCount * 8);
+            g->grid = std::min(kMaxGrid, prop.multiProcessorCount * kGridPerCU);
     }
     if (!rc) {
         Ctl c0;

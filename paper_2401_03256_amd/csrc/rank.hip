@@ -6,8 +6,9 @@
 //   - computes Delta r = |r - R[v]| and the L-inf maximum;
 //   - (Dynamic Frontier) marks the out-neighbours of every row whose rank
 //     moved by more than frontier_tol;
-//   - has its last workgroup fold the per-workgroup partials and decide
-//     convergence (Delta R <= tol) or the iteration cap.
+// followed by a one-workgroup launch of k_final that folds the
+// per-workgroup partials and decides convergence (Delta R <= tol) or the
+// iteration cap.
 // The host enqueues iterations in chunks and reads the stop flag between
 // chunks; launches issued after the stop flag is set return at once.
 //
@@ -50,7 +51,13 @@
 
 namespace dfpr {
 
-constexpr int kUnroll = 4;
+#ifndef DFPR_UNROLL
+#define DFPR_UNROLL 4
+#endif
+#ifndef DFPR_ITER_MIN_BLOCKS
+#define DFPR_ITER_MIN_BLOCKS 1
+#endif
+constexpr int kUnroll = DFPR_UNROLL;   // loads in flight per lane and round
 constexpr int kSchedChunk = 4096;   // vertices per workgroup in the schedule build
 
 struct IterArgs {
@@ -61,12 +68,15 @@ struct IterArgs {
     const int32_t *out_idx;
     const double *Rc, *Cc;      // read
     double *Rn, *Cn;            // written
+    const float *C32c;          // FP32 contributions read (precision form)
+    float *C32n;                // FP32 contributions written
     uint32_t *stamp, *xstamp;
     int32_t *bins;              // class lists (sparse mode), n entries each
     const int32_t *sched;       // class schedule of all vertices
     const uint32_t *sched_off;  // kBins + 1 offsets
     Ctl *ctl;
     double *dr_part;
+    double *rmax_part;          // per-workgroup largest new rank
     unsigned long long *cnt_part;   // kCounters per workgroup
     double base_rank;           // (1 - alpha) / n
     double alpha, tol, ftol;
@@ -80,8 +90,60 @@ __device__ inline int lane_id() { return __lane_id(); }
 
 struct Acc {
     double dr_max = 0.0;
+    double r_max = 0.0;
     unsigned long long c[kCounters] = {0, 0, 0, 0};   // rows, edges, xrows, xedges
 };
+
+// Sum of the contributions of in-edges idx[k] for k = first, first + step,
+// ... < cnt, added in that order.  FP64, or (F32) FP32 contributions added
+// with Kahan's compensated summation and returned as sum - compensation in
+// FP64.
+template <bool F32>
+__device__ inline double gather_sum(const IterArgs &a, const int32_t *idx, uint32_t first,
+                                    uint32_t step, uint32_t cnt)
+{
+    if (!F32) {
+        double s = 0.0;
+        for (uint32_t k0 = first; k0 < cnt; k0 += step * kUnroll) {
+            int32_t i[kUnroll];
+#pragma unroll
+            for (int j = 0; j < kUnroll; j++) {
+                const uint32_t k = k0 + j * step;
+                i[j] = k < cnt ? idx[k] : -1;
+            }
+            double c[kUnroll];
+#pragma unroll
+            for (int j = 0; j < kUnroll; j++) c[j] = i[j] >= 0 ? a.Cc[i[j]] : 0.0;
+#pragma unroll
+            for (int j = 0; j < kUnroll; j++)
+                if (i[j] >= 0) s += c[j];
+        }
+        return s;
+    } else {
+        float ks = 0.0f, kc = 0.0f;
+        for (uint32_t k0 = first; k0 < cnt; k0 += step * kUnroll) {
+            int32_t i[kUnroll];
+#pragma unroll
+            for (int j = 0; j < kUnroll; j++) {
+                const uint32_t k = k0 + j * step;
+                i[j] = k < cnt ? idx[k] : -1;
+            }
+            float c[kUnroll];
+#pragma unroll
+            for (int j = 0; j < kUnroll; j++) c[j] = i[j] >= 0 ? a.C32c[i[j]] : 0.0f;
+#pragma unroll
+            for (int j = 0; j < kUnroll; j++) {
+                if (i[j] >= 0) {
+                    const float y = c[j] - kc;
+                    const float t = ks + y;
+                    kc = (t - ks) - y;
+                    ks = t;
+                }
+            }
+        }
+        return (double)ks - (double)kc;
+    }
+}
 
 // Wave-aggregated append of the lanes with `take` set to the class lists.
 // Every lane of the wave calls it.
@@ -137,15 +199,17 @@ __device__ inline void mark_out_row(const IterArgs &a, int32_t w, uint32_t lane0
 }
 
 // Finish one row: Eq. 1, Delta r, writes; returns whether it must expand.
-template <bool DF>
+template <bool DF, bool F32>
 __device__ inline bool finish_row(const IterArgs &a, int32_t v, uint32_t cnt, double s, double rc,
                                   uint32_t oc, Acc &acc)
 {
     const double r = a.base_rank + a.alpha * s;
     const double dr = fabs(r - rc);
     a.Rn[v] = r;
-    a.Cn[v] = r / (double)oc;
+    if (F32) a.C32n[v] = (float)(r / (double)oc);
+    else a.Cn[v] = r / (double)oc;
     acc.dr_max = fmax(acc.dr_max, dr);
+    acc.r_max = fmax(acc.r_max, r);
     acc.c[0] += 1;
     acc.c[1] += cnt;
     if (DF && dr > a.ftol && a.xstamp[v] != a.sbase) {
@@ -158,7 +222,7 @@ __device__ inline bool finish_row(const IterArgs &a, int32_t v, uint32_t cnt, do
 }
 
 // One wave unit: 64/G rows of a class list, G lanes per row.
-template <int G, bool DF>
+template <int G, bool DF, bool F32>
 __device__ inline void wave_unit(const IterArgs &a, const int32_t *list, uint32_t count,
                                  uint32_t first, bool check, bool sparse, Acc &acc)
 {
@@ -187,29 +251,15 @@ __device__ inline void wave_unit(const IterArgs &a, const int32_t *list, uint32_
     if (active) {
         if (cnt == 1) {
             // the self-loop is the only in-edge
-            if (sub == 0) s = a.Cc[v];
+            if (sub == 0) s = F32 ? (double)a.C32c[v] : a.Cc[v];
         } else {
-            const int32_t *idx = a.in_idx + beg;
-            for (uint32_t k0 = sub; k0 < cnt; k0 += G * kUnroll) {
-                int32_t i[kUnroll];
-#pragma unroll
-                for (int j = 0; j < kUnroll; j++) {
-                    const uint32_t k = k0 + j * G;
-                    i[j] = k < cnt ? idx[k] : -1;
-                }
-                double c[kUnroll];
-#pragma unroll
-                for (int j = 0; j < kUnroll; j++) c[j] = i[j] >= 0 ? a.Cc[i[j]] : 0.0;
-#pragma unroll
-                for (int j = 0; j < kUnroll; j++)
-                    if (i[j] >= 0) s += c[j];
-            }
+            s = gather_sum<F32>(a, a.in_idx + beg, sub, G, cnt);
         }
     }
 #pragma unroll
     for (int off = G / 2; off > 0; off >>= 1) s += __shfl_xor(s, off, G);
     bool expand = false;
-    if (active && sub == 0) expand = finish_row<DF>(a, v, cnt, s, rc, oc, acc);
+    if (active && sub == 0) expand = finish_row<DF, F32>(a, v, cnt, s, rc, oc, acc);
     if (DF) {
         unsigned long long q = __ballot(expand);
         const uint32_t sv = a.sbase + (uint32_t)a.it + 1;
@@ -225,7 +275,7 @@ __device__ inline void wave_unit(const IterArgs &a, const int32_t *list, uint32_
 
 // One row of more than 1024 in-edges, the whole workgroup.  All threads
 // call it with the same v.
-template <bool DF>
+template <bool DF, bool F32>
 __device__ inline void block_row(const IterArgs &a, int32_t v, bool check, bool sparse, Acc &acc,
                                  double *red, int *flag)
 {
@@ -234,29 +284,14 @@ __device__ inline void block_row(const IterArgs &a, int32_t v, bool check, bool 
         if (!(st >= a.sbase && st <= a.sbase + (uint32_t)a.it)) return;   // uniform
     }
     const uint32_t beg = a.in_beg[v], cnt = a.in_cnt[v];
-    const int32_t *idx = a.in_idx + beg;
-    double s = 0.0;
-    for (uint32_t k0 = threadIdx.x; k0 < cnt; k0 += kBlock * kUnroll) {
-        int32_t i[kUnroll];
-#pragma unroll
-        for (int j = 0; j < kUnroll; j++) {
-            const uint32_t k = k0 + j * kBlock;
-            i[j] = k < cnt ? idx[k] : -1;
-        }
-        double c[kUnroll];
-#pragma unroll
-        for (int j = 0; j < kUnroll; j++) c[j] = i[j] >= 0 ? a.Cc[i[j]] : 0.0;
-#pragma unroll
-        for (int j = 0; j < kUnroll; j++)
-            if (i[j] >= 0) s += c[j];
-    }
+    double s = gather_sum<F32>(a, a.in_idx + beg, threadIdx.x, kBlock, cnt);
 #pragma unroll
     for (int off = kWave / 2; off > 0; off >>= 1) s += __shfl_xor(s, off, kWave);
     if (lane_id() == 0) red[threadIdx.x / kWave] = s;
     __syncthreads();
     if (threadIdx.x == 0) {
         const double t = ((red[0] + red[1]) + red[2]) + red[3];
-        *flag = finish_row<DF>(a, v, cnt, t, a.Rc[v], a.out_cnt[v], acc) ? 1 : 0;
+        *flag = finish_row<DF, F32>(a, v, cnt, t, a.Rc[v], a.out_cnt[v], acc) ? 1 : 0;
     }
     __syncthreads();
     if (DF && *flag) {
@@ -270,18 +305,20 @@ __device__ inline void block_row(const IterArgs &a, int32_t v, bool check, bool 
 // Fold a max and kCounters sums over the workgroup; thread 0 gets the
 // result.  Waves fold with shuffles, then the four wave results are
 // combined in a fixed order.
-__device__ inline void block_fold(double &dr, unsigned long long (&c)[kCounters], double *wdr,
-                                  unsigned long long (*wc)[kCounters])
+__device__ inline void block_fold(double &dr, double &rm, unsigned long long (&c)[kCounters],
+                                  double *wdr, double *wrm, unsigned long long (*wc)[kCounters])
 {
 #pragma unroll
     for (int off = kWave / 2; off > 0; off >>= 1) {
         dr = fmax(dr, __shfl_xor(dr, off, kWave));
+        rm = fmax(rm, __shfl_xor(rm, off, kWave));
 #pragma unroll
         for (int j = 0; j < kCounters; j++) c[j] += __shfl_xor(c[j], off, kWave);
     }
     const int wave = threadIdx.x / kWave;
     if (lane_id() == 0) {
         wdr[wave] = dr;
+        wrm[wave] = rm;
 #pragma unroll
         for (int j = 0; j < kCounters; j++) wc[wave][j] = c[j];
     }
@@ -289,6 +326,7 @@ __device__ inline void block_fold(double &dr, unsigned long long (&c)[kCounters]
     if (threadIdx.x == 0) {
         for (int w = 1; w < kWavesPerBlock; w++) {
             dr = fmax(dr, wdr[w]);
+            rm = fmax(rm, wrm[w]);
 #pragma unroll
             for (int j = 0; j < kCounters; j++) c[j] += wc[w][j];
         }
@@ -296,101 +334,126 @@ __device__ inline void block_fold(double &dr, unsigned long long (&c)[kCounters]
     __syncthreads();
 }
 
-template <bool DF>
-__global__ __launch_bounds__(kBlock) void k_iter(IterArgs a)
+// Work of one iteration: per class, the list and its length; wave units
+// of classes 5..0 in that order; block units are the class-6 rows.
+struct Plan {
+    uint32_t cnt[kBins];
+    const int32_t *list[kBins];
+    uint32_t ustart[kBins];
+    uint32_t nwu, nbu;
+};
+
+__device__ inline void make_plan(const IterArgs &a, const Ctl *ctl, bool sparse, int par, Plan &p)
 {
-    __shared__ uint32_t s_cnt[kBins];
-    __shared__ const int32_t *s_list[kBins];
-    __shared__ uint32_t s_ustart[kBins];   // wave-unit prefix, classes 5,4,...,0
-    __shared__ uint32_t s_nwu;
+    for (int b = 0; b < kBins; b++) {
+        if (sparse) {
+            p.cnt[b] = ctl->snap[par][b];
+            p.list[b] = a.bins + (size_t)b * a.n_stride;
+        } else {
+            p.cnt[b] = a.sched_off[b + 1] - a.sched_off[b];
+            p.list[b] = a.sched + a.sched_off[b];
+        }
+    }
+    uint32_t acc = 0;
+    for (int k = 0; k < kBins - 1; k++) {
+        const int b = kBins - 2 - k;
+        const uint32_t rows = kWave / group_of(b);
+        p.ustart[k] = acc;
+        acc += (p.cnt[b] + rows - 1) / rows;
+    }
+    p.nwu = acc;
+    p.nbu = p.cnt[kBins - 1];
+}
+
+// Workgroups that have work in an iteration: 0 .. active-1.  With no work
+// at all, workgroup 0 alone records the (empty) iteration.
+__device__ inline uint32_t active_blocks(const Plan &p, uint32_t grid)
+{
+    const uint32_t wblocks = (p.nwu + kWavesPerBlock - 1) / kWavesPerBlock;
+    return max(1u, max(min(grid, p.nbu), min(grid, wblocks)));
+}
+
+template <bool DF, bool F32>
+__global__ __launch_bounds__(kBlock, DFPR_ITER_MIN_BLOCKS) void k_iter(IterArgs a)
+{
+    __shared__ Plan s_plan;
     __shared__ double s_red[kWavesPerBlock];
     __shared__ int s_flag;
-    __shared__ int s_last;
-    __shared__ double s_wdr[kWavesPerBlock];
+    __shared__ double s_wdr[kWavesPerBlock], s_wrm[kWavesPerBlock];
     __shared__ unsigned long long s_wc[kWavesPerBlock][kCounters];
 
-    Ctl *ctl = a.ctl;
-    if (ctl->done) return;
+    const Ctl *ctl = a.ctl;
+    if (ctl->done || (F32 && ctl->phase_end)) return;
     const int par = a.it & 1;
     const bool sparse = DF && !ctl->dense;
     const bool check = DF && !sparse;
-    if (threadIdx.x == 0) {
-        for (int b = 0; b < kBins; b++) {
-            if (sparse) {
-                s_cnt[b] = ctl->snap[par][b];
-                s_list[b] = a.bins + (size_t)b * a.n_stride;
-            } else {
-                s_cnt[b] = a.sched_off[b + 1] - a.sched_off[b];
-                s_list[b] = a.sched + a.sched_off[b];
-            }
-        }
-        uint32_t acc = 0;
-        for (int k = 0; k < kBins - 1; k++) {
-            const int b = kBins - 2 - k;
-            const uint32_t rows = kWave / group_of(b);
-            s_ustart[k] = acc;
-            acc += (s_cnt[b] + rows - 1) / rows;
-        }
-        s_nwu = acc;
-    }
+    if (threadIdx.x == 0) make_plan(a, ctl, sparse, par, s_plan);
     __syncthreads();
-    const uint32_t nbu = s_cnt[kBins - 1], nwu = s_nwu;
     const uint32_t G = gridDim.x;
-    const uint32_t wblocks = (nwu + kWavesPerBlock - 1) / kWavesPerBlock;
-    // workgroups past the work take no part; with no work at all,
-    // workgroup 0 alone records the (empty) iteration
-    const uint32_t active = max(1u, max(min(G, nbu), min(G, wblocks)));
-    if (blockIdx.x >= active) return;
+    if (blockIdx.x >= active_blocks(s_plan, G)) return;
+    const uint32_t nbu = s_plan.nbu, nwu = s_plan.nwu;
 
     Acc acc;
     for (uint32_t u = blockIdx.x; u < nbu; u += G)
-        block_row<DF>(a, s_list[kBins - 1][u], check, sparse, acc, s_red, &s_flag);
+        block_row<DF, F32>(a, s_plan.list[kBins - 1][u], check, sparse, acc, s_red, &s_flag);
 
     const int wave = threadIdx.x / kWave;
     for (uint32_t u = blockIdx.x * kWavesPerBlock + wave; u < nwu; u += G * kWavesPerBlock) {
         int k = 0;
-        while (k + 1 < kBins - 1 && u >= s_ustart[k + 1]) k++;
+        while (k + 1 < kBins - 1 && u >= s_plan.ustart[k + 1]) k++;
         const int b = kBins - 2 - k;
-        const uint32_t first = (u - s_ustart[k]) * (kWave / group_of(b));
+        const uint32_t first = (u - s_plan.ustart[k]) * (kWave / group_of(b));
+        const int32_t *list = s_plan.list[b];
+        const uint32_t cnt = s_plan.cnt[b];
         switch (b) {
-        case 0: wave_unit<1, DF>(a, s_list[0], s_cnt[0], first, check, sparse, acc); break;
-        case 1: wave_unit<2, DF>(a, s_list[1], s_cnt[1], first, check, sparse, acc); break;
-        case 2: wave_unit<4, DF>(a, s_list[2], s_cnt[2], first, check, sparse, acc); break;
-        case 3: wave_unit<8, DF>(a, s_list[3], s_cnt[3], first, check, sparse, acc); break;
-        case 4: wave_unit<32, DF>(a, s_list[4], s_cnt[4], first, check, sparse, acc); break;
-        default: wave_unit<64, DF>(a, s_list[5], s_cnt[5], first, check, sparse, acc); break;
+        case 0: wave_unit<1, DF, F32>(a, list, cnt, first, check, sparse, acc); break;
+        case 1: wave_unit<2, DF, F32>(a, list, cnt, first, check, sparse, acc); break;
+        case 2: wave_unit<4, DF, F32>(a, list, cnt, first, check, sparse, acc); break;
+        case 3: wave_unit<8, DF, F32>(a, list, cnt, first, check, sparse, acc); break;
+        case 4: wave_unit<32, DF, F32>(a, list, cnt, first, check, sparse, acc); break;
+        default: wave_unit<64, DF, F32>(a, list, cnt, first, check, sparse, acc); break;
         }
     }
 
-    double dr = acc.dr_max;
+    double dr = acc.dr_max, rm = acc.r_max;
     unsigned long long c[kCounters];
 #pragma unroll
     for (int j = 0; j < kCounters; j++) c[j] = acc.c[j];
-    block_fold(dr, c, s_wdr, s_wc);
+    block_fold(dr, rm, c, s_wdr, s_wrm, s_wc);
     if (threadIdx.x == 0) {
         a.dr_part[blockIdx.x] = dr;
+        a.rmax_part[blockIdx.x] = rm;
 #pragma unroll
         for (int j = 0; j < kCounters; j++) a.cnt_part[blockIdx.x * kCounters + j] = c[j];
-        const uint32_t t = __hip_atomic_fetch_add(&ctl->ticket, 1u, __ATOMIC_ACQ_REL,
-                                                  __HIP_MEMORY_SCOPE_AGENT);
-        s_last = (t == active - 1);
     }
-    __syncthreads();
-    if (!s_last) return;
+}
 
-    // last workgroup: fold all partials, decide, prepare the next iteration
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-    dr = 0.0;
-#pragma unroll
-    for (int j = 0; j < kCounters; j++) c[j] = 0;
+// After each iteration (one workgroup): fold the partials of the
+// iteration's active workgroups, decide convergence or the cap, and prepare
+// the next iteration.  The launch boundary orders it after k_iter.
+// In the FP32 phase of the precision form, reaching tol or the FP32
+// resolution of the ranks ends the phase instead of the call.
+__global__ __launch_bounds__(kBlock) void k_final(IterArgs a, uint32_t grid, int df, int f32)
+{
+    __shared__ Plan s_plan;
+    __shared__ double s_wdr[kWavesPerBlock], s_wrm[kWavesPerBlock];
+    __shared__ unsigned long long s_wc[kWavesPerBlock][kCounters];
+    Ctl *ctl = a.ctl;
+    if (ctl->done || (f32 && ctl->phase_end)) return;
+    const int par = a.it & 1;
+    const bool sparse = df && !ctl->dense;
+    if (threadIdx.x == 0) make_plan(a, ctl, sparse, par, s_plan);
+    __syncthreads();
+    const uint32_t active = active_blocks(s_plan, grid);
+    double dr = 0.0, rm = 0.0;
+    unsigned long long c[kCounters] = {0, 0, 0, 0};
     for (uint32_t i = threadIdx.x; i < active; i += kBlock) {
-        dr = fmax(dr, __hip_atomic_load(&a.dr_part[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+        dr = fmax(dr, a.dr_part[i]);
+        rm = fmax(rm, a.rmax_part[i]);
 #pragma unroll
-        for (int j = 0; j < kCounters; j++)
-            c[j] += __hip_atomic_load(&a.cnt_part[i * kCounters + j], __ATOMIC_RELAXED,
-                                      __HIP_MEMORY_SCOPE_AGENT);
+        for (int j = 0; j < kCounters; j++) c[j] += a.cnt_part[i * kCounters + j];
     }
-    block_fold(dr, c, s_wdr, s_wc);
+    block_fold(dr, rm, c, s_wdr, s_wrm, s_wc);
     if (threadIdx.x == 0) {
         ctl->verts += c[0];
         ctl->edges += c[1];
@@ -398,13 +461,10 @@ __global__ __launch_bounds__(kBlock) void k_iter(IterArgs a)
         ctl->xedges += c[3];
         ctl->iterations = a.it + 1;
         ctl->final_linf = dr;
-        const bool conv = dr <= a.tol;
-        if (conv) ctl->converged = 1;
         if (sparse) {
             unsigned long long before = 0, after = 0;
             for (int b = 0; b < kBins; b++) {
-                const uint32_t l =
-                    __hip_atomic_load(&ctl->live[b], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                const uint32_t l = ctl->live[b];
                 before += ctl->snap[par][b];
                 after += l;
                 ctl->snap[par ^ 1][b] = l;
@@ -412,8 +472,20 @@ __global__ __launch_bounds__(kBlock) void k_iter(IterArgs a)
             ctl->marked += after - before;
             if (after > a.sparse_limit) ctl->dense = 1;
         }
-        ctl->ticket = 0;
-        if (conv || a.it + 1 >= a.max_iters) ctl->done = 1;
+        if (f32) {
+            // FP32 contributions carry a relative rounding error of 2^-24;
+            // changes below about 2^-22 of the largest rank are noise
+            const double floor32 = rm * 0x1p-22;
+            const bool stalled = ctl->phase_iters >= 3 && dr >= 0.97 * ctl->prev_linf;
+            ctl->phase_iters += 1;
+            if (dr <= a.tol || dr <= floor32 || stalled) ctl->phase_end = 1;
+            if (a.it + 1 >= a.max_iters) ctl->done = 1;
+        } else {
+            const bool conv = dr <= a.tol;
+            if (conv) ctl->converged = 1;
+            if (conv || a.it + 1 >= a.max_iters) ctl->done = 1;
+        }
+        ctl->prev_linf = dr;
     }
 }
 
@@ -429,9 +501,12 @@ __global__ void k_reset(Ctl *ctl)
             ctl->live[b] = 0;
             ctl->snap[0][b] = ctl->snap[1][b] = 0;
         }
-        ctl->ticket = 0;
         ctl->done = 0;
         ctl->dense = 0;
+        ctl->phase_end = 0;
+        ctl->phase_iters = 0;
+        ctl->prev_linf = 0.0;
+        ctl->renorm_scale = 1.0;
         ctl->iterations = 0;
         ctl->converged = 0;
         ctl->final_linf = 0.0;
@@ -452,7 +527,6 @@ __global__ void k_snap(Ctl *ctl, int32_t max_iters, uint32_t sparse_limit, int d
             ctl->snap[0][b] = ctl->live[b];
             tot += ctl->live[b];
         }
-        ctl->ticket = 0;
         ctl->dense = (dense || tot > sparse_limit) ? 1 : 0;
         ctl->done = (ctl->err || max_iters <= 0) ? 1 : 0;
     }
@@ -662,6 +736,65 @@ __global__ __launch_bounds__(kBlock) void k_finish(int32_t n, const uint32_t *st
     if (threadIdx.x == 0 && s_cnt) atomicAdd(&ctl->affected, s_cnt);
 }
 
+// Precision form: FP32 copies of the FP64 contributions, both buffers.
+__global__ void k_c32_init(int32_t n, const double *C, float *A, float *B)
+{
+    for (int32_t v = blockIdx.x * blockDim.x + threadIdx.x; v < n; v += gridDim.x * blockDim.x) {
+        const float c = (float)C[v];
+        A[v] = c;
+        B[v] = c;
+    }
+}
+
+// Sum of the ranks in FP64 with a fixed order: each workgroup folds a fixed
+// range with a fixed tree, then one workgroup folds the partials in order.
+constexpr int kSumBlocks = 1024;
+
+__global__ __launch_bounds__(kBlock) void k_sum_part(int32_t n, const double *R, double *part)
+{
+    __shared__ double s[kBlock];
+    const int64_t chunk = ((int64_t)n + gridDim.x - 1) / gridDim.x;
+    const int64_t lo = blockIdx.x * chunk, hi = min<int64_t>(lo + chunk, n);
+    double acc = 0.0;
+    for (int64_t v = lo + threadIdx.x; v < hi; v += kBlock) acc += R[v];
+    s[threadIdx.x] = acc;
+    __syncthreads();
+    for (int st = kBlock / 2; st > 0; st >>= 1) {
+        if (threadIdx.x < st) s[threadIdx.x] += s[threadIdx.x + st];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) part[blockIdx.x] = s[0];
+}
+
+__global__ __launch_bounds__(kBlock) void k_sum_final(const double *part, int nb, Ctl *ctl)
+{
+    __shared__ double s[kBlock];
+    double acc = 0.0;
+    for (int i = threadIdx.x; i < nb; i += kBlock) acc += part[i];
+    s[threadIdx.x] = acc;
+    __syncthreads();
+    for (int st = kBlock / 2; st > 0; st >>= 1) {
+        if (threadIdx.x < st) s[threadIdx.x] += s[threadIdx.x + st];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) ctl->renorm_scale = s[0] > 0.0 ? 1.0 / s[0] : 1.0;
+}
+
+// R <- R / sum(R) in both buffers and FP64 contributions rebuilt from it.
+__global__ void k_renorm(int32_t n, double *Rres, double *Roth, double *C0, double *C1,
+                         const uint32_t *out_cnt, const Ctl *ctl)
+{
+    const double scale = ctl->renorm_scale;
+    for (int32_t v = blockIdx.x * blockDim.x + threadIdx.x; v < n; v += gridDim.x * blockDim.x) {
+        const double r = Rres[v] * scale;
+        const double c = r / (double)out_cnt[v];
+        Rres[v] = r;
+        Roth[v] = r;
+        C0[v] = c;
+        C1[v] = c;
+    }
+}
+
 static inline int blocks_for(int64_t items, int per_block = kBlock)
 {
     const int64_t b = (items + per_block - 1) / per_block;
@@ -721,6 +854,7 @@ static IterArgs iter_args(dfpr_graph *g, const dfpr_params &p, uint32_t sbase)
     a.sched_off = g->sched_off;
     a.ctl = g->ctl;
     a.dr_part = g->it.dr_part;
+    a.rmax_part = g->it.rmax_part;
     a.cnt_part = g->it.cnt_part;
     a.base_rank = (1.0 - p.alpha) / (double)g->n;
     a.alpha = p.alpha;
@@ -762,32 +896,38 @@ static int take_base(dfpr_graph *g, int32_t max_iters, uint32_t *base)
     return DFPR_OK;
 }
 
-// Run iterations until the device sets the stop flag.  Iteration i reads
-// buffer (base ^ (i & 1)); returns the buffer holding the result.
-// Iterations are enqueued in chunks; between chunks the host reads the
-// control block once and sizes the next chunk from the observed geometric
-// decay of Delta R, so few launches run after convergence.
-static int run_loop(dfpr_graph *g, const dfpr_params &p, bool df, uint32_t sbase, int *res_buf)
+// Run iterations it0, it0+1, ... until the device sets the stop flag (or,
+// in the FP32 phase, the phase-end flag).  The phase starts on buffer
+// `base`; iteration i reads buffer base ^ ((i - it0) & 1).  *res_buf
+// receives the buffer holding the result.  Iterations are enqueued in
+// chunks; between chunks the host reads the control block once and sizes
+// the next chunk from the observed geometric decay of Delta R, so few
+// launches run after convergence.
+static int run_loop(dfpr_graph *g, const dfpr_params &p, bool df, bool f32, uint32_t sbase,
+                    int it0, int base, int *res_buf)
 {
     IterArgs a = iter_args(g, p, sbase);
-    const int base = g->cur;
-    int it = 0, chunk = 4;
+    int it = it0, chunk = 4;
     double prev_dr = -1.0;
-    int prev_it = 0;
+    int prev_it = it0;
     *res_buf = base;
     while (it < p.max_iters) {
         const int k = std::min(chunk, p.max_iters - it);
         if (g->prof.enabled) DFPR_HIP(hipEventRecord(g->evk0, g->stream));
         for (int j = 0; j < k; j++) {
             const int i = it + j;
-            const int src = base ^ (i & 1);
+            const int src = base ^ ((i - it0) & 1);
             a.Rc = g->R[src];
             a.Cc = g->C[src];
             a.Rn = g->R[src ^ 1];
             a.Cn = g->C[src ^ 1];
+            a.C32c = g->C32[src];
+            a.C32n = g->C32[src ^ 1];
             a.it = i;
-            if (df) k_iter<true><<<g->grid, kBlock, 0, g->stream>>>(a);
-            else k_iter<false><<<g->grid, kBlock, 0, g->stream>>>(a);
+            if (!df) k_iter<false, false><<<g->grid, kBlock, 0, g->stream>>>(a);
+            else if (f32) k_iter<true, true><<<g->grid, kBlock, 0, g->stream>>>(a);
+            else k_iter<true, false><<<g->grid, kBlock, 0, g->stream>>>(a);
+            k_final<<<1, kBlock, 0, g->stream>>>(a, (uint32_t)g->grid, df ? 1 : 0, f32 ? 1 : 0);
         }
         DFPR_HIP(hipGetLastError());
         if (g->prof.enabled) DFPR_HIP(hipEventRecord(g->evk1, g->stream));
@@ -799,12 +939,12 @@ static int run_loop(dfpr_graph *g, const dfpr_params &p, bool df, uint32_t sbase
             g->prof.ms += ms;
             g->prof.launches += k;
         }
-        if (g->ctl_host->done) break;
+        if (g->ctl_host->done || (f32 && g->ctl_host->phase_end)) break;
         it += k;
         const double dr = g->ctl_host->final_linf;
         const int its = g->ctl_host->iterations;
         int next = std::min(chunk * 2, 32);
-        if (prev_dr > 0.0 && dr > 0.0 && dr < prev_dr && its > prev_it && p.tol > 0.0) {
+        if (!f32 && prev_dr > 0.0 && dr > 0.0 && dr < prev_dr && its > prev_it && p.tol > 0.0) {
             const double rate = std::pow(dr / prev_dr, 1.0 / (its - prev_it));
             const double need = std::ceil(std::log(p.tol / dr) / std::log(rate));
             if (std::isfinite(need)) next = (int)std::min(64.0, std::max(1.0, need));
@@ -813,26 +953,35 @@ static int run_loop(dfpr_graph *g, const dfpr_params &p, bool df, uint32_t sbase
         prev_it = its;
         chunk = next;
     }
-    if (p.max_iters == 0) {
+    if (p.max_iters <= it0) {
         DFPR_HIP(hipMemcpyAsync(g->ctl_host, g->ctl, sizeof(Ctl), hipMemcpyDeviceToHost, g->stream));
         DFPR_HIP(hipStreamSynchronize(g->stream));
     }
-    *res_buf = base ^ (g->ctl_host->iterations & 1);
+    const Ctl &c = *g->ctl_host;
+    *res_buf = base ^ ((c.iterations - it0) & 1);
     if (g->prof.enabled) {
-        const Ctl &c = *g->ctl_host;
-        g->prof.rows += (int64_t)c.verts;
-        g->prof.edges += (int64_t)c.edges;
-        g->prof.exp_rows += (int64_t)c.xverts;
-        g->prof.exp_edges += (int64_t)c.xedges;
-        g->prof.marked += (int64_t)c.marked;
+        const int64_t dv = (int64_t)c.verts - g->prof_base[0];
+        const int64_t de = (int64_t)c.edges - g->prof_base[1];
+        const int64_t dxv = (int64_t)c.xverts - g->prof_base[2];
+        const int64_t dxe = (int64_t)c.xedges - g->prof_base[3];
+        g->prof.rows += dv;
+        g->prof.edges += de;
+        g->prof.exp_rows += dxv;
+        g->prof.exp_edges += dxe;
         // per processed row: schedule entry 4 B, row start and length 8 B,
-        // R[v] 8 B, |out(v)| 4 B, R'[v] and C'[v] written 16 B (+ its mark
-        // 4 B and expansion stamp 4 B in Dynamic Frontier); per in-edge:
-        // index 4 B and gathered contribution 8 B; per expanding row:
-        // out-row start and length 8 B; per scanned out-edge: index 4 B and
-        // the target's mark 4 B
-        const double row_bytes = df ? 48.0 : 40.0;
-        g->prof.bytes += row_bytes * c.verts + 12.0 * c.edges + 8.0 * c.xverts + 8.0 * c.xedges;
+        // R[v] 8 B, |out(v)| 4 B, R'[v] and C'[v] written 16 B (12 B with an
+        // FP32 contribution) (+ its mark 4 B and expansion stamp 4 B in
+        // Dynamic Frontier); per in-edge: index 4 B and the gathered
+        // contribution (8 B, or 4 B in FP32); per expanding row: out-row
+        // start and length 8 B; per scanned out-edge: index 4 B and the
+        // target's mark 4 B
+        const double row_bytes = (df ? 48.0 : 40.0) - (f32 ? 4.0 : 0.0);
+        const double edge_bytes = f32 ? 8.0 : 12.0;
+        g->prof.bytes += row_bytes * dv + edge_bytes * de + 8.0 * dxv + 8.0 * dxe;
+        g->prof_base[0] = (int64_t)c.verts;
+        g->prof_base[1] = (int64_t)c.edges;
+        g->prof_base[2] = (int64_t)c.xverts;
+        g->prof_base[3] = (int64_t)c.xedges;
     }
     return DFPR_OK;
 }
@@ -843,7 +992,7 @@ static void fill_stats(dfpr_graph *g, dfpr_stats *st, bool df)
     const Ctl &c = *g->ctl_host;
     st->iterations = c.iterations;
     st->converged = c.converged;
-    st->refine_sweeps = 0;
+    st->refine_sweeps = g->refine_sweeps;
     st->reserved = 0;
     st->final_linf = c.final_linf;
     float ms = 0.f;
@@ -884,7 +1033,9 @@ static int full_sweeps(dfpr_graph *g, const dfpr_params *pp, const double *prev,
     k_snap<<<1, 1, 0, s>>>(g->ctl, p.max_iters, g->sparse_limit, 1);
     DFPR_HIP(hipGetLastError());
     int res = cur;
-    rc = run_loop(g, p, false, 0, &res);
+    g->refine_sweeps = 0;
+    std::memset(g->prof_base, 0, sizeof(g->prof_base));
+    rc = run_loop(g, p, false, false, 0, 0, cur, &res);
     if (rc) return rc;
     k_copy2<<<blocks_for(n), kBlock, 0, s>>>(n, g->R[res], g->R[res ^ 1], g->C[res],
                                              g->C[res ^ 1]);
@@ -946,8 +1097,37 @@ static int df_impl(dfpr_graph *g, const dfpr_params *pp, int64_t nd, const int32
     k_snap<<<1, 1, 0, s>>>(g->ctl, p.max_iters, g->sparse_limit, dense);
     DFPR_HIP(hipGetLastError());
     int res = cur;
-    rc = run_loop(g, p, true, sbase, &res);
-    if (rc) return rc;
+    g->refine_sweeps = 0;
+    std::memset(g->prof_base, 0, sizeof(g->prof_base));
+    if (p.precision == DFPR_FP32_KAHAN) {
+        // FP32 phase on FP32 copies of the contributions
+        k_c32_init<<<blocks_for(n), kBlock, 0, s>>>(n, g->C[cur], g->C32[0], g->C32[1]);
+        rc = run_loop(g, p, true, true, sbase, 0, cur, &res);
+        if (rc) return rc;
+        if (g->ctl_host->err)
+            return set_error(DFPR_E_RANGE, "vertex id outside [0, n) in the batch");
+        if (g->ctl_host->done) {
+            // the cap ended the call inside the FP32 phase: rebuild the FP64
+            // contributions (and the second buffer) from the ranks
+            k_init_ranks<<<blocks_for(n), kBlock, 0, s>>>(n, g->R[res], g->R[0], g->R[1],
+                                                          g->C[0], g->C[1], g->csr[1].cnt);
+        } else {
+            // renormalise to sum 1 and continue in FP64 over the same marks
+            const int it0 = g->ctl_host->iterations;
+            k_sum_part<<<kSumBlocks, kBlock, 0, s>>>(n, g->R[res], g->scratch_sum);
+            k_sum_final<<<1, kBlock, 0, s>>>(g->scratch_sum, kSumBlocks, g->ctl);
+            k_renorm<<<blocks_for(n), kBlock, 0, s>>>(n, g->R[res], g->R[res ^ 1], g->C[0],
+                                                      g->C[1], g->csr[1].cnt, g->ctl);
+            DFPR_HIP(hipGetLastError());
+            const int base2 = res;
+            rc = run_loop(g, p, true, false, sbase, it0, base2, &res);
+            if (rc) return rc;
+            g->refine_sweeps = g->ctl_host->iterations - it0;
+        }
+    } else {
+        rc = run_loop(g, p, true, false, sbase, 0, cur, &res);
+        if (rc) return rc;
+    }
     const int32_t iters = g->ctl_host->iterations;
     if (g->ctl_host->err) return set_error(DFPR_E_RANGE, "vertex id outside [0, n) in the batch");
     k_finish<<<std::min(blocks_for(n), 2048), kBlock, 0, s>>>(

@@ -319,3 +319,75 @@ def test_dynamic_frontier_device_entry(dfpr):
     Ro, _ = o.dynamic_frontier(b, Ro)
     assert np.max(np.abs(out.cpu().numpy() - Ro)) < TOL_RANK
     assert st.converged
+
+
+# ---------------------------------------------------------------------------
+# FP32 precision form
+# ---------------------------------------------------------------------------
+
+def test_fp32_form_reaches_fp64_tolerance(dfpr):
+    n = 10000
+    src, dst = synth.gnm(n, 80000, seed=1)
+    g, o = _pair(dfpr, n, src, dst)
+    p64 = dfpr.params(frontier_tol=1e-13)
+    g.static(p64)
+    R0o, _ = o.static()
+    b = synth.random_batch(src, dst, n, 16, 64, seed=1)
+    g.apply_batch(b)
+    o.apply_batch(b)
+    p32 = dfpr.params(frontier_tol=1e-13, precision=dfpr.FP32_KAHAN)
+    R, st = g.dynamic_frontier(b, p=p32)
+    Ro, _ = o.dynamic_frontier(b, R0o, frontier_tol=1e-13)
+    assert st.converged and st.refine_sweeps >= 1
+    assert np.max(np.abs(R - Ro)) < TOL_RANK
+    assert abs(math.fsum(R) - 1.0) < 1e-6
+
+
+def test_fp32_phase_alone_within_1e6(dfpr):
+    # two iterations, both inside the FP32 phase, against the same two
+    # iterations in FP64 from the same start
+    n, src, dst = synth.rmat(12, 16, seed=3)
+    g = dfpr.Graph(n, src, dst)
+    g.static()
+    R0 = g.ranks()
+    b = synth.random_batch(src, dst, n, 20, 80, seed=4)
+    g.apply_batch(b)
+    R64, s64 = g.dynamic_frontier(b, prev=R0, p=dfpr.params(max_iters=2))
+    R32, s32 = g.dynamic_frontier(b, prev=R0, p=dfpr.params(max_iters=2,
+                                                            precision=dfpr.FP32_KAHAN))
+    assert s32.iterations == 2 and s32.refine_sweeps == 0
+    assert np.max(np.abs(R32 - R64)) < 1e-6
+    assert np.max(np.abs(R32 - R64)) > 0.0          # the FP32 path really ran
+
+
+def test_fp32_row_sum_is_compensated(dfpr):
+    # Kahan's bound: |computed - exact| <= (2u + N u^2) sum|x|, u = 2^-24
+    # (Higham, Accuracy and Stability of Numerical Algorithms, 4.3).  Vertex
+    # 0 has in-edges from itself (contribution 1.0) and k leaves
+    # (contribution 3e-8 each, just under half an FP32 ulp of 1.0).  Rows of
+    # this length are summed by 64 lanes, lane 0 taking positions
+    # 0, 64, 128, ...; plain FP32 addition would drop the 15 small terms that
+    # follow 1.0 in lane 0, an error above the bound.
+    k = 1000
+    n = k + 1
+    leaves = np.arange(1, k + 1, dtype=np.int32)
+    g = dfpr.Graph(n, leaves, np.zeros(k, np.int32))     # in-star, centre 0
+    R = np.full(n, 6e-8)
+    R[0] = 1.0            # |out(0)| = 1 (self-loop), |out(leaf)| = 2
+    g.set_ranks(R)
+    x = np.concatenate([[np.float32(1.0)], np.full(k, np.float32(6e-8 / 2))]).astype(np.float32)
+    u = 2.0 ** -24
+    lane0 = x[::64]
+    naive = np.float32(0.0)
+    for t in lane0:
+        naive = np.float32(naive + t)
+    assert abs(float(naive) - math.fsum(lane0.astype(np.float64))) > (2 * u) * float(x.sum())
+    p = dfpr.params(tol=0.0, max_iters=1, precision=dfpr.FP32_KAHAN)
+    Rn, st = g.dynamic_frontier(synth.Batch(np.zeros(0, np.int32), np.zeros(0, np.int32),
+                                            np.array([1], np.int32), np.array([0], np.int32)),
+                                p=p)
+    assert st.iterations == 1 and st.refine_sweeps == 0
+    alpha = 0.85
+    exact = (1 - alpha) / n + alpha * math.fsum(x.astype(np.float64))
+    bound = alpha * (2 * u + len(x) * u * u) * math.fsum(np.abs(x).astype(np.float64))
+    assert abs(Rn[0] - exact) <= bound + 4 * 2.0 ** -53 * exact
