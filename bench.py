@@ -32,7 +32,9 @@ sys.path.insert(0, ROOT)
 METRIC = "GTEPS (edges/s) + update latency p50/p99 per batch; FP32 vs FP64 at 1e-9 L∞"
 HBM_PEAK_GBS = 8000.0
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_iter_traffic.json")
-KERNEL_SRC = os.path.join(ROOT, "paper_2401_03256_amd", "csrc", "rank.hip")
+# sources whose text fixes the iteration kernel's code
+KERNEL_SRC = [os.path.join(ROOT, "paper_2401_03256_amd", "csrc", f)
+              for f in ("iter.h", "common.h", "rank.hip")]
 
 
 def log(*a):
@@ -49,8 +51,11 @@ def pct(xs, q):
 
 
 def kernel_hash():
-    with open(KERNEL_SRC, "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()[:16]
+    h = hashlib.sha256()
+    for path in KERNEL_SRC:
+        with open(path, "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
 
 
 def measured_traffic(workload):

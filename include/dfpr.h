@@ -225,6 +225,69 @@ int dfpr_profile_reset(dfpr_graph *g, int enable);
 /* Read the profile accumulated since the last dfpr_profile_reset. */
 int dfpr_profile_read(const dfpr_graph *g, dfpr_profile *out);
 
+/* ---- serving form --------------------------------------------------------
+ * A server keeps several graphs resident and serves update requests
+ * (graph, batch) that arrive over time, by continuous batching: a request is
+ * admitted into one of max_slots slots when a slot is free, its graph has no
+ * update in flight (one writer per graph, Section 3.2) and the HBM budget
+ * covers the resident graphs plus the scratch of the requests in flight
+ * (96 bytes per batch entry).  Admission applies the batch (as
+ * dfpr_apply_batch) and runs the initial marking; then every step runs one
+ * Dynamic Frontier iteration of every admitted request in one coalesced
+ * launch, and a finished request frees its slot at once.  A request's
+ * result equals that of dfpr_apply_batch followed by
+ * dfpr_pagerank_dynamic_frontier with the graph's parameters, whatever else
+ * is in flight.  The server borrows its graphs; they must stay alive and
+ * must not be used by other calls during dfpr_server_run. */
+
+typedef struct dfpr_server dfpr_server;
+
+typedef struct {
+    int64_t requests, completed, failed;
+    double wall_ms;            /* start of dfpr_server_run to the last completion   */
+    double updates_per_s;      /* completed requests / wall time                    */
+    double latency_p50_ms, latency_p99_ms, latency_mean_ms;   /* arrival to ranks ready */
+    double queue_p50_ms, queue_p99_ms;                        /* arrival to admission   */
+    int32_t max_active;        /* most requests in flight at once                   */
+    int32_t steps;             /* coalesced iteration launches                      */
+    int64_t peak_bytes;        /* largest resident + in-flight budget use           */
+} dfpr_server_stats;
+
+typedef struct {
+    int32_t graph_id;
+    int32_t status;            /* DFPR_OK, or the error that rejected the request   */
+    int32_t iterations, refine_sweeps, converged, reserved;
+    double arrival_ms, admit_ms, done_ms;   /* relative to the start of the run      */
+    int64_t applied[2];        /* effective deletions and insertions                */
+    int64_t edges_processed, affected;
+    double final_linf;
+} dfpr_request_result;
+
+/* max_slots in [1, 8]; hbm_budget_bytes > 0. */
+int dfpr_server_create(int32_t max_slots, int64_t hbm_budget_bytes, dfpr_server **out);
+void dfpr_server_free(dfpr_server *s);
+
+/* Add a resident graph (parameters p, NULL = defaults; p->precision picks
+ * FP64 or the FP32 form for its updates).  DFPR_E_NOMEM if the resident
+ * graphs would exceed the budget.  *graph_id receives its index. */
+int dfpr_server_add_graph(dfpr_server *s, dfpr_graph *g, const dfpr_params *p,
+                          int32_t *graph_id);
+
+/* Queue a request (host arrays, copied) arriving arrival_ms after the start
+ * of dfpr_server_run.  *request_id receives its index. */
+int dfpr_server_submit(dfpr_server *s, int32_t graph_id, double arrival_ms,
+                       int64_t n_del, const int32_t *del_src, const int32_t *del_dst,
+                       int64_t n_ins, const int32_t *ins_src, const int32_t *ins_dst,
+                       int64_t *request_id);
+
+/* Serve every queued request, admitting each no earlier than its arrival
+ * time, and return when all are done.  A request whose batch holds an id
+ * outside [0, n) fails (status DFPR_E_RANGE) without changing its graph. */
+int dfpr_server_run(dfpr_server *s, dfpr_server_stats *st);
+
+/* Outcome of one request after dfpr_server_run. */
+int dfpr_server_result(const dfpr_server *s, int64_t request_id, dfpr_request_result *out);
+
 /* Message for the last non-OK status returned on this thread. */
 const char *dfpr_last_error(void);
 

@@ -1,0 +1,470 @@
+// Device code of one PageRank iteration, shared by the single-graph
+// engines (rank.hip) and the multi-graph serving loop (serve.hip).  The
+// layout and the marking rules are described at the top of rank.hip.
+#pragma once
+
+#include "common.h"
+
+namespace dfpr {
+
+#ifndef DFPR_UNROLL
+#define DFPR_UNROLL 4
+#endif
+#ifndef DFPR_ITER_MIN_BLOCKS
+#define DFPR_ITER_MIN_BLOCKS 1
+#endif
+constexpr int kUnroll = DFPR_UNROLL;   // loads in flight per lane and round
+
+struct IterArgs {
+    int32_t n;
+    const uint32_t *in_beg, *in_cnt;
+    const int32_t *in_idx;
+    const uint32_t *out_beg, *out_cnt;
+    const int32_t *out_idx;
+    const double *Rc, *Cc;      // read
+    double *Rn, *Cn;            // written
+    const float *C32c;          // FP32 contributions read (precision form)
+    float *C32n;                // FP32 contributions written
+    uint32_t *stamp, *xstamp;
+    int32_t *bins;              // class lists (sparse mode), n entries each
+    const int32_t *sched;       // class schedule of all vertices
+    const uint32_t *sched_off;  // kBins + 1 offsets
+    Ctl *ctl;
+    double *dr_part;
+    double *rmax_part;          // per-workgroup largest new rank
+    unsigned long long *cnt_part;   // kCounters per workgroup
+    double base_rank;           // (1 - alpha) / n
+    double alpha, tol, ftol;
+    uint32_t sbase;             // stamp base of the call
+    uint32_t sparse_limit;
+    int32_t it, max_iters;
+    int32_t n_stride;
+};
+
+__device__ inline int lane_id() { return __lane_id(); }
+
+struct Acc {
+    double dr_max = 0.0;
+    double r_max = 0.0;
+    unsigned long long c[kCounters] = {0, 0, 0, 0};   // rows, edges, xrows, xedges
+};
+
+// Sum of the contributions of in-edges idx[k] for k = first, first + step,
+// ... < cnt, added in that order.  FP64, or (F32) FP32 contributions added
+// with Kahan's compensated summation and returned as sum - compensation in
+// FP64.
+template <bool F32>
+__device__ inline double gather_sum(const IterArgs &a, const int32_t *idx, uint32_t first,
+                                    uint32_t step, uint32_t cnt)
+{
+    if (!F32) {
+        double s = 0.0;
+        for (uint32_t k0 = first; k0 < cnt; k0 += step * kUnroll) {
+            int32_t i[kUnroll];
+#pragma unroll
+            for (int j = 0; j < kUnroll; j++) {
+                const uint32_t k = k0 + j * step;
+                i[j] = k < cnt ? idx[k] : -1;
+            }
+            double c[kUnroll];
+#pragma unroll
+            for (int j = 0; j < kUnroll; j++) c[j] = i[j] >= 0 ? a.Cc[i[j]] : 0.0;
+#pragma unroll
+            for (int j = 0; j < kUnroll; j++)
+                if (i[j] >= 0) s += c[j];
+        }
+        return s;
+    } else {
+        float ks = 0.0f, kc = 0.0f;
+        for (uint32_t k0 = first; k0 < cnt; k0 += step * kUnroll) {
+            int32_t i[kUnroll];
+#pragma unroll
+            for (int j = 0; j < kUnroll; j++) {
+                const uint32_t k = k0 + j * step;
+                i[j] = k < cnt ? idx[k] : -1;
+            }
+            float c[kUnroll];
+#pragma unroll
+            for (int j = 0; j < kUnroll; j++) c[j] = i[j] >= 0 ? a.C32c[i[j]] : 0.0f;
+#pragma unroll
+            for (int j = 0; j < kUnroll; j++) {
+                if (i[j] >= 0) {
+                    const float y = c[j] - kc;
+                    const float t = ks + y;
+                    kc = (t - ks) - y;
+                    ks = t;
+                }
+            }
+        }
+        return (double)ks - (double)kc;
+    }
+}
+
+// Wave-aggregated append of the lanes with `take` set to the class lists.
+// Every lane of the wave calls it.
+__device__ inline void append_to_bins(bool take, int32_t x, int cls, Ctl *ctl, int32_t *bins,
+                                      uint32_t stride)
+{
+    unsigned long long pend = __ballot(take);
+    const int lane = lane_id();
+    const unsigned long long below = (1ull << lane) - 1ull;
+    while (pend) {
+        const int leader = __ffsll((long long)pend) - 1;
+        const int c = __shfl(cls, leader);
+        const unsigned long long mine = __ballot(take && cls == c);
+        uint32_t base = 0;
+        if (lane == leader) base = atomicAdd(&ctl->live[c], (uint32_t)__popcll(mine));
+        base = __shfl(base, leader);
+        if (take && cls == c) bins[(size_t)c * stride + base + __popcll(mine & below)] = x;
+        pend &= ~mine;
+    }
+}
+
+// Mark the out-neighbours of w with stamp `sv`.  The calling lanes take
+// positions lane0, lane0 + step, ... (lane0 < step); every lane of every
+// calling wave runs the same number of rounds.
+template <bool SPARSE>
+__device__ inline void mark_out_row(const IterArgs &a, int32_t w, uint32_t lane0, uint32_t step,
+                                    uint32_t sv)
+{
+    const uint32_t ob = a.out_beg[w], oc = a.out_cnt[w];
+    for (uint32_t k0 = 0; k0 < oc; k0 += step * kUnroll) {
+        int32_t x[kUnroll];
+#pragma unroll
+        for (int j = 0; j < kUnroll; j++) {
+            const uint32_t k = k0 + lane0 + j * step;
+            x[j] = k < oc ? a.out_idx[ob + k] : -1;
+        }
+        uint32_t st[kUnroll];
+#pragma unroll
+        for (int j = 0; j < kUnroll; j++) st[j] = x[j] >= 0 ? a.stamp[x[j]] : 0xFFFFFFFFu;
+#pragma unroll
+        for (int j = 0; j < kUnroll; j++) {
+            bool nw = false;
+            if (st[j] < a.sbase) {
+                if (SPARSE) nw = atomicMax(&a.stamp[x[j]], sv) < a.sbase;
+                else a.stamp[x[j]] = sv;
+            }
+            if (SPARSE) {
+                const int cls = nw ? bin_of(a.in_cnt[x[j]]) : 0;
+                append_to_bins(nw, x[j], cls, a.ctl, a.bins, a.n_stride);
+            }
+        }
+    }
+}
+
+// Finish one row: Eq. 1, Delta r, writes; returns whether it must expand.
+template <bool DF, bool F32>
+__device__ inline bool finish_row(const IterArgs &a, int32_t v, uint32_t cnt, double s, double rc,
+                                  uint32_t oc, Acc &acc)
+{
+    const double r = a.base_rank + a.alpha * s;
+    const double dr = fabs(r - rc);
+    a.Rn[v] = r;
+    if (F32) a.C32n[v] = (float)(r / (double)oc);
+    else a.Cn[v] = r / (double)oc;
+    acc.dr_max = fmax(acc.dr_max, dr);
+    acc.r_max = fmax(acc.r_max, r);
+    acc.c[0] += 1;
+    acc.c[1] += cnt;
+    if (DF && dr > a.ftol && a.xstamp[v] != a.sbase) {
+        a.xstamp[v] = a.sbase;
+        acc.c[2] += 1;
+        acc.c[3] += oc;
+        return true;
+    }
+    return false;
+}
+
+// One wave unit: 64/G rows of a class list, G lanes per row.
+template <int G, bool DF, bool F32>
+__device__ inline void wave_unit(const IterArgs &a, const int32_t *list, uint32_t count,
+                                 uint32_t first, bool check, bool sparse, Acc &acc)
+{
+    const int lane = lane_id();
+    const int sub = lane & (G - 1);
+    const uint32_t pos = first + lane / G;
+    bool active = false;
+    int32_t v = 0;
+    uint32_t beg = 0, cnt = 0, oc = 1;
+    double rc = 0.0;
+    if (pos < count) {
+        v = list[pos];
+        beg = a.in_beg[v];
+        cnt = a.in_cnt[v];
+        if (sub == 0) {
+            rc = a.Rc[v];
+            oc = a.out_cnt[v];
+        }
+        active = true;
+        if (DF && check) {
+            const uint32_t st = a.stamp[v];
+            active = st >= a.sbase && st <= a.sbase + (uint32_t)a.it;
+        }
+    }
+    double s = 0.0;
+    if (active) {
+        if (cnt == 1) {
+            // the self-loop is the only in-edge
+            if (sub == 0) s = F32 ? (double)a.C32c[v] : a.Cc[v];
+        } else {
+            s = gather_sum<F32>(a, a.in_idx + beg, sub, G, cnt);
+        }
+    }
+#pragma unroll
+    for (int off = G / 2; off > 0; off >>= 1) s += __shfl_xor(s, off, G);
+    bool expand = false;
+    if (active && sub == 0) expand = finish_row<DF, F32>(a, v, cnt, s, rc, oc, acc);
+    if (DF) {
+        unsigned long long q = __ballot(expand);
+        const uint32_t sv = a.sbase + (uint32_t)a.it + 1;
+        while (q) {
+            const int l = __ffsll((long long)q) - 1;
+            const int32_t w = __shfl(v, l);
+            if (sparse) mark_out_row<true>(a, w, lane, kWave, sv);
+            else mark_out_row<false>(a, w, lane, kWave, sv);
+            q &= q - 1;
+        }
+    }
+}
+
+// One row of more than 1024 in-edges, the whole workgroup.  All threads
+// call it with the same v.
+template <bool DF, bool F32>
+__device__ inline void block_row(const IterArgs &a, int32_t v, bool check, bool sparse, Acc &acc,
+                                 double *red, int *flag)
+{
+    if (DF && check) {
+        const uint32_t st = a.stamp[v];
+        if (!(st >= a.sbase && st <= a.sbase + (uint32_t)a.it)) return;   // uniform
+    }
+    const uint32_t beg = a.in_beg[v], cnt = a.in_cnt[v];
+    double s = gather_sum<F32>(a, a.in_idx + beg, threadIdx.x, kBlock, cnt);
+#pragma unroll
+    for (int off = kWave / 2; off > 0; off >>= 1) s += __shfl_xor(s, off, kWave);
+    if (lane_id() == 0) red[threadIdx.x / kWave] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const double t = ((red[0] + red[1]) + red[2]) + red[3];
+        *flag = finish_row<DF, F32>(a, v, cnt, t, a.Rc[v], a.out_cnt[v], acc) ? 1 : 0;
+    }
+    __syncthreads();
+    if (DF && *flag) {
+        const uint32_t sv = a.sbase + (uint32_t)a.it + 1;
+        if (sparse) mark_out_row<true>(a, v, threadIdx.x, kBlock, sv);
+        else mark_out_row<false>(a, v, threadIdx.x, kBlock, sv);
+    }
+    __syncthreads();
+}
+
+// Fold a max and kCounters sums over the workgroup; thread 0 gets the
+// result.  Waves fold with shuffles, then the four wave results are
+// combined in a fixed order.
+__device__ inline void block_fold(double &dr, double &rm, unsigned long long (&c)[kCounters],
+                                  double *wdr, double *wrm, unsigned long long (*wc)[kCounters])
+{
+#pragma unroll
+    for (int off = kWave / 2; off > 0; off >>= 1) {
+        dr = fmax(dr, __shfl_xor(dr, off, kWave));
+        rm = fmax(rm, __shfl_xor(rm, off, kWave));
+#pragma unroll
+        for (int j = 0; j < kCounters; j++) c[j] += __shfl_xor(c[j], off, kWave);
+    }
+    const int wave = threadIdx.x / kWave;
+    if (lane_id() == 0) {
+        wdr[wave] = dr;
+        wrm[wave] = rm;
+#pragma unroll
+        for (int j = 0; j < kCounters; j++) wc[wave][j] = c[j];
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int w = 1; w < kWavesPerBlock; w++) {
+            dr = fmax(dr, wdr[w]);
+            rm = fmax(rm, wrm[w]);
+#pragma unroll
+            for (int j = 0; j < kCounters; j++) c[j] += wc[w][j];
+        }
+    }
+    __syncthreads();
+}
+
+// Work of one iteration: per class, the list and its length; wave units
+// of classes 5..0 in that order; block units are the class-6 rows.
+struct Plan {
+    uint32_t cnt[kBins];
+    const int32_t *list[kBins];
+    uint32_t ustart[kBins];
+    uint32_t nwu, nbu;
+};
+
+__device__ inline void make_plan(const IterArgs &a, const Ctl *ctl, bool sparse, int par, Plan &p)
+{
+    for (int b = 0; b < kBins; b++) {
+        if (sparse) {
+            p.cnt[b] = ctl->snap[par][b];
+            p.list[b] = a.bins + (size_t)b * a.n_stride;
+        } else {
+            p.cnt[b] = a.sched_off[b + 1] - a.sched_off[b];
+            p.list[b] = a.sched + a.sched_off[b];
+        }
+    }
+    uint32_t acc = 0;
+    for (int k = 0; k < kBins - 1; k++) {
+        const int b = kBins - 2 - k;
+        const uint32_t rows = kWave / group_of(b);
+        p.ustart[k] = acc;
+        acc += (p.cnt[b] + rows - 1) / rows;
+    }
+    p.nwu = acc;
+    p.nbu = p.cnt[kBins - 1];
+}
+
+// Workgroups that have work in an iteration: 0 .. active-1.  With no work
+// at all, workgroup 0 alone records the (empty) iteration.
+__device__ inline uint32_t active_blocks(const Plan &p, uint32_t grid)
+{
+    const uint32_t wblocks = (p.nwu + kWavesPerBlock - 1) / kWavesPerBlock;
+    return max(1u, max(min(grid, p.nbu), min(grid, wblocks)));
+}
+
+// Shared memory of one workgroup of an iteration.
+struct IterShared {
+    Plan plan;
+    double red[kWavesPerBlock];
+    int flag;
+    double wdr[kWavesPerBlock], wrm[kWavesPerBlock];
+    unsigned long long wc[kWavesPerBlock][kCounters];
+};
+
+// One workgroup's share of an iteration of one graph: workgroup blk of the
+// G workgroups given to the graph.  Its partials go to slot blk.
+template <bool DF, bool F32>
+__device__ inline void iter_body(const IterArgs &a, uint32_t blk, uint32_t G, IterShared &sh)
+{
+    const Ctl *ctl = a.ctl;
+    if (ctl->done || (F32 && ctl->phase_end)) return;
+    const int par = a.it & 1;
+    const bool sparse = DF && !ctl->dense;
+    const bool check = DF && !sparse;
+    if (threadIdx.x == 0) make_plan(a, ctl, sparse, par, sh.plan);
+    __syncthreads();
+    if (blk >= active_blocks(sh.plan, G)) return;
+    const uint32_t nbu = sh.plan.nbu, nwu = sh.plan.nwu;
+
+    Acc acc;
+    for (uint32_t u = blk; u < nbu; u += G)
+        block_row<DF, F32>(a, sh.plan.list[kBins - 1][u], check, sparse, acc, sh.red, &sh.flag);
+
+    const int wave = threadIdx.x / kWave;
+    for (uint32_t u = blk * kWavesPerBlock + wave; u < nwu; u += G * kWavesPerBlock) {
+        int k = 0;
+        while (k + 1 < kBins - 1 && u >= sh.plan.ustart[k + 1]) k++;
+        const int b = kBins - 2 - k;
+        const uint32_t first = (u - sh.plan.ustart[k]) * (kWave / group_of(b));
+        const int32_t *list = sh.plan.list[b];
+        const uint32_t cnt = sh.plan.cnt[b];
+        switch (b) {
+        case 0: wave_unit<1, DF, F32>(a, list, cnt, first, check, sparse, acc); break;
+        case 1: wave_unit<2, DF, F32>(a, list, cnt, first, check, sparse, acc); break;
+        case 2: wave_unit<4, DF, F32>(a, list, cnt, first, check, sparse, acc); break;
+        case 3: wave_unit<8, DF, F32>(a, list, cnt, first, check, sparse, acc); break;
+        case 4: wave_unit<32, DF, F32>(a, list, cnt, first, check, sparse, acc); break;
+        default: wave_unit<64, DF, F32>(a, list, cnt, first, check, sparse, acc); break;
+        }
+    }
+
+    double dr = acc.dr_max, rm = acc.r_max;
+    unsigned long long c[kCounters];
+#pragma unroll
+    for (int j = 0; j < kCounters; j++) c[j] = acc.c[j];
+    block_fold(dr, rm, c, sh.wdr, sh.wrm, sh.wc);
+    if (threadIdx.x == 0) {
+        a.dr_part[blk] = dr;
+        a.rmax_part[blk] = rm;
+#pragma unroll
+        for (int j = 0; j < kCounters; j++) a.cnt_part[blk * kCounters + j] = c[j];
+    }
+}
+
+// After each iteration (one workgroup): fold the partials of the
+// iteration's active workgroups, decide convergence or the cap, and prepare
+// the next iteration.  The launch boundary orders it after k_iter.
+// In the FP32 phase of the precision form, reaching tol or the FP32
+// resolution of the ranks ends the phase instead of the call.
+// `active` is the number of workgroups that wrote partials for this graph.
+__device__ inline void final_body(const IterArgs &a, uint32_t active, bool df, bool f32,
+                                  IterShared &sh)
+{
+    Ctl *ctl = a.ctl;
+    if (ctl->done || (f32 && ctl->phase_end)) return;
+    const int par = a.it & 1;
+    const bool sparse = df && !ctl->dense;
+    double dr = 0.0, rm = 0.0;
+    unsigned long long c[kCounters] = {0, 0, 0, 0};
+    for (uint32_t i = threadIdx.x; i < active; i += kBlock) {
+        dr = fmax(dr, a.dr_part[i]);
+        rm = fmax(rm, a.rmax_part[i]);
+#pragma unroll
+        for (int j = 0; j < kCounters; j++) c[j] += a.cnt_part[i * kCounters + j];
+    }
+    block_fold(dr, rm, c, sh.wdr, sh.wrm, sh.wc);
+    if (threadIdx.x == 0) {
+        ctl->verts += c[0];
+        ctl->edges += c[1];
+        ctl->xverts += c[2];
+        ctl->xedges += c[3];
+        ctl->iterations = a.it + 1;
+        ctl->final_linf = dr;
+        if (sparse) {
+            unsigned long long before = 0, after = 0;
+            for (int b = 0; b < kBins; b++) {
+                const uint32_t l = ctl->live[b];
+                before += ctl->snap[par][b];
+                after += l;
+                ctl->snap[par ^ 1][b] = l;
+            }
+            ctl->marked += after - before;
+            if (after > a.sparse_limit) ctl->dense = 1;
+        }
+        if (f32) {
+            // FP32 contributions carry a relative rounding error of 2^-24;
+            // changes below about 2^-22 of the largest rank are noise
+            const double floor32 = rm * 0x1p-22;
+            const bool stalled = ctl->phase_iters >= 3 && dr >= 0.97 * ctl->prev_linf;
+            ctl->phase_iters += 1;
+            if (dr <= a.tol || dr <= floor32 || stalled) ctl->phase_end = 1;
+            if (a.it + 1 >= a.max_iters) ctl->done = 1;
+        } else {
+            const bool conv = dr <= a.tol;
+            if (conv) ctl->converged = 1;
+            if (conv || a.it + 1 >= a.max_iters) ctl->done = 1;
+        }
+        ctl->prev_linf = dr;
+    }
+}
+
+
+// Workgroups that hold partials of the iteration just run (single graph).
+__device__ inline uint32_t single_graph_active(const IterArgs &a, bool df, uint32_t grid,
+                                               Plan &plan)
+{
+    const bool sparse = df && !a.ctl->dense;
+    make_plan(a, a.ctl, sparse, a.it & 1, plan);
+    return active_blocks(plan, grid);
+}
+
+}  // namespace dfpr
+
+namespace dfpr {
+
+// Host helpers of rank.hip shared with the serving loop (serve.hip).
+IterArgs iter_args(dfpr_graph *g, const dfpr_params &p, uint32_t sbase);
+int check_params(const dfpr_params *p, dfpr_params &out);
+int df_begin(dfpr_graph *g, const dfpr_params &p, int64_t nd, const int32_t *bds,
+             const int32_t *bdd, int64_t ni, const int32_t *bis, const int32_t *bid,
+             const double *prev, int prev_dev, uint32_t *sbase_out);
+int df_phase_end(dfpr_graph *g, int res, bool call_done);
+int df_finish(dfpr_graph *g, uint32_t sbase, int res, int32_t iters);
+
+}  // namespace dfpr

@@ -34,6 +34,8 @@ EXPORTED = [
     "dfpr_pagerank_dynamic_frontier", "dfpr_pagerank_dynamic_frontier_device",
     "dfpr_mark_affected", "dfpr_get_affected", "dfpr_get_ranks", "dfpr_set_ranks",
     "dfpr_export_csr", "dfpr_last_error", "dfpr_profile_reset", "dfpr_profile_read",
+    "dfpr_server_create", "dfpr_server_free", "dfpr_server_add_graph", "dfpr_server_submit",
+    "dfpr_server_run", "dfpr_server_result",
 ]
 
 
@@ -65,6 +67,34 @@ class Profile(ctypes.Structure):
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class ServerStats(ctypes.Structure):
+    _fields_ = [("requests", ctypes.c_int64), ("completed", ctypes.c_int64),
+                ("failed", ctypes.c_int64), ("wall_ms", ctypes.c_double),
+                ("updates_per_s", ctypes.c_double), ("latency_p50_ms", ctypes.c_double),
+                ("latency_p99_ms", ctypes.c_double), ("latency_mean_ms", ctypes.c_double),
+                ("queue_p50_ms", ctypes.c_double), ("queue_p99_ms", ctypes.c_double),
+                ("max_active", ctypes.c_int32), ("steps", ctypes.c_int32),
+                ("peak_bytes", ctypes.c_int64)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class RequestResult(ctypes.Structure):
+    _fields_ = [("graph_id", ctypes.c_int32), ("status", ctypes.c_int32),
+                ("iterations", ctypes.c_int32), ("refine_sweeps", ctypes.c_int32),
+                ("converged", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("arrival_ms", ctypes.c_double), ("admit_ms", ctypes.c_double),
+                ("done_ms", ctypes.c_double), ("applied", ctypes.c_int64 * 2),
+                ("edges_processed", ctypes.c_int64), ("affected", ctypes.c_int64),
+                ("final_linf", ctypes.c_double)]
+
+    def as_dict(self):
+        d = {k: getattr(self, k) for k, _ in self._fields_ if k != "applied"}
+        d["applied"] = (int(self.applied[0]), int(self.applied[1]))
+        return d
 
 
 @dataclass
@@ -125,6 +155,13 @@ def lib():
     L.dfpr_export_csr.argtypes = [_P, ctypes.c_int, _P, _P]
     L.dfpr_profile_reset.argtypes = [_P, ctypes.c_int]
     L.dfpr_profile_read.argtypes = [_P, _P]
+    L.dfpr_server_create.argtypes = [_I32, _I64, ctypes.POINTER(_P)]
+    L.dfpr_server_free.argtypes = [_P]
+    L.dfpr_server_free.restype = None
+    L.dfpr_server_add_graph.argtypes = [_P, _P, _P, _P]
+    L.dfpr_server_submit.argtypes = [_P, _I32, ctypes.c_double, *batch, _P]
+    L.dfpr_server_run.argtypes = [_P, _P]
+    L.dfpr_server_result.argtypes = [_P, _I64, _P]
     L.dfpr_last_error.argtypes = []
     L.dfpr_last_error.restype = ctypes.c_char_p
     _lib = L
@@ -304,3 +341,50 @@ class Graph:
         idx = np.zeros(max(self.m, 1), np.int32)
         _check(lib().dfpr_export_csr(self._h, 1 if out else 0, _hp(off), _hp(idx)))
         return off, idx[: self.m]
+
+
+class Server:
+    """Serving form: resident graphs, update requests served by continuous
+    batching (``dfpr_server_*`` in include/dfpr.h)."""
+
+    def __init__(self, max_slots=8, hbm_budget_bytes=64 << 30):
+        h = _P()
+        _check(lib().dfpr_server_create(int(max_slots), int(hbm_budget_bytes), ctypes.byref(h)))
+        self._h = h
+        self._graphs = []
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            lib().dfpr_server_free(self._h)
+        self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def add_graph(self, graph: Graph, p: Params | None = None) -> int:
+        gid = _I32()
+        _check(lib().dfpr_server_add_graph(self._h, graph.handle, ctypes.byref(p) if p else None,
+                                           ctypes.byref(gid)))
+        self._graphs.append(graph)
+        return int(gid.value)
+
+    def submit(self, gid, arrival_ms, batch) -> int:
+        ds, dd, is_, id_ = (_i32(batch.del_src), _i32(batch.del_dst), _i32(batch.ins_src),
+                            _i32(batch.ins_dst))
+        rid = _I64()
+        _check(lib().dfpr_server_submit(self._h, int(gid), float(arrival_ms), ds.size, _hp(ds),
+                                        _hp(dd), is_.size, _hp(is_), _hp(id_), ctypes.byref(rid)))
+        return int(rid.value)
+
+    def run(self) -> dict:
+        st = ServerStats()
+        _check(lib().dfpr_server_run(self._h, ctypes.byref(st)))
+        return st.as_dict()
+
+    def result(self, rid) -> dict:
+        r = RequestResult()
+        _check(lib().dfpr_server_result(self._h, int(rid), ctypes.byref(r)))
+        return r.as_dict()

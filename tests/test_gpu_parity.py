@@ -391,3 +391,128 @@ def test_fp32_row_sum_is_compensated(dfpr):
     exact = (1 - alpha) / n + alpha * math.fsum(x.astype(np.float64))
     bound = alpha * (2 * u + len(x) * u * u) * math.fsum(np.abs(x).astype(np.float64))
     assert abs(Rn[0] - exact) <= bound + 4 * 2.0 ** -53 * exact
+
+
+# ---------------------------------------------------------------------------
+# serving form
+# ---------------------------------------------------------------------------
+
+def _serving_workload():
+    specs = [("rmat", 10, 1, dfpr_mod_fp64), ("rmat", 11, 2, dfpr_mod_fp32),
+             ("rmat", 12, 3, dfpr_mod_fp64), ("gnm", 5000, 4, dfpr_mod_fp64)]
+    out = []
+    for kind, size, seed, prec in specs:
+        if kind == "rmat":
+            n, s, d = synth.rmat(size, 16, seed=seed)
+        else:
+            n = size
+            s, d = synth.gnm(n, 8 * n, seed=seed)
+        m = s.size + n
+        counts = [synth.batch_counts(f, m) for f in (1e-4, 1e-2, 1e-3, 3e-3)]
+        out.append((n, s, d, prec, synth.batch_sequence(s, d, n, counts, seed=seed + 100)))
+    return out
+
+
+dfpr_mod_fp64, dfpr_mod_fp32 = 0, 1
+
+
+def test_serving_results_equal_alone_and_in_the_mix(dfpr):
+    work = _serving_workload()
+    # alone: each graph's batches one after another through the plain calls
+    alone = []
+    for n, s, d, prec, batches in work:
+        g = dfpr.Graph(n, s, d)
+        p = dfpr.params(frontier_tol=1e-13, precision=prec)
+        g.static(dfpr.params(frontier_tol=1e-13))
+        its = []
+        for b in batches:
+            g.apply_batch(b)
+            _, st = g.dynamic_frontier(b, p=p)
+            its.append(st.iterations)
+        alone.append((g.ranks(), its))
+        g.close()
+    # mix: the same requests, all arriving at once, through the server
+    graphs = []
+    srv = dfpr.Server(max_slots=4)
+    for n, s, d, prec, batches in work:
+        g = dfpr.Graph(n, s, d)
+        g.static(dfpr.params(frontier_tol=1e-13))
+        gid = srv.add_graph(g, dfpr.params(frontier_tol=1e-13, precision=prec))
+        graphs.append((g, gid))
+    rids = []
+    for k in range(4):
+        for (g, gid), (_, _, _, _, batches) in zip(graphs, work):
+            rids.append((gid, k, srv.submit(gid, 0.0, batches[k])))
+    st = srv.run()
+    assert st["completed"] == len(rids) and st["failed"] == 0
+    assert st["max_active"] > 1                    # requests really overlapped
+    for gid, k, rid in rids:
+        r = srv.result(rid)
+        assert r["status"] == 0 and r["converged"]
+        assert r["iterations"] == alone[gid][1][k]
+    for (g, gid) in graphs:
+        assert np.array_equal(g.ranks(), alone[gid][0])
+
+
+def test_serving_budget_limits_concurrency(dfpr):
+    n, s, d = synth.rmat(10, 16, seed=5)
+    gs = []
+    for i in range(3):
+        g = dfpr.Graph(n, s, d)
+        g.static()
+        gs.append(g)
+    counts = [synth.batch_counts(1e-3, s.size + n)] * 2
+    seq = synth.batch_sequence(s, d, n, counts, seed=6)
+    # the resident bytes of the three graphs, from a server with no requests
+    probe = dfpr.Server(max_slots=8, hbm_budget_bytes=1 << 40)
+    for g in gs:
+        probe.add_graph(g)
+    resident = probe.run()["peak_bytes"]
+    probe.close()
+    # room for one request at a time: three graphs, all requests at t = 0
+    srv = dfpr.Server(max_slots=8, hbm_budget_bytes=resident + 96 * seq[0].size + 8)
+    ids = [srv.add_graph(g) for g in gs]
+    rids = [srv.submit(gid, 0.0, seq[i % 2]) for i, gid in enumerate(ids)]
+    st = srv.run()
+    assert st["completed"] == 3 and st["max_active"] == 1
+    assert st["peak_bytes"] <= resident + 96 * seq[0].size + 8
+    ends = sorted((srv.result(r)["admit_ms"], srv.result(r)["done_ms"]) for r in rids)
+    for (a0, e0), (a1, _) in zip(ends, ends[1:]):
+        assert a1 >= e0                                # one at a time
+    # a second run serves only the new request
+    r4 = srv.submit(ids[0], 0.0, synth.Batch.empty())
+    st = srv.run()
+    assert st["completed"] == 1 and srv.result(r4)["iterations"] == 1
+    # graphs that do not fit the budget are refused
+    small = dfpr.Server(max_slots=2, hbm_budget_bytes=1024)
+    with pytest.raises(dfpr.DfprError):
+        small.add_graph(gs[0])
+
+
+def test_serving_arrivals_one_writer_and_bad_requests(dfpr):
+    n, s, d = synth.rmat(11, 16, seed=7)
+    g = dfpr.Graph(n, s, d)
+    g.static()
+    counts = [synth.batch_counts(1e-3, s.size + n)] * 3
+    seq = synth.batch_sequence(s, d, n, counts, seed=8)
+    ref = dfpr.Graph(n, s, d)
+    ref.static()
+    for b in seq:
+        ref.apply_batch(b)
+        ref.dynamic_frontier(b)
+    srv = dfpr.Server(max_slots=4)
+    gid = srv.add_graph(g)
+    arr = [0.0, 0.0, 30.0]
+    bad = _batch([], [(0, n)])
+    rids = [srv.submit(gid, arr[0], seq[0]), srv.submit(gid, arr[1], seq[1]),
+            srv.submit(gid, 1.0, bad), srv.submit(gid, arr[2], seq[2])]
+    st = srv.run()
+    assert st["completed"] == 3 and st["failed"] == 1
+    res = [srv.result(r) for r in rids]
+    assert res[2]["status"] != 0                       # rejected, graph unchanged
+    good = [res[0], res[1], res[3]]
+    for r, a in zip(good, arr):
+        assert r["status"] == 0 and r["admit_ms"] >= a
+    for r0, r1 in zip(good, good[1:]):
+        assert r1["admit_ms"] >= r0["done_ms"]         # one writer per graph
+    assert np.array_equal(g.ranks(), ref.ranks())
