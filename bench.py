@@ -82,6 +82,13 @@ def main():
     ap.add_argument("--frontier-tol", type=float, default=1e-13)
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--serve", action="store_true",
+                    help="serving form: 12 resident R-MAT graphs, Poisson update stream")
+    ap.add_argument("--serve-requests", type=int, default=96)
+    ap.add_argument("--serve-load", type=float, default=0.9,
+                    help="arrival rate as a fraction of one-at-a-time FP64 capacity")
+    ap.add_argument("--serve-scales", default="16,18,20,22")
+    ap.add_argument("--serve-slots", type=int, default=8)
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build runs the whole update on a "
@@ -98,6 +105,9 @@ def main():
     assert torch.cuda.is_available(), "no GPU"
     torch.cuda.set_device(0)
     dfpr.lib()
+    if args.serve:
+        serve_bench(args, dfpr, synth)
+        return
     fracs = [float(x) for x in args.fracs.split(",")]
     workload = f"rmat{args.scale}_ef{args.edge_factor}_df_fp64"
 
@@ -259,6 +269,141 @@ def cpu_baseline(n, src, dst, seq, R0, warm_ranks, args, log):
             "sample": f"Dynamic Frontier (mark + iterate) on the first {used} batches of the "
                       f"same sequence and graph, {spent:.1f}s of CPU time",
             "gpu_vs_oracle_linf": linf}
+
+
+def serve_bench(args, dfpr, synth):
+    """Serving form: resident R-MAT graphs of scales 16..22 (three seeds
+    each), update batches of log-uniform size in [1e-7, 1e-3] |E| for a
+    uniformly chosen graph, FP32 storage on one graph of every scale.
+    Two request sets run one after the other on two copies of the graphs:
+    a closed-loop set (all requests at t = 0; saturation throughput) and an
+    open-loop set with Poisson arrivals at --serve-load of the one-at-a-time
+    capacity (latency).  The comparator serves every request alone, in
+    arrival order, with plain FP64 Dynamic Frontier; its latencies follow
+    from the measured service times on a FIFO timeline."""
+    scales = [int(x) for x in args.serve_scales.split(",")]
+    graphs = []                      # (name, n, src, dst, precision)
+    t = time.time()
+    for sc in scales:
+        for k in range(3):
+            n, s_, d_ = synth.rmat(sc, 16, seed=100 + 10 * sc + k)
+            graphs.append((f"rmat{sc}s{k}", n, s_, d_, dfpr.FP32_KAHAN if k == 1 else dfpr.FP64))
+    log(f"generated {len(graphs)} graphs ({time.time() - t:.1f}s)")
+    G = len(graphs)
+    rng = synth.rng_for(7)
+    nreq = args.serve_requests
+
+    def request_set(tag):
+        gid = rng.integers(0, G, size=nreq)
+        u = rng.random(nreq)
+        gaps = rng.exponential(1.0, size=nreq)
+        fr = np.exp(np.log(1e-7) + u * (np.log(1e-3) - np.log(1e-7)))
+        return {"tag": tag, "gid": gid, "frac": fr, "gaps": gaps}
+
+    sets = [request_set("closed"), request_set("open")]
+    # per graph: the batches of both sets, in order, as one disjoint sequence
+    batches = {}
+    for gi, (name, n, s_, d_, prec) in enumerate(graphs):
+        m = s_.size + n
+        order = [(si, k) for si, rs in enumerate(sets) for k in range(nreq) if rs["gid"][k] == gi]
+        counts = [synth.batch_counts(sets[si]["frac"][k], m) for si, k in order]
+        seq = synth.batch_sequence(s_, d_, n, counts, seed=200 + gi)
+        for (si, k), b in zip(order, seq):
+            batches[(si, k)] = b
+
+    pdef = dfpr.params(frontier_tol=args.frontier_tol)
+    pg = [dfpr.params(frontier_tol=args.frontier_tol, precision=gr[4]) for gr in graphs]
+    t = time.time()
+    base = [dfpr.Graph(gr[1], gr[2], gr[3]) for gr in graphs]
+    mine = [dfpr.Graph(gr[1], gr[2], gr[3]) for gr in graphs]
+    for g in base + mine:
+        g.static(pdef, out=False)
+    log(f"loaded and solved 2 x {G} graphs ({time.time() - t:.1f}s)")
+
+    def one_at_a_time(si):
+        svc = []
+        for k in range(nreq):
+            g = base[sets[si]["gid"][k]]
+            b = batches[(si, k)]
+            ts = time.perf_counter()
+            g.apply_batch(b)
+            g.dynamic_frontier(b, p=pdef, out=False)
+            svc.append((time.perf_counter() - ts) * 1e3)
+        return svc
+
+    def serve(si, arrivals):
+        srv = dfpr.Server(max_slots=args.serve_slots, hbm_budget_bytes=200 << 30)
+        ids = [srv.add_graph(g, p) for g, p in zip(mine, pg)]
+        rids = [srv.submit(ids[sets[si]["gid"][k]], arrivals[k], batches[(si, k)])
+                for k in range(nreq)]
+        st = srv.run()
+        res = [srv.result(r) for r in rids]
+        srv.close()
+        return st, res
+
+    def fifo(arrivals, svc):
+        done, lat, t_free = [], [], 0.0
+        for a, s_ in zip(arrivals, svc):
+            t_free = max(t_free, a) + s_
+            lat.append(t_free - a)
+        return lat, t_free
+
+    out = {"metric": "serving: update latency p50/p99 and updates/s", "n_gpus": 1,
+           "data": "synthetic", "dtype": "f64+f32-storage",
+           "config": {"workload": "serving_rmat" + "_".join(map(str, scales)) + "_x3",
+                      "graphs": [gr[0] for gr in graphs],
+                      "fp32_graphs": [gr[0] for gr in graphs if gr[4] == dfpr.FP32_KAHAN],
+                      "requests_per_set": nreq, "batch_frac_range": [1e-7, 1e-3],
+                      "slots": args.serve_slots, "frontier_tol": args.frontier_tol}}
+    # closed loop: everything at t = 0
+    svc0 = one_at_a_time(0)
+    cap = nreq / (sum(svc0) / 1e3)
+    st0, res0 = serve(0, [0.0] * nreq)
+    log(f"closed loop: one-at-a-time {cap:.1f} updates/s, served {st0['updates_per_s']:.1f} "
+        f"updates/s, max active {st0['max_active']}, steps {st0['steps']}")
+    out["closed_loop"] = {"one_at_a_time_updates_per_s": round(cap, 2),
+                          "served_updates_per_s": round(st0["updates_per_s"], 2),
+                          "speedup": round(st0["updates_per_s"] / cap, 3),
+                          "served_max_active": st0["max_active"], "served_steps": st0["steps"]}
+    # open loop: Poisson arrivals at a fraction of the one-at-a-time capacity
+    rate = args.serve_load * cap / 1e3                       # per ms
+    arr = list(np.cumsum(sets[1]["gaps"]) / rate)
+    arr = [a - arr[0] for a in arr]
+    svc1 = one_at_a_time(1)
+    lat_b, end_b = fifo(arr, svc1)
+    st1, res1 = serve(1, arr)
+    lat_s = [r["done_ms"] - r["arrival_ms"] for r in res1]
+    log(f"open loop at {args.serve_load:.2f} load: one-at-a-time p50 {pct(lat_b, 50):.2f} p99 "
+        f"{pct(lat_b, 99):.2f} ms; served p50 {pct(lat_s, 50):.2f} p99 {pct(lat_s, 99):.2f} ms")
+    out["open_loop"] = {
+        "load": args.serve_load, "rate_per_s": round(rate * 1e3, 2),
+        "one_at_a_time": {"p50_ms": round(pct(lat_b, 50), 3), "p99_ms": round(pct(lat_b, 99), 3),
+                          "mean_ms": round(float(np.mean(lat_b)), 3),
+                          "updates_per_s": round(nreq / (end_b / 1e3), 2)},
+        "served": {"p50_ms": round(st1["latency_p50_ms"], 3),
+                   "p99_ms": round(st1["latency_p99_ms"], 3),
+                   "mean_ms": round(st1["latency_mean_ms"], 3),
+                   "queue_p50_ms": round(st1["queue_p50_ms"], 3),
+                   "queue_p99_ms": round(st1["queue_p99_ms"], 3),
+                   "updates_per_s": round(st1["updates_per_s"], 2),
+                   "max_active": st1["max_active"], "steps": st1["steps"]},
+    }
+    # final ranks: FP64 graphs bitwise equal to one-at-a-time, FP32 storage
+    # graphs within the tolerance
+    acc = {}
+    for gi, gr in enumerate(graphs):
+        Ra, Rb = base[gi].ranks(), mine[gi].ranks()
+        acc[gr[0]] = {"precision": "fp32" if gr[4] else "fp64",
+                      "bitwise_equal": bool(np.array_equal(Ra, Rb)),
+                      "linf": float(np.max(np.abs(Ra - Rb))),
+                      "l1": float(np.sum(np.abs(Ra - Rb)))}
+    out["final_ranks_vs_one_at_a_time"] = acc
+    fails = [r for r in res0 + res1 if r["status"] != 0 or not r["converged"]]
+    out["failed_or_unconverged"] = len(fails)
+    out["value"] = round(st0["updates_per_s"], 3)
+    out["unit"] = "updates/s"
+    out["higher_is_better"] = True
+    print(json.dumps(out), flush=True)
 
 
 if __name__ == "__main__":

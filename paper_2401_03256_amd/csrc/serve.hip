@@ -6,13 +6,20 @@
 // one of a few slots when (a) a slot is free, (b) their graph has no update
 // in flight (one writer per graph, Section 3.2) and (c) the HBM budget
 // covers the resident graphs plus the scratch of every admitted request.
-// Admission applies the batch to the graph and runs the initial marking.
-// Every step then runs one iteration of every admitted request in one
-// coalesced launch: the workgroups are split among the slots in proportion
-// to the work each can use, so small and large graphs share the device.
-// After each step a request whose iteration loop ended is retired and its
-// slot is free for the next arrival, so requests join and leave at
-// iteration boundaries rather than waiting for a whole batch to finish.
+// Admission applies the batch to the graph and runs the initial marking on
+// a second stream, while the iterations of the requests already admitted
+// keep running on the first.
+//
+// Every step runs one iteration of every admitted request in one launch:
+// each slot owns a range of workgroups sized for its graph (the class
+// schedule bounds the work of any iteration), the hardware dispatcher
+// spreads the ranges over the chip, and workgroups of a small graph that
+// finish early leave their compute units to the others.  FP64 slots and
+// slots in the FP32 phase of the precision form share the launch.  Steps
+// are enqueued in chunks; the chunk length follows the observed geometric
+// decay of Delta R of the slots (so a slot is retired soon after it
+// converges) and is kept short while requests wait, because requests join
+// and leave at chunk boundaries.
 //
 // Each slot runs exactly the per-row code of the single-graph engine
 // (iter.h) with the same class of every row, so a request's result does not
@@ -29,77 +36,75 @@
 namespace dfpr {
 
 constexpr int kMaxSlots = 8;
+constexpr int kMaxChunk = 32;
 constexpr int64_t kRequestBytesPerEntry = 96;   // device scratch per batch entry
+constexpr double kChunkMsWhileWaiting = 1.0;   // chunk length while requests wait
 
 struct MultiArgs {
     int32_t nslots;
-    uint32_t grid;            // workgroups shared by the slots
-    uint32_t *active_out;     // per slot: workgroups that wrote partials
+    uint32_t f32_mask;                 // slot s is in an FP32 phase
+    uint32_t off[kMaxSlots + 1];       // slot s owns workgroups off[s] .. off[s+1]-1
     IterArgs s[kMaxSlots];
 };
 static_assert(sizeof(MultiArgs) <= 4096, "kernel arguments must fit in 4 KiB");
 
-// Split m.grid workgroups among the slots in proportion to the workgroups
-// each can use; a slot whose loop has ended gets none.  Every workgroup
-// computes the same split.
-template <bool F32>
-__device__ inline void split_grid(const MultiArgs &m, Plan &tmp, uint32_t *start,
-                                  uint32_t *alloc, uint32_t *active)
-{
-    uint32_t demand[kMaxSlots];
-    uint64_t total = 0;
-    for (int s = 0; s < m.nslots; s++) {
-        const IterArgs &a = m.s[s];
-        const Ctl *c = a.ctl;
-        demand[s] = 0;
-        if (c->done || (F32 && c->phase_end)) continue;
-        make_plan(a, c, !c->dense, a.it & 1, tmp);
-        demand[s] = active_blocks(tmp, m.grid);
-        total += demand[s];
-    }
-    uint32_t at = 0;
-    for (int s = 0; s < m.nslots; s++) {
-        uint32_t g = demand[s];
-        if (g && total > m.grid) g = max(1u, (uint32_t)((uint64_t)demand[s] * m.grid / total));
-        start[s] = at;
-        alloc[s] = g;
-        active[s] = 0;
-        if (g) {
-            const IterArgs &a = m.s[s];
-            make_plan(a, a.ctl, !a.ctl->dense, a.it & 1, tmp);
-            active[s] = active_blocks(tmp, g);
-        }
-        at += g;
-    }
-    start[m.nslots] = at;
-}
+struct CtlGather {
+    int32_t n;
+    const Ctl *src[kMaxSlots];
+    Ctl *dst;
+};
+static_assert(sizeof(Ctl) % 4 == 0, "control blocks are copied as words");
 
-template <bool F32>
 __global__ __launch_bounds__(kBlock) void k_iter_multi(MultiArgs m)
 {
     __shared__ IterShared sh;
-    __shared__ uint32_t s_start[kMaxSlots + 1], s_alloc[kMaxSlots], s_active[kMaxSlots];
-    if (threadIdx.x == 0) {
-        split_grid<F32>(m, sh.plan, s_start, s_alloc, s_active);
-        if (blockIdx.x == 0)
-            for (int s = 0; s < m.nslots; s++) m.active_out[s] = s_active[s];
-    }
-    __syncthreads();
-    int slot = -1;
-    for (int s = 0; s < m.nslots; s++)
-        if (blockIdx.x >= s_start[s] && blockIdx.x < s_start[s + 1]) slot = s;
-    if (slot < 0) return;
-    iter_body<true, F32>(m.s[slot], blockIdx.x - s_start[slot], s_alloc[slot], sh);
+    const uint32_t b = blockIdx.x;
+    int s = 0;
+    while (s + 1 < m.nslots && b >= m.off[s + 1]) s++;
+    const uint32_t G = m.off[s + 1] - m.off[s];
+    if ((m.f32_mask >> s) & 1u) iter_body<true, true>(m.s[s], b - m.off[s], G, sh);
+    else iter_body<true, false>(m.s[s], b - m.off[s], G, sh);
 }
 
 // One workgroup per slot.
-template <bool F32>
 __global__ __launch_bounds__(kBlock) void k_final_multi(MultiArgs m)
 {
     __shared__ IterShared sh;
+    __shared__ uint32_t s_active;
     const int s = blockIdx.x;
-    if (s >= m.nslots || m.active_out[s] == 0) return;
-    final_body(m.s[s], m.active_out[s], true, F32, sh);
+    const IterArgs &a = m.s[s];
+    const bool f32 = (m.f32_mask >> s) & 1u;
+    if (a.ctl->done || (f32 && a.ctl->phase_end)) return;
+    if (threadIdx.x == 0) s_active = single_graph_active(a, true, m.off[s + 1] - m.off[s], sh.plan);
+    __syncthreads();
+    final_body(a, s_active, true, f32, sh);
+}
+
+// Copy the control blocks of the slots into one array for one host copy.
+__global__ __launch_bounds__(kBlock) void k_gather_ctl(CtlGather g)
+{
+    constexpr int words = (int)(sizeof(Ctl) / 4);
+    for (int i = threadIdx.x; i < g.n * words; i += kBlock) {
+        const int s = i / words, w = i % words;
+        reinterpret_cast<uint32_t *>(g.dst + s)[w] =
+            reinterpret_cast<const uint32_t *>(g.src[s])[w];
+    }
+}
+
+// Workgroups that can have work in any iteration of a graph whose class
+// schedule has the given offsets: the count of the full schedule, which
+// bounds every frontier.
+static uint32_t blocks_bound(const uint32_t *off, uint32_t grid)
+{
+    uint64_t nwu = 0;
+    for (int b = 0; b < kBins - 1; b++) {
+        const uint64_t rows = kWave / group_of(b);
+        nwu += ((uint64_t)(off[b + 1] - off[b]) + rows - 1) / rows;
+    }
+    const uint64_t nbu = off[kBins] - off[kBins - 1];
+    const uint64_t wblocks = (nwu + kWavesPerBlock - 1) / kWavesPerBlock;
+    return (uint32_t)std::max<uint64_t>(1, std::max(std::min<uint64_t>(grid, nbu),
+                                                    std::min<uint64_t>(grid, wblocks)));
 }
 
 using Clock = std::chrono::steady_clock;
@@ -120,6 +125,10 @@ struct Slot {
     int it0 = 0;              // first iteration of the current phase
     int base = 0;             // buffer the current phase started on
     int it = 0;               // next iteration
+    uint32_t blocks = 1;      // workgroups in a coalesced launch
+    double prev_dr = -1.0;    // Delta R and iteration count at the last look
+    int prev_it = 0;
+    int pred = 4;             // predicted iterations left in the phase
 };
 
 struct GraphEntry {
@@ -157,9 +166,11 @@ struct dfpr_server {
     int64_t resident = 0;
     std::vector<dfpr::GraphEntry> graphs;
     std::vector<dfpr::Request> reqs;
-    hipStream_t stream = nullptr;
-    uint32_t *active_dev = nullptr;   // 2 x kMaxSlots
-    int grid = 1024;
+    hipStream_t stream = nullptr;     // iterations, phase ends, finishing
+    hipStream_t astream = nullptr;    // admission: apply + initial marking
+    dfpr::Ctl *ctl_dev = nullptr;     // kMaxSlots gathered control blocks
+    dfpr::Ctl *ctl_pin = nullptr;     // their pinned host copy
+    uint32_t *sched_pin = nullptr;    // class schedule offsets of an admitted graph
 };
 
 using namespace dfpr;
@@ -171,7 +182,8 @@ static double ms_since(Clock::time_point t0)
     return std::chrono::duration<double, std::milli>(Clock::now() - t0).count();
 }
 
-// Admit request r into slot sl: apply the batch, then begin the update.
+// Admit request r into slot sl on the admission stream: apply the batch,
+// then begin the update; returns when both are done on the device.
 static int admit(dfpr_server *srv, int64_t r, Slot &sl, double now_ms)
 {
     Request &q = srv->reqs[r];
@@ -179,61 +191,100 @@ static int admit(dfpr_server *srv, int64_t r, Slot &sl, double now_ms)
     dfpr_graph *g = ge.g;
     q.state = 1;
     q.res.admit_ms = now_ms;
-    int64_t applied[2] = {0, 0};
-    const int64_t nd = (int64_t)q.ds.size(), ni = (int64_t)q.is.size();
-    int rc = apply_batch_impl(g, nd, q.ds.data(), q.dd.data(), ni, q.is.data(), q.id.data(), 0,
+    g->stream = srv->astream;
+    int rc = DFPR_OK;
+    do {
+        int64_t applied[2] = {0, 0};
+        const int64_t nd = (int64_t)q.ds.size(), ni = (int64_t)q.is.size();
+        rc = apply_batch_impl(g, nd, q.ds.data(), q.dd.data(), ni, q.is.data(), q.id.data(), 0,
                               applied);
-    if (rc) return rc;
-    q.res.applied[0] = applied[0];
-    q.res.applied[1] = applied[1];
-    const int32_t *bds, *bdd, *bis, *bid;
-    rc = stage_batch(g, nd, q.ds.data(), q.dd.data(), ni, q.is.data(), q.id.data(), &bds, &bdd,
-                     &bis, &bid);
-    if (rc) return rc;
-    uint32_t sbase = 0;
-    rc = df_begin(g, ge.p, nd, bds, bdd, ni, bis, bid, nullptr, 0, &sbase);
-    if (rc) return rc;
-    sl.req = r;
-    sl.sbase = sbase;
-    sl.phase32 = ge.p.precision == DFPR_FP32_KAHAN ? 1 : 0;
-    sl.it0 = 0;
-    sl.base = g->cur;
-    sl.it = 0;
+        if (rc) break;
+        q.res.applied[0] = applied[0];
+        q.res.applied[1] = applied[1];
+        const int32_t *bds, *bdd, *bis, *bid;
+        rc = stage_batch(g, nd, q.ds.data(), q.dd.data(), ni, q.is.data(), q.id.data(), &bds,
+                         &bdd, &bis, &bid);
+        if (rc) break;
+        uint32_t sbase = 0;
+        rc = df_begin(g, ge.p, nd, bds, bdd, ni, bis, bid, nullptr, 0, &sbase);
+        if (rc) break;
+        if (hipMemcpyAsync(srv->sched_pin, g->sched_off, (kBins + 1) * sizeof(uint32_t),
+                           hipMemcpyDeviceToHost, srv->astream) != hipSuccess ||
+            hipStreamSynchronize(srv->astream) != hipSuccess) {
+            rc = set_error(DFPR_E_DEVICE, "admission failed on the device");
+            break;
+        }
+        sl = Slot();
+        sl.req = r;
+        sl.sbase = sbase;
+        sl.phase32 = ge.p.precision == DFPR_FP32_KAHAN ? 1 : 0;
+        sl.base = g->cur;
+        sl.blocks = blocks_bound(srv->sched_pin, (uint32_t)g->grid);
+    } while (0);
+    g->stream = srv->stream;
+    return rc;
+}
+
+// Enqueue K coalesced steps of the slots in the chunk, then one copy of
+// their control blocks to the host.
+static int launch_chunk(dfpr_server *srv, std::vector<Slot *> &cs, int K)
+{
+    MultiArgs m{};
+    m.nslots = (int32_t)cs.size();
+    uint32_t at = 0;
+    for (int i = 0; i < m.nslots; i++) {
+        m.off[i] = at;
+        at += cs[i]->blocks;
+        if (cs[i]->phase32) m.f32_mask |= 1u << i;
+    }
+    m.off[m.nslots] = at;
+    for (int j = 0; j < K; j++) {
+        for (int i = 0; i < m.nslots; i++) {
+            Slot &sl = *cs[i];
+            const Request &q = srv->reqs[sl.req];
+            GraphEntry &ge = srv->graphs[q.gid];
+            dfpr_graph *g = ge.g;
+            IterArgs a = iter_args(g, ge.p, sl.sbase);
+            const int it = sl.it + j;
+            const int src = sl.base ^ ((it - sl.it0) & 1);
+            a.Rc = g->R[src];
+            a.Cc = g->C[src];
+            a.Rn = g->R[src ^ 1];
+            a.Cn = g->C[src ^ 1];
+            a.C32c = g->C32[src];
+            a.C32n = g->C32[src ^ 1];
+            a.it = it;
+            m.s[i] = a;
+        }
+        k_iter_multi<<<at, kBlock, 0, srv->stream>>>(m);
+        k_final_multi<<<m.nslots, kBlock, 0, srv->stream>>>(m);
+    }
+    CtlGather cg{};
+    cg.n = m.nslots;
+    for (int i = 0; i < m.nslots; i++) cg.src[i] = srv->graphs[srv->reqs[cs[i]->req].gid].g->ctl;
+    cg.dst = srv->ctl_dev;
+    k_gather_ctl<<<1, kBlock, 0, srv->stream>>>(cg);
+    DFPR_HIP(hipGetLastError());
+    DFPR_HIP(hipMemcpyAsync(srv->ctl_pin, srv->ctl_dev, m.nslots * sizeof(Ctl),
+                            hipMemcpyDeviceToHost, srv->stream));
     return DFPR_OK;
 }
 
-// One coalesced iteration of every slot in the given phase.
-static int launch_group(dfpr_server *srv, std::vector<Slot> &slots, bool f32)
+// Predicted iterations left in a slot's phase, from the geometric decay of
+// Delta R between two looks.
+static void predict(Slot &sl, const Ctl &c, double tol)
 {
-    MultiArgs m{};
-    m.grid = (uint32_t)srv->grid;
-    m.active_out = srv->active_dev + (f32 ? kMaxSlots : 0);
-    for (Slot &sl : slots) {
-        if (sl.req < 0 || (sl.phase32 != 0) != f32) continue;
-        const Request &q = srv->reqs[sl.req];
-        GraphEntry &ge = srv->graphs[q.gid];
-        dfpr_graph *g = ge.g;
-        IterArgs a = iter_args(g, ge.p, sl.sbase);
-        const int src = sl.base ^ ((sl.it - sl.it0) & 1);
-        a.Rc = g->R[src];
-        a.Cc = g->C[src];
-        a.Rn = g->R[src ^ 1];
-        a.Cn = g->C[src ^ 1];
-        a.C32c = g->C32[src];
-        a.C32n = g->C32[src ^ 1];
-        a.it = sl.it;
-        m.s[m.nslots++] = a;
+    const double dr = c.final_linf;
+    const int its = c.iterations;
+    int next = std::min(sl.pred * 2, kMaxChunk);
+    if (sl.prev_dr > 0.0 && dr > 0.0 && dr < sl.prev_dr && its > sl.prev_it && tol > 0.0) {
+        const double rate = std::pow(dr / sl.prev_dr, 1.0 / (its - sl.prev_it));
+        const double need = std::ceil(std::log(tol / dr) / std::log(rate));
+        if (std::isfinite(need)) next = (int)std::min<double>(kMaxChunk, std::max(1.0, need));
     }
-    if (!m.nslots) return DFPR_OK;
-    if (f32) {
-        k_iter_multi<true><<<m.grid + kMaxSlots, kBlock, 0, srv->stream>>>(m);
-        k_final_multi<true><<<m.nslots, kBlock, 0, srv->stream>>>(m);
-    } else {
-        k_iter_multi<false><<<m.grid + kMaxSlots, kBlock, 0, srv->stream>>>(m);
-        k_final_multi<false><<<m.nslots, kBlock, 0, srv->stream>>>(m);
-    }
-    DFPR_HIP(hipGetLastError());
-    return DFPR_OK;
+    sl.prev_dr = dr;
+    sl.prev_it = its;
+    sl.pred = next;
 }
 
 static int run(dfpr_server *srv, dfpr_server_stats *st)
@@ -245,7 +296,7 @@ static int run(dfpr_server *srv, dfpr_server_stats *st)
         return srv->reqs[a].arrival_ms < srv->reqs[b].arrival_ms;
     });
     // work already queued on a graph's own stream comes first; the server
-    // stream carries every graph while it runs and the graphs get their
+    // streams carry every graph while it runs and the graphs get their
     // streams back at the end
     std::vector<hipStream_t> saved(srv->graphs.size());
     for (size_t i = 0; i < srv->graphs.size(); i++) {
@@ -262,47 +313,72 @@ static int run(dfpr_server *srv, dfpr_server_stats *st)
     size_t next = 0;              // first request of `order` not yet admitted
     int64_t done = 0, failed = 0;
     int32_t steps = 0, max_active = 0;
+    double step_ms = 0.0;         // recent wall time of one step
     const Clock::time_point t0 = Clock::now();
     double last_done = 0.0;
     int rc = DFPR_OK;
     while (done + failed < pending) {
-        // admission in arrival order; a request whose graph is busy waits
-        // without blocking later ones; the budget is first come, first served
-        double now = ms_since(t0);
-        for (size_t k = next; k < order.size(); k++) {
-            Request &q = srv->reqs[order[k]];
-            if (q.state != 0) continue;
-            if (q.arrival_ms > now) break;
-            auto free_slot = std::find_if(slots.begin(), slots.end(),
-                                          [](const Slot &s) { return s.req < 0; });
-            if (free_slot == slots.end()) break;
-            if (srv->graphs[q.gid].busy) continue;
-            if (srv->resident + in_flight + q.charge > srv->budget) break;
-            srv->graphs[q.gid].busy = 1;
-            in_flight += q.charge;
-            peak = std::max(peak, srv->resident + in_flight);
-            int arc = admit(srv, order[k], *free_slot, now);
-            if (arc) {
-                // a rejected batch leaves its graph unchanged
-                q.state = 2;
-                q.res.status = arc;
-                q.res.done_ms = ms_since(t0);
-                free_slot->req = -1;
-                srv->graphs[q.gid].busy = 0;
-                in_flight -= q.charge;
-                failed++;
-                if (arc != DFPR_E_RANGE) {
-                    rc = arc;
-                    goto out;
-                }
-            }
-            now = ms_since(t0);
+        // 1. launch a chunk of steps for the admitted requests
+        std::vector<Slot *> cs;
+        for (Slot &s : slots)
+            if (s.req >= 0) cs.push_back(&s);
+        int K = 0;
+        Clock::time_point tc = Clock::now();
+        if (!cs.empty()) {
+            K = kMaxChunk;
+            for (Slot *s : cs) K = std::min(K, s->pred);
+            // requests join at chunk boundaries: keep chunks short while
+            // a slot is free and requests are still to come
+            while (next < order.size() && srv->reqs[order[next]].state != 0) next++;
+            if (next < order.size() && (int)cs.size() < srv->max_slots && step_ms > 0.0)
+                K = std::min(K, std::max(1, (int)(kChunkMsWhileWaiting / step_ms)));
+            K = std::max(K, 1);
+            rc = launch_chunk(srv, cs, K);
+            if (rc) goto out;
+            steps += K;
+            max_active = std::max(max_active, (int32_t)cs.size());
         }
-        while (next < order.size() && srv->reqs[order[next]].state != 0) next++;
-        int active = 0;
-        for (const Slot &s : slots) active += s.req >= 0;
-        if (!active) {
-            if (next < order.size()) {
+        // 2. admission in arrival order, overlapping the chunk; a request
+        // whose graph is busy waits without blocking later ones; the budget
+        // is first come, first served
+        int admitted = 0;
+        {
+            double now = ms_since(t0);
+            for (size_t k = next; k < order.size(); k++) {
+                Request &q = srv->reqs[order[k]];
+                if (q.state != 0) continue;
+                if (q.arrival_ms > now) break;
+                auto free_slot = std::find_if(slots.begin(), slots.end(),
+                                              [](const Slot &s) { return s.req < 0; });
+                if (free_slot == slots.end()) break;
+                if (srv->graphs[q.gid].busy) continue;
+                if (srv->resident + in_flight + q.charge > srv->budget) break;
+                srv->graphs[q.gid].busy = 1;
+                in_flight += q.charge;
+                peak = std::max(peak, srv->resident + in_flight);
+                const int arc = admit(srv, order[k], *free_slot, now);
+                if (arc) {
+                    // a rejected batch leaves its graph unchanged
+                    q.state = 2;
+                    q.res.status = arc;
+                    q.res.done_ms = ms_since(t0);
+                    free_slot->req = -1;
+                    srv->graphs[q.gid].busy = 0;
+                    in_flight -= q.charge;
+                    failed++;
+                    if (arc != DFPR_E_RANGE) {
+                        rc = arc;
+                        goto out;
+                    }
+                } else {
+                    admitted++;
+                }
+                now = ms_since(t0);
+            }
+        }
+        if (cs.empty()) {
+            while (next < order.size() && srv->reqs[order[next]].state != 0) next++;
+            if (!admitted && next < order.size()) {
                 const double wait = srv->reqs[order[next]].arrival_ms - ms_since(t0);
                 if (wait > 0.05)
                     std::this_thread::sleep_for(std::chrono::duration<double, std::milli>(
@@ -310,38 +386,30 @@ static int run(dfpr_server *srv, dfpr_server_stats *st)
             }
             continue;
         }
-        max_active = std::max(max_active, active);
-        // one iteration of every admitted request
-        rc = launch_group(srv, slots, false);
-        if (!rc) rc = launch_group(srv, slots, true);
-        if (rc) goto out;
-        steps++;
-        for (const Slot &s : slots) {
-            if (s.req < 0) continue;
-            dfpr_graph *g = srv->graphs[srv->reqs[s.req].gid].g;
-            if (hipMemcpyAsync(g->ctl_host, g->ctl, sizeof(Ctl), hipMemcpyDeviceToHost,
-                               srv->stream) != hipSuccess) {
-                rc = set_error(DFPR_E_DEVICE, "control block copy failed");
-                goto out;
-            }
-        }
+        // 3. the chunk's results
         if (hipStreamSynchronize(srv->stream) != hipSuccess) {
             rc = set_error(DFPR_E_DEVICE, "stream synchronisation failed");
             goto out;
         }
-        bool finishing = false;
-        for (Slot &s : slots) {
-            if (s.req < 0) continue;
+        {
+            const double chunk_ms =
+                std::chrono::duration<double, std::milli>(Clock::now() - tc).count();
+            const double per = chunk_ms / K;
+            step_ms = step_ms > 0.0 ? 0.5 * step_ms + 0.5 * per : per;
+        }
+        std::vector<Slot *> fin;
+        for (size_t i = 0; i < cs.size(); i++) {
+            Slot &s = *cs[i];
             Request &q = srv->reqs[s.req];
             GraphEntry &ge = srv->graphs[q.gid];
             dfpr_graph *g = ge.g;
-            const Ctl c = *g->ctl_host;
+            const Ctl c = srv->ctl_pin[i];
+            *g->ctl_host = c;
             s.it = c.iterations;
             const int res = s.base ^ ((c.iterations - s.it0) & 1);
             if (c.err) {
                 q.res.status = DFPR_E_RANGE;
-                q.state = 3;       // retire without results
-                finishing = true;
+                fin.push_back(&s);
                 continue;
             }
             if (s.phase32 && (c.phase_end || c.done)) {
@@ -351,6 +419,8 @@ static int run(dfpr_server *srv, dfpr_server_stats *st)
                     s.phase32 = 0;
                     s.it0 = c.iterations;
                     s.base = res;
+                    s.prev_dr = -1.0;
+                    s.pred = 2;
                     q.res.refine_sweeps = -c.iterations;   // completed at retirement
                     continue;
                 }
@@ -358,26 +428,32 @@ static int run(dfpr_server *srv, dfpr_server_stats *st)
             if (c.done) {
                 rc = df_finish(g, s.sbase, res, c.iterations);
                 if (rc) goto out;
-                if (hipMemcpyAsync(g->ctl_host, g->ctl, sizeof(Ctl), hipMemcpyDeviceToHost,
-                                   srv->stream) != hipSuccess) {
-                    rc = set_error(DFPR_E_DEVICE, "control block copy failed");
-                    goto out;
-                }
-                q.state = 3;
-                finishing = true;
+                fin.push_back(&s);
+                continue;
             }
+            predict(s, c, ge.p.tol);
         }
-        if (finishing) {
-            if (hipStreamSynchronize(srv->stream) != hipSuccess) {
-                rc = set_error(DFPR_E_DEVICE, "stream synchronisation failed");
+        if (!fin.empty()) {
+            CtlGather cg{};
+            cg.n = (int32_t)fin.size();
+            for (size_t i = 0; i < fin.size(); i++)
+                cg.src[i] = srv->graphs[srv->reqs[fin[i]->req].gid].g->ctl;
+            cg.dst = srv->ctl_dev;
+            k_gather_ctl<<<1, kBlock, 0, srv->stream>>>(cg);
+            if (hipGetLastError() != hipSuccess ||
+                hipMemcpyAsync(srv->ctl_pin, srv->ctl_dev, fin.size() * sizeof(Ctl),
+                               hipMemcpyDeviceToHost, srv->stream) != hipSuccess ||
+                hipStreamSynchronize(srv->stream) != hipSuccess) {
+                rc = set_error(DFPR_E_DEVICE, "finishing failed on the device");
                 goto out;
             }
             const double t = ms_since(t0);
-            for (Slot &s : slots) {
-                if (s.req < 0 || srv->reqs[s.req].state != 3) continue;
+            for (size_t i = 0; i < fin.size(); i++) {
+                Slot &s = *fin[i];
                 Request &q = srv->reqs[s.req];
                 GraphEntry &ge = srv->graphs[q.gid];
-                const Ctl &c = *ge.g->ctl_host;
+                const Ctl &c = srv->ctl_pin[i];
+                *ge.g->ctl_host = c;
                 q.state = 2;
                 q.res.done_ms = t;
                 if (q.res.status == DFPR_OK) {
@@ -395,12 +471,15 @@ static int run(dfpr_server *srv, dfpr_server_stats *st)
                 last_done = t;
                 ge.busy = 0;
                 in_flight -= q.charge;
-                s.req = -1;
+                s = Slot();
             }
         }
     }
 out:
-    if (rc) (void)hipStreamSynchronize(srv->stream);
+    if (rc) {
+        (void)hipStreamSynchronize(srv->stream);
+        (void)hipStreamSynchronize(srv->astream);
+    }
     for (size_t i = 0; i < srv->graphs.size(); i++) srv->graphs[i].g->stream = saved[i];
     if (rc) return rc;
     if (st) {
@@ -443,14 +522,14 @@ int dfpr_server_create(int32_t max_slots, int64_t hbm_budget_bytes, dfpr_server 
     s->max_slots = max_slots;
     s->budget = hbm_budget_bytes;
     hipError_t e = hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking);
-    if (e == hipSuccess) e = hipMalloc(&s->active_dev, 2 * kMaxSlots * sizeof(uint32_t));
+    if (e == hipSuccess) e = hipStreamCreateWithFlags(&s->astream, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipMalloc(&s->ctl_dev, kMaxSlots * sizeof(Ctl));
+    if (e == hipSuccess) e = hipHostMalloc(&s->ctl_pin, kMaxSlots * sizeof(Ctl));
+    if (e == hipSuccess) e = hipHostMalloc(&s->sched_pin, (kBins + 1) * sizeof(uint32_t));
     if (e != hipSuccess) {
         dfpr_server_free(s);
         return hip_fail(e, "server set-up");
     }
-    hipDeviceProp_t prop;
-    if (hipGetDeviceProperties(&prop, 0) == hipSuccess && prop.multiProcessorCount > 0)
-        s->grid = std::min(kMaxGrid - kMaxSlots, prop.multiProcessorCount * 8);
     *out = s;
     return DFPR_OK;
 }
@@ -458,11 +537,14 @@ int dfpr_server_create(int32_t max_slots, int64_t hbm_budget_bytes, dfpr_server 
 void dfpr_server_free(dfpr_server *s)
 {
     if (!s) return;
-    if (s->stream) {
-        (void)hipStreamSynchronize(s->stream);
-        (void)hipStreamDestroy(s->stream);
-    }
-    (void)hipFree(s->active_dev);
+    for (hipStream_t st : {s->stream, s->astream})
+        if (st) {
+            (void)hipStreamSynchronize(st);
+            (void)hipStreamDestroy(st);
+        }
+    (void)hipFree(s->ctl_dev);
+    (void)hipHostFree(s->ctl_pin);
+    (void)hipHostFree(s->sched_pin);
     delete s;
 }
 
