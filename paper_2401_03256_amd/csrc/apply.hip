@@ -517,9 +517,12 @@ static inline unsigned grid_for(uint64_t items, unsigned per = kBlock)
     return (unsigned)std::max<uint64_t>(1, (items + per - 1) / per);
 }
 
+// Copy a batch (host or device arrays) into the graph's staging buffer in
+// internal ids; ids outside [0, n) become -1 and are rejected later.
 int stage_batch(dfpr_graph *g, int64_t n_del, const int32_t *ds, const int32_t *dd,
-                int64_t n_ins, const int32_t *is, const int32_t *id, const int32_t **dds,
-                const int32_t **ddd, const int32_t **dis, const int32_t **did)
+                int64_t n_ins, const int32_t *is, const int32_t *id, int on_device,
+                const int32_t **dds, const int32_t **ddd, const int32_t **dis,
+                const int32_t **did)
 {
     ApplyBufs &ap = g->ap;
     const uint64_t need = 2 * (uint64_t)(n_del + n_ins);
@@ -531,19 +534,24 @@ int stage_batch(dfpr_graph *g, int64_t n_del, const int32_t *ds, const int32_t *
         ap.batch_cap = cap;
     }
     int32_t *p = ap.batch_dev;
-    *dds = p;
-    *ddd = p + n_del;
-    *dis = p + 2 * n_del;
-    *did = p + 2 * n_del + n_ins;
+    int32_t *dst[4] = {p, p + n_del, p + 2 * n_del, p + 2 * n_del + n_ins};
+    const int32_t *src[4] = {ds, dd, is, id};
+    const int64_t len[4] = {n_del, n_del, n_ins, n_ins};
     hipStream_t s = g->stream;
-    if (n_del) {
-        DFPR_HIP(hipMemcpyAsync(p, ds, n_del * 4, hipMemcpyHostToDevice, s));
-        DFPR_HIP(hipMemcpyAsync(p + n_del, dd, n_del * 4, hipMemcpyHostToDevice, s));
+    for (int k = 0; k < 4; k++) {
+        if (!len[k]) continue;
+        const int32_t *from = src[k];
+        if (!on_device) {
+            DFPR_HIP(hipMemcpyAsync(dst[k], src[k], len[k] * 4, hipMemcpyHostToDevice, s));
+            from = dst[k];
+        }
+        const int rc = map_ids(g, from, dst[k], len[k]);
+        if (rc) return rc;
     }
-    if (n_ins) {
-        DFPR_HIP(hipMemcpyAsync(p + 2 * n_del, is, n_ins * 4, hipMemcpyHostToDevice, s));
-        DFPR_HIP(hipMemcpyAsync(p + 2 * n_del + n_ins, id, n_ins * 4, hipMemcpyHostToDevice, s));
-    }
+    *dds = dst[0];
+    *ddd = dst[1];
+    *dis = dst[2];
+    *did = dst[3];
     return DFPR_OK;
 }
 
@@ -640,10 +648,8 @@ int apply_batch_impl(dfpr_graph *g, int64_t n_del, const int32_t *ds, const int3
     if (!rc) rc = ensure_slab(g);
     if (rc) return rc;
     hipStream_t s = g->stream;
-    if (!on_device) {
-        rc = stage_batch(g, n_del, ds, dd, n_ins, is, id, &ds, &dd, &is, &id);
-        if (rc) return rc;
-    }
+    rc = stage_batch(g, n_del, ds, dd, n_ins, is, id, on_device, &ds, &dd, &is, &id);
+    if (rc) return rc;
     ApplyArgs a = apply_args(g);
     a.nd = n_del;
     a.ni = n_ins;

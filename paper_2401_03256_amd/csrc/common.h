@@ -5,6 +5,7 @@
 
 #include <cstdint>
 #include <string>
+#include <vector>
 
 #include "dfpr.h"
 
@@ -103,9 +104,18 @@ struct ApplyBufs {
 
 }  // namespace dfpr
 
+// Vertices are renumbered at load: internal ids follow decreasing in-degree
+// (ties by the caller's id), so that the rows of one in-degree class form a
+// contiguous id range and high-degree sources share cache lines.  Every id,
+// rank and flag that crosses the C-ABI is in the caller's numbering.
 struct dfpr_graph {
     int32_t n = 0;
     int64_t m = 0;                    // live edges, self-loops included
+    int32_t *ext2int = nullptr;       // device: caller id -> internal id
+    int32_t *int2ext = nullptr;       // device: internal id -> caller id
+    std::vector<int32_t> ext2int_h;   // host copies of the two maps
+    std::vector<int32_t> int2ext_h;
+    double *Rx = nullptr;             // n ranks in the caller's numbering (staging)
     dfpr::Csr csr[2];                 // [0] = in (rows = dst), [1] = out (rows = src)
     double *R[2] = {};                // rank double buffer
     double *C[2] = {};                // contribution R[v] / |out(v)|
@@ -154,10 +164,15 @@ int apply_batch_impl(dfpr_graph *g, int64_t n_del, const int32_t *ds, const int3
                      int64_t n_ins, const int32_t *is, const int32_t *id, int on_device,
                      int64_t applied[2]);
 int stage_batch(dfpr_graph *g, int64_t n_del, const int32_t *ds, const int32_t *dd,
-                int64_t n_ins, const int32_t *is, const int32_t *id,
+                int64_t n_ins, const int32_t *is, const int32_t *id, int on_device,
                 const int32_t **dds, const int32_t **ddd, const int32_t **dis,
                 const int32_t **did);
 int check_ids_host(int32_t n, int64_t len, const int32_t *a, const int32_t *b);
+
+// renumbering at the boundary (graph.hip); enqueued on g->stream
+int map_ids(dfpr_graph *g, const int32_t *in, int32_t *out, int64_t len);
+int ranks_to_caller(const dfpr_graph *g, const double *Rint, double *out, int out_dev);
+int ranks_from_caller(const dfpr_graph *g, const double *in, int in_dev, double *Rint);
 
 // device helpers (rank.hip)
 int launch_fill_u32(dfpr_graph *g, uint32_t *p, uint64_t len, uint32_t value);

@@ -4,7 +4,10 @@
 //   csr[0] (in-edges)  : row v lists G.in(v), used by the pull of Eq. 1;
 //   csr[1] (out-edges) : row u lists G.out(u); its live count is |out(u)|.
 // Loading (not timed by the paper, Section 5.1.5) is done on the host with
-// counting sorts and then copied up once.
+// counting sorts and then copied up once.  Vertices get internal ids in
+// order of decreasing in-degree (stable in the caller's ids); the maps
+// between the two numberings are applied wherever ids or per-vertex values
+// cross the C-ABI.
 #include <algorithm>
 #include <cstring>
 #include <vector>
@@ -99,6 +102,87 @@ static void free_csr(Csr &c)
     c = Csr{};
 }
 
+// Internal numbering: decreasing in-degree counted over the input edges
+// (repeats and self-loops included, which only affects ties), ties kept in
+// the caller's order.  A counting sort by degree.
+static void renumber(int32_t n, int64_t m, const int32_t *src, const int32_t *dst,
+                     std::vector<int32_t> &ext2int, std::vector<int32_t> &int2ext)
+{
+    std::vector<uint32_t> deg(n, 1);
+    uint32_t dmax = 1;
+    for (int64_t i = 0; i < m; i++) dmax = std::max(dmax, ++deg[dst[i]]);
+    std::vector<uint64_t> start(dmax + 2, 0);
+    for (int32_t v = 0; v < n; v++) start[dmax - deg[v] + 1]++;
+    for (uint32_t d = 0; d <= dmax; d++) start[d + 1] += start[d];
+    ext2int.assign(n, 0);
+    int2ext.assign(n, 0);
+    for (int32_t v = 0; v < n; v++) {
+        const int32_t i = (int32_t)start[dmax - deg[v]]++;
+        ext2int[v] = i;
+        int2ext[i] = v;
+    }
+}
+
+__global__ void k_map_ids(int32_t n, const int32_t *ext2int, const int32_t *in, int32_t *out,
+                          int64_t len)
+{
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= len) return;
+    const int32_t x = in[i];
+    out[i] = (x >= 0 && x < n) ? ext2int[x] : -1;
+}
+
+// out[v] = Rint[ext2int[v]]: caller order from internal order
+__global__ void k_to_caller(int32_t n, const int32_t *ext2int, const double *Rint, double *out)
+{
+    const int32_t v = blockIdx.x * blockDim.x + threadIdx.x;
+    if (v < n) out[v] = Rint[ext2int[v]];
+}
+
+// Rint[i] = in[int2ext[i]]: internal order from caller order
+__global__ void k_from_caller(int32_t n, const int32_t *int2ext, const double *in, double *Rint)
+{
+    const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) Rint[i] = in[int2ext[i]];
+}
+
+static inline unsigned grid_of(int64_t items)
+{
+    return (unsigned)std::max<int64_t>(1, (items + kBlock - 1) / kBlock);
+}
+
+// Ids outside [0, n) become -1, which every later check rejects.  `in` may
+// equal `out`.
+int map_ids(dfpr_graph *g, const int32_t *in, int32_t *out, int64_t len)
+{
+    if (len <= 0) return DFPR_OK;
+    k_map_ids<<<grid_of(len), kBlock, 0, g->stream>>>(g->n, g->ext2int, in, out, len);
+    DFPR_HIP(hipGetLastError());
+    return DFPR_OK;
+}
+
+int ranks_to_caller(const dfpr_graph *g, const double *Rint, double *out, int out_dev)
+{
+    const int32_t n = g->n;
+    k_to_caller<<<grid_of(n), kBlock, 0, g->stream>>>(n, g->ext2int, Rint, out_dev ? out : g->Rx);
+    DFPR_HIP(hipGetLastError());
+    if (!out_dev)
+        DFPR_HIP(hipMemcpyAsync(out, g->Rx, (size_t)n * 8, hipMemcpyDeviceToHost, g->stream));
+    return DFPR_OK;
+}
+
+int ranks_from_caller(const dfpr_graph *g, const double *in, int in_dev, double *Rint)
+{
+    const int32_t n = g->n;
+    if (!in_dev) {
+        DFPR_HIP(hipMemcpyAsync(g->Rx, in, (size_t)n * 8, hipMemcpyHostToDevice, g->stream));
+        in = g->Rx;
+    }
+    k_from_caller<<<grid_of(n), kBlock, 0, g->stream>>>(n, g->int2ext, in, Rint);
+    DFPR_HIP(hipGetLastError());
+    return DFPR_OK;
+}
+
 static int load_impl(int32_t n, int64_t m, const int32_t *src, const int32_t *dst,
                      dfpr_graph *g, uint32_t top[2])
 {
@@ -179,6 +263,9 @@ void dfpr_free_graph(dfpr_graph *g)
     (void)hipFree(g->sched_tmp);
     (void)hipFree(g->ctl);
     (void)hipFree(g->scratch_sum);
+    (void)hipFree(g->Rx);
+    (void)hipFree(g->ext2int);
+    (void)hipFree(g->int2ext);
     if (g->ctl_host) (void)hipHostFree(g->ctl_host);
     (void)hipFree(g->it.dr_part);
     (void)hipFree(g->it.rmax_part);
@@ -212,7 +299,15 @@ int dfpr_load_graph(int32_t n, int64_t m, const int32_t *src, const int32_t *dst
     dfpr_graph *g = new dfpr_graph();
     g->n = n;
     uint32_t top[2] = {0, 0};
-    rc = load_impl(n, m, src, dst, g, top);
+    renumber(n, m, src, dst, g->ext2int_h, g->int2ext_h);
+    {
+        std::vector<int32_t> s2(m), d2(m);
+        for (int64_t i = 0; i < m; i++) {
+            s2[i] = g->ext2int_h[src[i]];
+            d2[i] = g->ext2int_h[dst[i]];
+        }
+        rc = load_impl(n, m, s2.data(), d2.data(), g, top);
+    }
     if (!rc) {
         auto al = [&](void **p, size_t bytes) -> int {
             hipError_t e = hipMalloc(p, std::max<size_t>(bytes, 4));
@@ -236,6 +331,15 @@ int dfpr_load_graph(int32_t n, int64_t m, const int32_t *src, const int32_t *dst
         if (!rc) rc = al((void **)&g->C32[1], (size_t)n * 4);
         if (!rc) rc = al((void **)&g->it.cnt_part, (size_t)kMaxGrid * kCounters * 8);
         if (!rc) rc = al((void **)&g->scratch_sum, 4096 * 8);
+        if (!rc) rc = al((void **)&g->Rx, nd);
+        if (!rc) rc = al((void **)&g->ext2int, (size_t)n * 4);
+        if (!rc) rc = al((void **)&g->int2ext, (size_t)n * 4);
+        if (!rc && hipMemcpy(g->ext2int, g->ext2int_h.data(), (size_t)n * 4,
+                             hipMemcpyHostToDevice) != hipSuccess)
+            rc = set_error(DFPR_E_DEVICE, "map upload failed");
+        if (!rc && hipMemcpy(g->int2ext, g->int2ext_h.data(), (size_t)n * 4,
+                             hipMemcpyHostToDevice) != hipSuccess)
+            rc = set_error(DFPR_E_DEVICE, "map upload failed");
     }
     if (!rc) {
         hipError_t e = hipHostMalloc((void **)&g->ctl_host, sizeof(Ctl), hipHostMallocDefault);
@@ -308,12 +412,15 @@ int dfpr_export_csr(const dfpr_graph *g, int out_orientation, int64_t *offsets, 
     DFPR_HIP(hipMemcpy(beg.data(), c.beg, (size_t)n * 4, hipMemcpyDeviceToHost));
     DFPR_HIP(hipMemcpy(cnt.data(), c.cnt, (size_t)n * 4, hipMemcpyDeviceToHost));
     DFPR_HIP(hipMemcpy(slots.data(), c.idx, c.slots * 4, hipMemcpyDeviceToHost));
+    // rows and entries in the caller's numbering, entries ascending
     int64_t pos = 0;
-    for (int32_t r = 0; r < n; r++) {
-        offsets[r] = pos;
+    for (int32_t v = 0; v < n; v++) {
+        const int32_t r = g->ext2int_h[v];
+        offsets[v] = pos;
         if (pos + cnt[r] > g->m)
             return set_error(DFPR_E_DEVICE, "device CSR holds more entries than m");
-        std::memcpy(idx + pos, slots.data() + beg[r], (size_t)cnt[r] * 4);
+        for (uint32_t k = 0; k < cnt[r]; k++) idx[pos + k] = g->int2ext_h[slots[beg[r] + k]];
+        std::sort(idx + pos, idx + pos + cnt[r]);
         pos += cnt[r];
     }
     offsets[n] = pos;
@@ -324,9 +431,8 @@ int dfpr_export_csr(const dfpr_graph *g, int out_orientation, int64_t *offsets, 
 int dfpr_get_ranks(const dfpr_graph *g, double *ranks, int on_device)
 {
     if (!g || !ranks) return set_error(DFPR_E_ARG, "NULL argument");
-    DFPR_HIP(hipMemcpyAsync(ranks, g->R[g->cur], (size_t)g->n * 8,
-                            on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost,
-                            g->stream));
+    const int rc = ranks_to_caller(g, g->R[g->cur], ranks, on_device);
+    if (rc) return rc;
     DFPR_HIP(hipStreamSynchronize(g->stream));
     return DFPR_OK;
 }

@@ -13,7 +13,25 @@ namespace dfpr {
 #ifndef DFPR_ITER_MIN_BLOCKS
 #define DFPR_ITER_MIN_BLOCKS 1
 #endif
+#ifndef DFPR_NT_IDX
+#define DFPR_NT_IDX 0
+#endif
+#ifndef DFPR_XCD_MAP
+#define DFPR_XCD_MAP 0
+#endif
 constexpr int kUnroll = DFPR_UNROLL;   // loads in flight per lane and round
+constexpr int kXcds = 8;               // workgroup i runs on XCD i mod 8
+
+// Streamed index loads: marked non-temporal so that they do not displace
+// gathered contributions from L2.
+__device__ inline int32_t load_idx(const int32_t *p)
+{
+#if DFPR_NT_IDX
+    return __builtin_nontemporal_load(p);
+#else
+    return *p;
+#endif
+}
 
 struct IterArgs {
     int32_t n;
@@ -64,7 +82,7 @@ __device__ inline double gather_sum(const IterArgs &a, const int32_t *idx, uint3
 #pragma unroll
             for (int j = 0; j < kUnroll; j++) {
                 const uint32_t k = k0 + j * step;
-                i[j] = k < cnt ? idx[k] : -1;
+                i[j] = k < cnt ? load_idx(idx + k) : -1;
             }
             double c[kUnroll];
 #pragma unroll
@@ -81,7 +99,7 @@ __device__ inline double gather_sum(const IterArgs &a, const int32_t *idx, uint3
 #pragma unroll
             for (int j = 0; j < kUnroll; j++) {
                 const uint32_t k = k0 + j * step;
-                i[j] = k < cnt ? idx[k] : -1;
+                i[j] = k < cnt ? load_idx(idx + k) : -1;
             }
             float c[kUnroll];
 #pragma unroll
@@ -133,7 +151,7 @@ __device__ inline void mark_out_row(const IterArgs &a, int32_t w, uint32_t lane0
 #pragma unroll
         for (int j = 0; j < kUnroll; j++) {
             const uint32_t k = k0 + lane0 + j * step;
-            x[j] = k < oc ? a.out_idx[ob + k] : -1;
+            x[j] = k < oc ? load_idx(a.out_idx + ob + k) : -1;
         }
         uint32_t st[kUnroll];
 #pragma unroll
@@ -353,13 +371,8 @@ __device__ inline void iter_body(const IterArgs &a, uint32_t blk, uint32_t G, It
     const uint32_t nbu = sh.plan.nbu, nwu = sh.plan.nwu;
 
     Acc acc;
-    for (uint32_t u = blk; u < nbu; u += G)
-        block_row<DF, F32>(a, sh.plan.list[kBins - 1][u], check, sparse, acc, sh.red, &sh.flag);
-
     const int wave = threadIdx.x / kWave;
-    for (uint32_t u = blk * kWavesPerBlock + wave; u < nwu; u += G * kWavesPerBlock) {
-        int k = 0;
-        while (k + 1 < kBins - 1 && u >= sh.plan.ustart[k + 1]) k++;
+    auto run_unit = [&](uint32_t u, int k) {
         const int b = kBins - 2 - k;
         const uint32_t first = (u - sh.plan.ustart[k]) * (kWave / group_of(b));
         const int32_t *list = sh.plan.list[b];
@@ -371,6 +384,45 @@ __device__ inline void iter_body(const IterArgs &a, uint32_t blk, uint32_t G, It
         case 3: wave_unit<8, DF, F32>(a, list, cnt, first, check, sparse, acc); break;
         case 4: wave_unit<32, DF, F32>(a, list, cnt, first, check, sparse, acc); break;
         default: wave_unit<64, DF, F32>(a, list, cnt, first, check, sparse, acc); break;
+        }
+    };
+    bool xcd = false;
+#if DFPR_XCD_MAP
+    // Every workgroup has work and the grid is a multiple of the XCD count:
+    // the workgroups of XCD x take the x-th eighth of every class, so that
+    // each XCD's L2 serves a contiguous id range of every class.
+    xcd = (G % kXcds) == 0 && (nwu + kWavesPerBlock - 1) / kWavesPerBlock >= G;
+#endif
+    if (!xcd) {
+        for (uint32_t u = blk; u < nbu; u += G)
+            block_row<DF, F32>(a, sh.plan.list[kBins - 1][u], check, sparse, acc, sh.red,
+                               &sh.flag);
+        for (uint32_t u = blk * kWavesPerBlock + wave; u < nwu; u += G * kWavesPerBlock) {
+            int k = 0;
+            while (k + 1 < kBins - 1 && u >= sh.plan.ustart[k + 1]) k++;
+            run_unit(u, k);
+        }
+    } else {
+        const uint32_t x = blk % kXcds, lb = blk / kXcds, GX = G / kXcds;
+        const uint32_t b0 = (uint32_t)((uint64_t)nbu * x / kXcds);
+        const uint32_t b1 = (uint32_t)((uint64_t)nbu * (x + 1) / kXcds);
+        for (uint32_t u = b0 + lb; u < b1; u += GX)
+            block_row<DF, F32>(a, sh.plan.list[kBins - 1][u], check, sparse, acc, sh.red,
+                               &sh.flag);
+        uint32_t lo[kBins - 1], len[kBins - 1], total = 0;
+        for (int k = 0; k < kBins - 1; k++) {
+            const uint32_t us = sh.plan.ustart[k];
+            const uint32_t ue = k + 1 < kBins - 1 ? sh.plan.ustart[k + 1] : nwu;
+            const uint64_t nu = ue - us;
+            lo[k] = us + (uint32_t)(nu * x / kXcds);
+            len[k] = us + (uint32_t)(nu * (x + 1) / kXcds) - lo[k];
+            total += len[k];
+        }
+        for (uint32_t j = lb * kWavesPerBlock + wave; j < total; j += GX * kWavesPerBlock) {
+            int k = 0;
+            uint32_t r = j;
+            while (r >= len[k]) r -= len[k++];
+            run_unit(lo[k] + r, k);
         }
     }
 

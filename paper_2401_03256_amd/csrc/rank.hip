@@ -605,8 +605,8 @@ static int full_sweeps(dfpr_graph *g, const dfpr_params *pp, const double *prev,
     DFPR_HIP(hipEventRecord(g->ev0, s));
     const int cur = g->cur;
     if (prev) {
-        DFPR_HIP(hipMemcpyAsync(g->R[cur], prev, (size_t)n * 8,
-                                prev_dev ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, s));
+        rc = ranks_from_caller(g, prev, prev_dev, g->R[cur]);
+        if (rc) return rc;
         k_init_ranks<<<blocks_for(n), kBlock, 0, s>>>(n, g->R[cur], g->R[0], g->R[1], g->C[0],
                                                       g->C[1], g->csr[1].cnt);
     } else if (!use_resident) {
@@ -627,9 +627,10 @@ static int full_sweeps(dfpr_graph *g, const dfpr_params *pp, const double *prev,
                                              g->C[res ^ 1]);
     g->cur = res;
     DFPR_HIP(hipEventRecord(g->ev1, s));
-    if (ranks_out)
-        DFPR_HIP(hipMemcpyAsync(ranks_out, g->R[res], (size_t)n * 8,
-                                out_dev ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, s));
+    if (ranks_out) {
+        rc = ranks_to_caller(g, g->R[res], ranks_out, out_dev);
+        if (rc) return rc;
+    }
     DFPR_HIP(hipStreamSynchronize(s));
     fill_stats(g, st, false);
     return DFPR_OK;
@@ -646,13 +647,14 @@ int df_begin(dfpr_graph *g, const dfpr_params &p, int64_t nd, const int32_t *bds
     const int32_t n = g->n;
     hipStream_t s = g->stream;
     const int cur = g->cur;
+    int rc = DFPR_OK;
     if (prev) {
-        DFPR_HIP(hipMemcpyAsync(g->R[cur], prev, (size_t)n * 8,
-                                prev_dev ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, s));
+        rc = ranks_from_caller(g, prev, prev_dev, g->R[cur]);
+        if (rc) return rc;
         k_init_ranks<<<blocks_for(n), kBlock, 0, s>>>(n, g->R[cur], g->R[0], g->R[1], g->C[0],
                                                       g->C[1], g->csr[1].cnt);
     }
-    int rc = ensure_schedule(g);
+    rc = ensure_schedule(g);
     uint32_t sbase = 0;
     if (!rc) rc = take_base(g, p.max_iters, &sbase);
     if (rc) return rc;
@@ -729,14 +731,11 @@ static int df_impl(dfpr_graph *g, const dfpr_params *pp, int64_t nd, const int32
     }
     BusyGuard guard(g);
     if (!guard.ok) return set_error(DFPR_E_BUSY, "graph in use");
-    const int32_t n = g->n;
     hipStream_t s = g->stream;
     DFPR_HIP(hipEventRecord(g->ev0, s));
-    const int32_t *bds = ds, *bdd = dd, *bis = is, *bid = id;
-    if (!on_device) {
-        rc = stage_batch(g, nd, ds, dd, ni, is, id, &bds, &bdd, &bis, &bid);
-        if (rc) return rc;
-    }
+    const int32_t *bds, *bdd, *bis, *bid;
+    rc = stage_batch(g, nd, ds, dd, ni, is, id, on_device, &bds, &bdd, &bis, &bid);
+    if (rc) return rc;
     const int cur = g->cur;
     uint32_t sbase = 0;
     rc = df_begin(g, p, nd, bds, bdd, ni, bis, bid, prev, on_device, &sbase);
@@ -766,9 +765,10 @@ static int df_impl(dfpr_graph *g, const dfpr_params *pp, int64_t nd, const int32
     rc = df_finish(g, sbase, res, iters);
     if (rc) return rc;
     DFPR_HIP(hipEventRecord(g->ev1, s));
-    if (ranks_out)
-        DFPR_HIP(hipMemcpyAsync(ranks_out, g->R[res], (size_t)n * 8,
-                                on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, s));
+    if (ranks_out) {
+        rc = ranks_to_caller(g, g->R[res], ranks_out, on_device);
+        if (rc) return rc;
+    }
     DFPR_HIP(hipMemcpyAsync(g->ctl_host, g->ctl, sizeof(Ctl), hipMemcpyDeviceToHost, s));
     DFPR_HIP(hipStreamSynchronize(s));
     fill_stats(g, st, true);
@@ -786,9 +786,10 @@ int dfpr_set_ranks(dfpr_graph *g, const double *ranks, int on_device)
     if (!g) return set_error(DFPR_E_ARG, "graph is NULL");
     const int32_t n = g->n;
     hipStream_t s = g->stream;
-    if (ranks)
-        DFPR_HIP(hipMemcpyAsync(g->R[0], ranks, (size_t)n * 8,
-                                on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, s));
+    if (ranks) {
+        const int rc = ranks_from_caller(g, ranks, on_device, g->R[0]);
+        if (rc) return rc;
+    }
     k_init_ranks<<<blocks_for(n), kBlock, 0, s>>>(n, ranks ? g->R[0] : nullptr, g->R[0], g->R[1],
                                                   g->C[0], g->C[1], g->csr[1].cnt);
     DFPR_HIP(hipGetLastError());
@@ -845,7 +846,8 @@ int dfpr_mark_affected(dfpr_graph *g, int64_t n_del, const int32_t *del_src,
     const int32_t n = g->n;
     hipStream_t s = g->stream;
     const int32_t *bds, *bdd, *bis, *bid;
-    rc = stage_batch(g, n_del, del_src, del_dst, n_ins, ins_src, ins_dst, &bds, &bdd, &bis, &bid);
+    rc = stage_batch(g, n_del, del_src, del_dst, n_ins, ins_src, ins_dst, 0, &bds, &bdd, &bis,
+                     &bid);
     dfpr_params p;
     dfpr_params_default(&p);
     uint32_t sbase = 0;
@@ -860,7 +862,7 @@ int dfpr_mark_affected(dfpr_graph *g, int64_t n_del, const int32_t *del_src,
     std::vector<uint32_t> st(n);
     DFPR_HIP(hipMemcpyAsync(st.data(), g->stamp, (size_t)n * 4, hipMemcpyDeviceToHost, s));
     DFPR_HIP(hipStreamSynchronize(s));
-    for (int32_t v = 0; v < n; v++) flags_out[v] = st[v] == sbase ? 1 : 0;
+    for (int32_t v = 0; v < n; v++) flags_out[v] = st[g->ext2int_h[v]] == sbase ? 1 : 0;
     return DFPR_OK;
 }
 
@@ -872,8 +874,10 @@ int dfpr_get_affected(const dfpr_graph *g, uint8_t *flags_out)
     DFPR_HIP(hipStreamSynchronize(g->stream));
     DFPR_HIP(hipMemcpy(st.data(), g->stamp, (size_t)n * 4, hipMemcpyDeviceToHost));
     const uint32_t lo = g->last_base, hi = g->last_base + (uint32_t)std::max(g->last_iters, 0);
-    for (int32_t v = 0; v < n; v++)
-        flags_out[v] = (g->last_iters >= 0 && st[v] >= lo && st[v] <= hi) ? 1 : 0;
+    for (int32_t v = 0; v < n; v++) {
+        const uint32_t x = st[g->ext2int_h[v]];
+        flags_out[v] = (g->last_iters >= 0 && x >= lo && x <= hi) ? 1 : 0;
+    }
     return DFPR_OK;
 }
 

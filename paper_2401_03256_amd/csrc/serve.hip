@@ -145,7 +145,7 @@ static int64_t graph_bytes(const dfpr_graph *g)
     const int64_t n = g->n;
     int64_t b = 0;
     for (int o = 0; o < 2; o++) b += (int64_t)g->csr[o].slots * 4 + 3 * n * 4;
-    b += 4 * n * 8 + 2 * n * 4 + 2 * n * 4 + (int64_t)kBins * n * 4 + n * 4;
+    b += 5 * n * 8 + 2 * n * 4 + 2 * n * 4 + (int64_t)kBins * n * 4 + n * 4 + 2 * n * 4;
     return b;
 }
 
@@ -202,7 +202,7 @@ static int admit(dfpr_server *srv, int64_t r, Slot &sl, double now_ms)
         q.res.applied[0] = applied[0];
         q.res.applied[1] = applied[1];
         const int32_t *bds, *bdd, *bis, *bid;
-        rc = stage_batch(g, nd, q.ds.data(), q.dd.data(), ni, q.is.data(), q.id.data(), &bds,
+        rc = stage_batch(g, nd, q.ds.data(), q.dd.data(), ni, q.is.data(), q.id.data(), 0, &bds,
                          &bdd, &bis, &bid);
         if (rc) break;
         uint32_t sbase = 0;
