@@ -518,14 +518,17 @@ static inline unsigned grid_for(uint64_t items, unsigned per = kBlock)
 }
 
 // Copy a batch (host or device arrays) into the graph's staging buffer in
-// internal ids; ids outside [0, n) become -1 and are rejected later.
+// internal ids; ids outside [0, n) become -1 and are rejected later.  The
+// buffer keeps 2 (n_del + n_ins) more entries after the batch for the
+// initial marking.
 int stage_batch(dfpr_graph *g, int64_t n_del, const int32_t *ds, const int32_t *dd,
                 int64_t n_ins, const int32_t *is, const int32_t *id, int on_device,
                 const int32_t **dds, const int32_t **ddd, const int32_t **dis,
                 const int32_t **did)
 {
     ApplyBufs &ap = g->ap;
-    const uint64_t need = 2 * (uint64_t)(n_del + n_ins);
+    // the batch, then room for the two source lists of the initial marking
+    const uint64_t need = 4 * (uint64_t)(n_del + n_ins);
     if (need > ap.batch_cap || !ap.batch_dev) {
         (void)hipFree(ap.batch_dev);
         ap.batch_dev = nullptr;

@@ -53,6 +53,9 @@ struct Ctl {
     unsigned long long affected0;   // marks after the initial marking
     unsigned long long affected;    // marks when the call ended
     uint32_t err;               // an id outside [0, n) was seen
+    uint32_t mk_light;          // initial marking: claimed sources scanned by one wave
+    uint32_t mk_heavy;          //   ... and by the whole grid
+    unsigned long long reach;   //   out-edges of the claimed sources
     uint32_t nsmall[2];         // batch applier: touched rows per orientation
     uint32_t nbig[2];           //   ... rows whose capacity exceeds the LDS copy
     uint32_t novf[2];           //   ... rows that need a re-layout

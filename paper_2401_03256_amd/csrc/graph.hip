@@ -16,10 +16,13 @@
 
 namespace dfpr {
 
+// Iteration-kernel workgroups per CU.  The kernel fits five waves per SIMD,
+// so most of the grid waits for a free slot; many small workgroups even
+// out the uneven rows (32 per CU measured best on R-MAT scale 22, 5% over 8).
 #ifndef DFPR_GRID_PER_CU
-#define DFPR_GRID_PER_CU 8
+#define DFPR_GRID_PER_CU 32
 #endif
-constexpr int kGridPerCU = DFPR_GRID_PER_CU;   // iteration-kernel workgroups per CU
+constexpr int kGridPerCU = DFPR_GRID_PER_CU;
 
 static thread_local std::string g_last_error;
 

@@ -100,6 +100,8 @@ __global__ void k_reset(Ctl *ctl)
         ctl->xverts = ctl->xedges = ctl->marked = 0;
         ctl->affected0 = ctl->affected = 0;
         ctl->err = 0;
+        ctl->mk_light = ctl->mk_heavy = 0;
+        ctl->reach = 0;
     }
 }
 
@@ -113,7 +115,7 @@ __global__ void k_snap(Ctl *ctl, int32_t max_iters, uint32_t sparse_limit, int d
             ctl->snap[0][b] = ctl->live[b];
             tot += ctl->live[b];
         }
-        ctl->dense = (dense || tot > sparse_limit) ? 1 : 0;
+        ctl->dense = (dense || ctl->dense || tot > sparse_limit) ? 1 : 0;
         ctl->done = (ctl->err || max_iters <= 0) ? 1 : 0;
     }
 }
@@ -255,47 +257,111 @@ __global__ void k_validate(int32_t n, int64_t nd, const int32_t *ds, const int32
     }
 }
 
-// Initial marking (Section 4.1.1, Algorithm 1): one wave per batch edge
-// (u, v) marks G^t.out(u), and for a deletion also v, which was in
-// G^{t-1}.out(u); the union is (G^{t-1} U G^t).out(u).  The marks carry
-// stamp base, i.e. they are processed from iteration 0.  u's out-row is now
-// fully marked, so u never needs to scan it again in this call.  With
-// `append`, newly marked vertices also go to the class lists.
-__global__ __launch_bounds__(kBlock) void k_mark_initial(IterArgs a, int64_t nd, const int32_t *ds,
-                                                         const int32_t *dd, int64_t ni,
-                                                         const int32_t *is, int append)
+// Initial marking (Section 4.1.1, Algorithm 1): every batch edge (u, v)
+// marks G^t.out(u), and a deletion also marks v, which was in
+// G^{t-1}.out(u).  Marks are stamps equal to the call's base.  A source
+// whose out-row has been scanned gets its expansion stamp, so it never
+// scans that row again in this call.
+//
+// Claim pass, one thread per batch entry: the first entry of each distinct
+// source claims it through its expansion stamp; claimed sources go to a
+// light list (out-row scanned by one wave) or a heavy list (scanned by the
+// whole grid in workgroup-sized chunks), and their out-degrees are summed.
+constexpr uint32_t kHeavyRow = 2048;   // out-rows longer than this use the grid
+
+__global__ __launch_bounds__(kBlock) void k_mark_claim(IterArgs a, int64_t nd, const int32_t *ds,
+                                                       int64_t ni, const int32_t *is,
+                                                       int32_t *light, int32_t *heavy)
+{
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    int32_t u = -1;
+    if (i < nd + ni) u = i < nd ? ds[i] : is[i - nd];
+    bool take = false;
+    uint32_t oc = 0;
+    if (u >= 0 && u < a.n && a.xstamp[u] != a.sbase) {
+        take = atomicMax(&a.xstamp[u], a.sbase) < a.sbase;
+        if (take) oc = a.out_cnt[u];
+    }
+    const bool big = take && oc > kHeavyRow;
+    const int lane = lane_id();
+    const unsigned long long below = (1ull << lane) - 1ull;
+    const unsigned long long ml = __ballot(take && !big), mh = __ballot(big);
+    unsigned long long r = oc;
+#pragma unroll
+    for (int off = kWave / 2; off > 0; off >>= 1) r += __shfl_xor(r, off, kWave);
+    uint32_t bl = 0, bh = 0;
+    if (lane == 0) {
+        if (ml) bl = atomicAdd(&a.ctl->mk_light, (uint32_t)__popcll(ml));
+        if (mh) bh = atomicAdd(&a.ctl->mk_heavy, (uint32_t)__popcll(mh));
+        if (r) atomicAdd(&a.ctl->reach, r);
+    }
+    bl = __shfl(bl, 0);
+    bh = __shfl(bh, 0);
+    if (take && !big) light[bl + __popcll(ml & below)] = u;
+    if (big) heavy[bh + __popcll(mh & below)] = u;
+}
+
+// Mark x (x < 0: no vertex).  Every lane of the wave calls it.
+__device__ inline void mark_one(const IterArgs &a, int32_t x, bool append,
+                                unsigned long long &mine)
+{
+    bool nw = false;
+    if (x >= 0 && a.stamp[x] < a.sbase) nw = atomicMax(&a.stamp[x], a.sbase) < a.sbase;
+    const unsigned long long m = __ballot(nw);
+    if (lane_id() == 0) mine += __popcll(m);
+    if (append) {
+        const int cls = nw ? bin_of(a.in_cnt[x]) : 0;
+        append_to_bins(nw, x, cls, a.ctl, a.bins, a.n_stride);
+    }
+}
+
+// Marking pass: deletion targets, then light sources one wave each, then
+// heavy sources in chunks of kBlock out-edges spread over the grid.  The
+// class lists are filled (sparse mode) unless `dense` is set or the claimed
+// sources reach more vertices than the sparse limit; the decision goes to
+// the control block for the iterations.  Every loop bound is uniform
+// within a wave.
+__global__ __launch_bounds__(kBlock) void k_mark_initial(IterArgs a, int64_t nd, const int32_t *dd,
+                                                         const int32_t *light,
+                                                         const int32_t *heavy, int dense)
 {
     __shared__ unsigned long long s_new;
-    if (a.ctl->err) return;
+    Ctl *ctl = a.ctl;
+    if (ctl->err) return;
+    const bool dn = dense || ctl->reach + (unsigned long long)nd > a.sparse_limit;
+    const bool append = !dn;
+    if (blockIdx.x == 0 && threadIdx.x == 0 && dn) ctl->dense = 1;
     if (threadIdx.x == 0) s_new = 0;
     __syncthreads();
     const int lane = lane_id();
+    const int64_t wave = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) / kWave;
     const int64_t waves = (int64_t)gridDim.x * kWavesPerBlock;
     unsigned long long mine = 0;
-    for (int64_t w = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) / kWave; w < nd + ni;
-         w += waves) {
-        const int32_t u = w < nd ? ds[w] : is[w - nd];
+    for (int64_t b0 = wave * kWave; b0 < nd; b0 += waves * kWave) {
+        const int64_t i = b0 + lane;
+        mark_one(a, i < nd ? dd[i] : -1, append, mine);
+    }
+    const uint32_t nl = ctl->mk_light, nh = ctl->mk_heavy;
+    for (int64_t w = wave; w < nl; w += waves) {
+        const int32_t u = light[w];
         const uint32_t ob = a.out_beg[u], oc = a.out_cnt[u];
-        const uint32_t len = oc + (w < nd ? 1u : 0u);
-        for (uint32_t kb = 0; kb < len; kb += kWave) {
+        for (uint32_t kb = 0; kb < oc; kb += kWave) {
             const uint32_t k = kb + lane;
-            int32_t x = -1;
-            if (k < oc) x = a.out_idx[ob + k];
-            else if (k < len) x = dd[w];
-            bool nw = false;
-            if (x >= 0 && a.stamp[x] < a.sbase) nw = atomicMax(&a.stamp[x], a.sbase) < a.sbase;
-            const unsigned long long m = __ballot(nw);
-            if (lane == 0) mine += __popcll(m);
-            if (append) {
-                const int cls = nw ? bin_of(a.in_cnt[x]) : 0;
-                append_to_bins(nw, x, cls, a.ctl, a.bins, a.n_stride);
-            }
+            mark_one(a, k < oc ? a.out_idx[ob + k] : -1, append, mine);
         }
-        if (lane == 0) a.xstamp[u] = a.sbase;
+    }
+    for (uint32_t h = 0; h < nh; h++) {
+        const int32_t u = heavy[h];
+        const uint32_t ob = a.out_beg[u], oc = a.out_cnt[u];
+        const uint32_t chunks = (oc + kBlock - 1) / kBlock;
+        for (uint32_t c = blockIdx.x; c < chunks; c += gridDim.x) {
+            const uint32_t k = c * kBlock + threadIdx.x;
+            mark_one(a, k < oc ? a.out_idx[ob + k] : -1, append, mine);
+        }
     }
     if (lane == 0 && mine) atomicAdd(&s_new, mine);
     __syncthreads();
-    if (threadIdx.x == 0 && s_new) atomicAdd(&a.ctl->affected0, s_new);
+    if (threadIdx.x == 0 && s_new) atomicAdd(&ctl->affected0, s_new);
 }
 
 // End of a Dynamic Frontier call: copy the rows processed in this call from
@@ -386,6 +452,21 @@ static inline int blocks_for(int64_t items, int per_block = kBlock)
     const int64_t b = (items + per_block - 1) / per_block;
     return (int)std::max<int64_t>(1, std::min<int64_t>(b, 65535 * 16));
 }
+
+// Both passes of the initial marking on the graph's stream.  The batch
+// arrays are in the staging buffer, which has room for the source lists.
+static void launch_initial_marking(dfpr_graph *g, const IterArgs &a, int64_t nd,
+                                   const int32_t *ds, const int32_t *dd, int64_t ni,
+                                   const int32_t *is, int dense)
+{
+    int32_t *light = g->ap.batch_dev + 2 * (nd + ni);
+    int32_t *heavy = light + (nd + ni);
+    k_mark_claim<<<blocks_for(nd + ni), kBlock, 0, g->stream>>>(a, nd, ds, ni, is, light, heavy);
+    const int64_t waves = std::max<int64_t>(nd + ni, 1024);
+    k_mark_initial<<<(unsigned)std::min<int64_t>(blocks_for(waves * kWave), 2048), kBlock, 0,
+                     g->stream>>>(a, nd, dd, light, heavy, dense);
+}
+
 
 int launch_fill_u32(dfpr_graph *g, uint32_t *p, uint64_t len, uint32_t value)
 {
@@ -658,15 +739,14 @@ int df_begin(dfpr_graph *g, const dfpr_params &p, int64_t nd, const int32_t *bds
     uint32_t sbase = 0;
     if (!rc) rc = take_base(g, p.max_iters, &sbase);
     if (rc) return rc;
-    // a batch whose sources reach many vertices starts on the full schedule
-    const double reach = (double)(nd + ni) * ((double)g->m / (double)n);
-    const int dense = reach > (double)g->sparse_limit ? 1 : 0;
+    // the initial marking decides on the device whether the batch's
+    // sources reach enough vertices to start on the full schedule
+    const int dense = 0;
     IterArgs a = iter_args(g, p, sbase);
     k_reset<<<1, 1, 0, s>>>(g->ctl);
     if (nd + ni > 0) {
         k_validate<<<blocks_for(nd + ni), kBlock, 0, s>>>(n, nd, bds, bdd, ni, bis, bid, g->ctl);
-        k_mark_initial<<<std::min(blocks_for((nd + ni) * kWave), 2048), kBlock, 0, s>>>(
-            a, nd, bds, bdd, ni, bis, dense ? 0 : 1);
+        launch_initial_marking(g, a, nd, bds, bdd, ni, bis, dense);
     }
     k_snap<<<1, 1, 0, s>>>(g->ctl, p.max_iters, g->sparse_limit, dense);
     if (p.precision == DFPR_FP32_KAHAN)
@@ -855,9 +935,7 @@ int dfpr_mark_affected(dfpr_graph *g, int64_t n_del, const int32_t *del_src,
     if (rc) return rc;
     IterArgs a = iter_args(g, p, sbase);
     k_reset<<<1, 1, 0, s>>>(g->ctl);
-    if (n_del + n_ins > 0)
-        k_mark_initial<<<std::min(blocks_for((n_del + n_ins) * kWave), 2048), kBlock, 0, s>>>(
-            a, n_del, bds, bdd, n_ins, bis, 0);
+    if (n_del + n_ins > 0) launch_initial_marking(g, a, n_del, bds, bdd, n_ins, bis, 1);
     DFPR_HIP(hipGetLastError());
     std::vector<uint32_t> st(n);
     DFPR_HIP(hipMemcpyAsync(st.data(), g->stamp, (size_t)n * 4, hipMemcpyDeviceToHost, s));
