@@ -82,8 +82,11 @@ def main():
     ap.add_argument("--frontier-tol", type=float, default=1e-13)
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--serve", action="store_true",
-                    help="serving form: 12 resident R-MAT graphs, Poisson update stream")
+    ap.add_argument("--workload", default="rmat22", choices=["rmat22", "grid", "fp32", "serve"],
+                    help="rmat22: the headline line; grid: 4096x4096 grid, uniform and "
+                         "localised batches; fp32: R-MAT scale 24, FP32 storage form vs FP64; "
+                         "serve: 12 resident R-MAT graphs, Poisson update stream")
+    ap.add_argument("--serve", action="store_true", help="same as --workload serve")
     ap.add_argument("--serve-requests", type=int, default=96)
     ap.add_argument("--serve-load", type=float, default=0.9,
                     help="arrival rate as a fraction of one-at-a-time FP64 capacity")
@@ -105,8 +108,14 @@ def main():
     assert torch.cuda.is_available(), "no GPU"
     torch.cuda.set_device(0)
     dfpr.lib()
-    if args.serve:
+    if args.serve or args.workload == "serve":
         serve_bench(args, dfpr, synth)
+        return
+    if args.workload == "grid":
+        grid_bench(args, dfpr, synth)
+        return
+    if args.workload == "fp32":
+        fp32_bench(args, dfpr, synth)
         return
     fracs = [float(x) for x in args.fracs.split(",")]
     workload = f"rmat{args.scale}_ef{args.edge_factor}_df_fp64"
@@ -177,9 +186,11 @@ def main():
         g.apply_batch_device(*dev[i])
         st_df = g.dynamic_frontier_device(*dev[i], p=p)
         R_df = g.ranks()
-        st_32 = g.dynamic_frontier_device(*dev[i], prev=torch.from_numpy(R_prev).cuda(), p=p32)
+        g.set_ranks(R_prev)
+        st_32 = g.dynamic_frontier_device(*dev[i], p=p32)
         R_32 = g.ranks()
-        _, st_nv = g.naive_dynamic(R_prev, p=p, out=False)
+        g.set_ranks(R_prev)
+        _, st_nv = g.naive_dynamic(None, p=p, out=False)
         R_nv = g.ranks()
         _, st_st = g.static(p, out=False)
         R_st = g.ranks()
@@ -206,6 +217,8 @@ def main():
 
     achieved = prof.bytes / (prof.ms / 1e3) / 1e9 if prof.ms > 0 else 0.0
     tb = measured_traffic(workload)
+    copy_gbs = copy_bandwidth(torch)
+    log(f"achievable copy bandwidth {copy_gbs:.0f} GB/s")
     roofline = {
         "bound": "hbm", "kernel": "k_iter<true> (pull + Delta r + L-inf + expand)",
         "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
@@ -213,6 +226,9 @@ def main():
         "traffic": None if tb is None else round(tb, 1),
         "launches": prof.launches, "avg_launch_us": round(prof.ms * 1e3 / max(prof.launches, 1), 2),
         "algorithmic_bytes_per_launch": round(prof.bytes / max(prof.launches, 1), 1),
+        "kernel_gteps": round(prof.edges / prof.ms / 1e6, 2) if prof.ms > 0 else None,
+        "achievable_copy_GBps": round(copy_gbs, 1),
+        "frac_of_copy": round(achieved / copy_gbs, 4) if copy_gbs > 0 else None,
     }
 
     cpu = None
@@ -237,6 +253,26 @@ def main():
         "comparators": comparators,
     }
     print(json.dumps(out), flush=True)
+
+
+def copy_bandwidth(torch, nbytes=1 << 30, reps=5):
+    """Read + write bandwidth of a plain device copy of `nbytes` (torch's
+    copy kernel), best of `reps`: the achievable streaming rate beside the
+    8 TB/s peak."""
+    a = torch.empty(nbytes // 8, dtype=torch.float64, device="cuda").fill_(1.0)
+    b = torch.empty_like(a)
+    b.copy_(a)
+    best = 0.0
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        b.copy_(a)
+        e1.record()
+        e1.synchronize()
+        best = max(best, 2 * nbytes / (e0.elapsed_time(e1) / 1e3) / 1e9)
+    del a, b
+    torch.cuda.empty_cache()
+    return best
 
 
 def cpu_baseline(n, src, dst, seq, R0, warm_ranks, args, log):
@@ -269,6 +305,111 @@ def cpu_baseline(n, src, dst, seq, R0, warm_ranks, args, log):
             "sample": f"Dynamic Frontier (mark + iterate) on the first {used} batches of the "
                       f"same sequence and graph, {spent:.1f}s of CPU time",
             "gpu_vs_oracle_linf": linf}
+
+
+def grid_bench(args, dfpr, synth, side=4096, kinds=("uniform", "localised"), per_kind=5):
+    """High-diameter workload: side x side grid with bidirectional
+    4-neighbour edges and diagonal shortcuts for 5% of the vertices;
+    batches of 1e-5 |E|, uniform and localised to one square window."""
+    t = time.time()
+    n, src, dst = synth.grid2d(side, 0.05, seed=1)
+    g = dfpr.Graph(n, src, dst)
+    m = g.m
+    log(f"grid {side}x{side}: n={n} m={m} ({time.time() - t:.1f}s)")
+    p = dfpr.params(frontier_tol=args.frontier_tol)
+    R0, st0 = g.static(p, out=False)
+    nd, ni = synth.batch_counts(1e-5, m)
+    uni = synth.batch_sequence(src, dst, n, [(nd, ni)] * per_kind, seed=2)
+    loc = [synth.localized_batch(src, dst, side, nd, ni, seed=10 + k) for k in range(per_kind)]
+    res = {}
+    for kind, batches in (("uniform", uni), ("localised", loc)):
+        rows = []
+        for b in batches:
+            g.apply_batch(b)
+            _, st = g.dynamic_frontier(b, p=p, out=False)
+            rows.append(st)
+            log(f"{kind}: batch {b.size}, {st.iterations} it, affected {st.affected_final}, "
+                f"{st.ms_device:.2f} ms")
+        ms = [r.ms_device for r in rows]
+        R_prev = g.ranks()
+        _, st_nv = g.naive_dynamic(R_prev, p=p, out=False)
+        res[kind] = {
+            "df_ms_p50": round(pct(ms, 50), 3), "df_ms_p99": round(pct(ms, 99), 3),
+            "df_iterations_mean": round(float(np.mean([r.iterations for r in rows])), 1),
+            "df_affected_mean": int(np.mean([r.affected_final for r in rows])),
+            "df_us_per_iteration": round(float(np.sum(ms) * 1e3 / np.sum([r.iterations for r in rows])), 1),
+            "df_gteps": round(float(np.sum([r.edges_processed for r in rows]) / np.sum(ms) / 1e6), 2),
+            "naive_ms": round(st_nv.ms_device, 3), "naive_iterations": st_nv.iterations,
+            "speedup_vs_naive": round(st_nv.ms_device / pct(ms, 50), 2),
+        }
+    out = {"metric": METRIC, "workload": f"grid{side}_diag5_df_fp64", "n": n, "m": m,
+           "batch": [nd, ni], "static_ms": round(st0.ms_device, 3),
+           "static_iterations": st0.iterations,
+           "static_gteps": round(st0.edges_processed / st0.ms_device / 1e6, 2), "kinds": res}
+    for kind in res:
+        res[kind]["speedup_vs_static"] = round(st0.ms_device / res[kind]["df_ms_p50"], 2)
+    print(json.dumps(out), flush=True)
+
+
+def fp32_bench(args, dfpr, synth, scale=24, per_size=5):
+    """Precision form on R-MAT scale 24: for each batch, from the same
+    previous ranks, plain FP64 Dynamic Frontier, the FP32 storage form (FP32
+    phase + FP64 refinement) and the FP32 phase alone (the same call capped
+    at its FP32 iterations), with max-abs and L1 differences from the FP64
+    result, which stands for the FP64 method (the FP64 path matches the
+    oracle to ~1e-17 at scale 22)."""
+    t = time.time()
+    n, src, dst = synth.rmat(scale, 16, seed=1)
+    log(f"R-MAT scale {scale}: n={n} edges={src.size} ({time.time() - t:.1f}s)")
+    g = dfpr.Graph(n, src, dst)
+    m = g.m
+    p64 = dfpr.params(frontier_tol=args.frontier_tol)
+    p32 = dfpr.params(frontier_tol=args.frontier_tol, precision=dfpr.FP32_KAHAN)
+    g.static(p64, out=False)
+    counts = [synth.batch_counts(f, m) for f in (1e-6, 1e-4) * per_size]
+    seq = synth.batch_sequence(src, dst, n, counts, seed=2)
+    by = {}
+    for i, b in enumerate(seq):
+        f = (1e-6, 1e-4)[i % 2]
+        R_prev = g.ranks()
+        g.apply_batch(b)
+        # each variant starts from the same resident ranks (set outside the
+        # timed call); FP64 runs last so its result carries on
+        _, s32 = g.dynamic_frontier(b, p=p32, out=False)
+        R32 = g.ranks()
+        k32 = s32.iterations - s32.refine_sweeps
+        p32c = dfpr.params(frontier_tol=args.frontier_tol, precision=dfpr.FP32_KAHAN, max_iters=k32)
+        g.set_ranks(R_prev)
+        _, s32p = g.dynamic_frontier(b, p=p32c, out=False)
+        R32p = g.ranks()
+        g.set_ranks(R_prev)
+        _, s64 = g.dynamic_frontier(b, p=p64, out=False)
+        R64 = g.ranks()
+        row = {"fp64_ms": s64.ms_device, "fp64_iterations": s64.iterations,
+               "fp32_ms": s32.ms_device, "fp32_iterations": s32.iterations,
+               "fp32_refine_sweeps": s32.refine_sweeps,
+               "linf": float(np.max(np.abs(R32 - R64))), "l1": float(np.sum(np.abs(R32 - R64))),
+               "linf_fp32_phase": float(np.max(np.abs(R32p - R64))),
+               "l1_fp32_phase": float(np.sum(np.abs(R32p - R64))),
+               "rel_linf_fp32_phase": float(np.max(np.abs(R32p - R64) / R64))}
+        by.setdefault(str(f), []).append(row)
+        log(f"{f}: batch {b.size}: FP64 {s64.ms_device:.2f} ms {s64.iterations} it; FP32 form "
+            f"{s32.ms_device:.2f} ms ({s32.refine_sweeps} refine); Linf {row['linf']:.2e}, "
+            f"FP32 phase alone {row['linf_fp32_phase']:.2e}")
+    summ = {}
+    for f, rows in by.items():
+        t64 = [r["fp64_ms"] for r in rows]
+        t32 = [r["fp32_ms"] for r in rows]
+        summ[f] = {"fp64_ms_p50": round(pct(t64, 50), 3), "fp32_form_ms_p50": round(pct(t32, 50), 3),
+                   "fp32_form_updates_per_s_vs_fp64": round(sum(t64) / sum(t32), 3),
+                   "fp32_refine_sweeps_mean": round(float(np.mean([r["fp32_refine_sweeps"] for r in rows])), 1),
+                   "max_linf_vs_fp64": max(r["linf"] for r in rows),
+                   "max_l1_vs_fp64": max(r["l1"] for r in rows),
+                   "max_linf_fp32_phase_vs_fp64": max(r["linf_fp32_phase"] for r in rows),
+                   "max_l1_fp32_phase_vs_fp64": max(r["l1_fp32_phase"] for r in rows),
+                   "max_rel_linf_fp32_phase": max(r["rel_linf_fp32_phase"] for r in rows)}
+    print(json.dumps({"metric": METRIC, "workload": f"rmat{scale}_ef16_fp32_form_vs_fp64",
+                      "n": n, "m": m, "by_frac": summ}), flush=True)
 
 
 def serve_bench(args, dfpr, synth):

@@ -62,6 +62,7 @@ struct Ctl {
     uint32_t max_cap[2];        //   largest row capacity
     unsigned long long top[2];  //   first free slot of each index array
     unsigned long long applied[2];  // effective deletions, insertions
+    uint32_t cls_moved;         //   an in-row changed its in-degree class
 };
 
 // One orientation of the graph: row r holds cnt[r] sorted ids in

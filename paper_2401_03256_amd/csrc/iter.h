@@ -10,8 +10,12 @@ namespace dfpr {
 #ifndef DFPR_UNROLL
 #define DFPR_UNROLL 4
 #endif
-#ifndef DFPR_ITER_MIN_BLOCKS
-#define DFPR_ITER_MIN_BLOCKS 1
+// Minimum waves per SIMD the iteration kernels are compiled for (the second
+// launch bound).  Five fit with a few spills of the expansion path; the
+// compiler alone picks four.  Measured on R-MAT scale 22 and the 4096^2
+// grid, five is faster on both.
+#ifndef DFPR_ITER_WAVES_PER_SIMD
+#define DFPR_ITER_WAVES_PER_SIMD 5
 #endif
 #ifndef DFPR_NT_IDX
 #define DFPR_NT_IDX 0
@@ -171,6 +175,40 @@ __device__ inline void mark_out_row(const IterArgs &a, int32_t w, uint32_t lane0
     }
 }
 
+// Expansion of the rows of a wave whose lanes have `deg` > 0 out-edges
+// starting at `ob` (`incl` = inclusive prefix sum of `deg` over the wave,
+// `total` its last value): every lane takes one out-edge per round, so
+// rows with few out-edges share rounds and list appends.  Every lane of
+// the wave calls it with the same `total`.
+template <bool SPARSE>
+__device__ inline void expand_rows(const IterArgs &a, uint32_t incl, uint32_t deg, uint32_t ob,
+                                   uint32_t total, uint32_t sv)
+{
+    const int lane = lane_id();
+    for (uint32_t t0 = 0; t0 < total; t0 += kWave) {
+        const uint32_t t = t0 + lane;
+        const uint32_t tt = min(t, total - 1);
+        // owner: the first lane whose inclusive sum exceeds tt
+        int j = 0;
+#pragma unroll
+        for (int step = kWave / 2; step > 0; step >>= 1)
+            if (__shfl(incl, j + step - 1) <= tt) j += step;
+        const uint32_t first = __shfl(incl, j) - __shfl(deg, j);
+        const uint32_t base = __shfl(ob, j);
+        const int32_t x = t < total ? load_idx(a.out_idx + base + (tt - first)) : -1;
+        const uint32_t st = x >= 0 ? a.stamp[x] : 0xFFFFFFFFu;
+        bool nw = false;
+        if (st < a.sbase) {
+            if (SPARSE) nw = atomicMax(&a.stamp[x], sv) < a.sbase;
+            else a.stamp[x] = sv;
+        }
+        if (SPARSE) {
+            const int cls = nw ? bin_of(a.in_cnt[x]) : 0;
+            append_to_bins(nw, x, cls, a.ctl, a.bins, a.n_stride);
+        }
+    }
+}
+
 // Finish one row: Eq. 1, Delta r, writes; returns whether it must expand.
 template <bool DF, bool F32>
 __device__ inline bool finish_row(const IterArgs &a, int32_t v, uint32_t cnt, double s, double rc,
@@ -208,16 +246,19 @@ __device__ inline void wave_unit(const IterArgs &a, const int32_t *list, uint32_
     double rc = 0.0;
     if (pos < count) {
         v = list[pos];
-        beg = a.in_beg[v];
-        cnt = a.in_cnt[v];
-        if (sub == 0) {
-            rc = a.Rc[v];
-            oc = a.out_cnt[v];
-        }
         active = true;
         if (DF && check) {
+            // full schedule: read a row only if it is marked
             const uint32_t st = a.stamp[v];
             active = st >= a.sbase && st <= a.sbase + (uint32_t)a.it;
+        }
+        if (active) {
+            beg = a.in_beg[v];
+            cnt = a.in_cnt[v];
+            if (sub == 0) {
+                rc = a.Rc[v];
+                oc = a.out_cnt[v];
+            }
         }
     }
     double s = 0.0;
@@ -233,9 +274,26 @@ __device__ inline void wave_unit(const IterArgs &a, const int32_t *list, uint32_
     for (int off = G / 2; off > 0; off >>= 1) s += __shfl_xor(s, off, G);
     bool expand = false;
     if (active && sub == 0) expand = finish_row<DF, F32>(a, v, cnt, s, rc, oc, acc);
-    if (DF) {
-        unsigned long long q = __ballot(expand);
+    // Rows with fewer out-edges than a wave has lanes expand together, one
+    // out-edge per lane and round; longer rows one at a time with the whole
+    // wave and kUnroll loads in flight per lane.
+    if (DF && __ballot(expand)) {
         const uint32_t sv = a.sbase + (uint32_t)a.it + 1;
+        const bool small = expand && oc < (uint32_t)kWave;
+        if (__ballot(small)) {
+            const uint32_t deg = small ? oc : 0u;
+            const uint32_t ob = small ? a.out_beg[v] : 0u;
+            uint32_t incl = deg;
+#pragma unroll
+            for (int d = 1; d < kWave; d <<= 1) {
+                const uint32_t y = __shfl_up(incl, d);
+                if (lane >= d) incl += y;
+            }
+            const uint32_t total = __shfl(incl, kWave - 1);
+            if (sparse) expand_rows<true>(a, incl, deg, ob, total, sv);
+            else expand_rows<false>(a, incl, deg, ob, total, sv);
+        }
+        unsigned long long q = __ballot(expand && !small);
         while (q) {
             const int l = __ffsll((long long)q) - 1;
             const int32_t w = __shfl(v, l);
@@ -454,11 +512,27 @@ __device__ inline void final_body(const IterArgs &a, uint32_t active, bool df, b
     const bool sparse = df && !ctl->dense;
     double dr = 0.0, rm = 0.0;
     unsigned long long c[kCounters] = {0, 0, 0, 0};
-    for (uint32_t i = threadIdx.x; i < active; i += kBlock) {
-        dr = fmax(dr, a.dr_part[i]);
-        rm = fmax(rm, a.rmax_part[i]);
+    // kFold partials per thread and round, all loads issued before use
+    constexpr int kFold = 8;
+    for (uint32_t i0 = threadIdx.x; i0 < active; i0 += kBlock * kFold) {
+        double pd[kFold], pr[kFold];
+        unsigned long long pc[kFold][kCounters];
 #pragma unroll
-        for (int j = 0; j < kCounters; j++) c[j] += a.cnt_part[i * kCounters + j];
+        for (int u = 0; u < kFold; u++) {
+            const uint32_t i = i0 + u * kBlock;
+            const bool in = i < active;
+            pd[u] = in ? a.dr_part[i] : 0.0;
+            pr[u] = in ? a.rmax_part[i] : 0.0;
+#pragma unroll
+            for (int j = 0; j < kCounters; j++) pc[u][j] = in ? a.cnt_part[i * kCounters + j] : 0ull;
+        }
+#pragma unroll
+        for (int u = 0; u < kFold; u++) {
+            dr = fmax(dr, pd[u]);
+            rm = fmax(rm, pr[u]);
+#pragma unroll
+            for (int j = 0; j < kCounters; j++) c[j] += pc[u][j];
+        }
     }
     block_fold(dr, rm, c, sh.wdr, sh.wrm, sh.wc);
     if (threadIdx.x == 0) {
@@ -481,9 +555,12 @@ __device__ inline void final_body(const IterArgs &a, uint32_t active, bool df, b
         }
         if (f32) {
             // FP32 contributions carry a relative rounding error of 2^-24;
-            // changes below about 2^-22 of the largest rank are noise
+            // changes below about 2^-22 of the largest rank are noise.  A
+            // Delta R that stops falling counts as a stall only near that
+            // floor (early on it can rise while the frontier grows).
             const double floor32 = rm * 0x1p-22;
-            const bool stalled = ctl->phase_iters >= 3 && dr >= 0.97 * ctl->prev_linf;
+            const bool stalled = ctl->phase_iters >= 3 && dr >= 0.97 * ctl->prev_linf &&
+                                 dr <= rm * 0x1p-16;
             ctl->phase_iters += 1;
             if (dr <= a.tol || dr <= floor32 || stalled) ctl->phase_end = 1;
             if (a.it + 1 >= a.max_iters) ctl->done = 1;

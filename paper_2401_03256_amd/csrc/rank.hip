@@ -55,7 +55,7 @@ namespace dfpr {
 constexpr int kSchedChunk = 4096;   // vertices per workgroup in the schedule build
 
 template <bool DF, bool F32>
-__global__ __launch_bounds__(kBlock, DFPR_ITER_MIN_BLOCKS) void k_iter(IterArgs a)
+__global__ __launch_bounds__(kBlock, DFPR_ITER_WAVES_PER_SIMD) void k_iter(IterArgs a)
 {
     __shared__ IterShared sh;
     iter_body<DF, F32>(a, blockIdx.x, gridDim.x, sh);
@@ -182,33 +182,33 @@ __global__ __launch_bounds__(kBlock) void k_sched_count(int32_t n, const uint32_
 }
 
 // Exclusive scan of the class-major count table; off[b] = start of class b.
+// Each thread sums a contiguous run of the table, the run totals are
+// scanned across the workgroup, and each thread then rewrites its run.
 __global__ __launch_bounds__(kBlock) void k_sched_scan(uint32_t *tmp, uint32_t nblocks,
                                                        uint32_t *off)
 {
     __shared__ uint32_t s[kBlock];
     const uint32_t len = nblocks * kBins;
-    uint32_t carry = 0;
-    for (uint32_t b0 = 0; b0 < len; b0 += kBlock) {
-        const uint32_t i = b0 + threadIdx.x;
-        const uint32_t v = i < len ? tmp[i] : 0;
-        s[threadIdx.x] = v;
+    const uint32_t run = (len + kBlock - 1) / kBlock;
+    const uint32_t lo = min(len, threadIdx.x * run), hi = min(len, lo + run);
+    uint32_t tot = 0;
+    for (uint32_t i = lo; i < hi; i++) tot += tmp[i];
+    s[threadIdx.x] = tot;
+    __syncthreads();
+    for (int o = 1; o < kBlock; o <<= 1) {
+        const uint32_t t = threadIdx.x >= (uint32_t)o ? s[threadIdx.x - o] : 0;
         __syncthreads();
-        for (int o = 1; o < kBlock; o <<= 1) {
-            const uint32_t t = threadIdx.x >= (uint32_t)o ? s[threadIdx.x - o] : 0;
-            __syncthreads();
-            s[threadIdx.x] += t;
-            __syncthreads();
-        }
-        if (i < len) {
-            const uint32_t ex = carry + s[threadIdx.x] - v;
-            tmp[i] = ex;
-            if (i % nblocks == 0) off[i / nblocks] = ex;
-        }
-        const uint32_t tot = s[kBlock - 1];
+        s[threadIdx.x] += t;
         __syncthreads();
-        carry += tot;
     }
-    if (threadIdx.x == 0) off[kBins] = carry;
+    uint32_t acc = s[threadIdx.x] - tot;
+    for (uint32_t i = lo; i < hi; i++) {
+        const uint32_t v = tmp[i];
+        tmp[i] = acc;
+        if (i % nblocks == 0) off[i / nblocks] = acc;
+        acc += v;
+    }
+    if (threadIdx.x == kBlock - 1) off[kBins] = s[kBlock - 1];
 }
 
 __global__ __launch_bounds__(kBlock) void k_sched_scatter(int32_t n, const uint32_t *in_cnt,

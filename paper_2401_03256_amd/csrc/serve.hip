@@ -55,7 +55,7 @@ struct CtlGather {
 };
 static_assert(sizeof(Ctl) % 4 == 0, "control blocks are copied as words");
 
-__global__ __launch_bounds__(kBlock) void k_iter_multi(MultiArgs m)
+__global__ __launch_bounds__(kBlock, DFPR_ITER_WAVES_PER_SIMD) void k_iter_multi(MultiArgs m)
 {
     __shared__ IterShared sh;
     const uint32_t b = blockIdx.x;
