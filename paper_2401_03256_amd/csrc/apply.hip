@@ -24,6 +24,7 @@
 //      row to its new place with fresh free space, and the merge is run
 //      again from the round that did not fit.
 #include <algorithm>
+#include <cstring>
 #include <vector>
 
 #include "common.h"
@@ -111,33 +112,44 @@ __global__ void k_apply_keys(ApplyArgs a)
     a.keys[1][i] = ((uint64_t)s << 33) | ((uint64_t)(uint32_t)d << 1) | t;   // out-CSR: row = src
 }
 
-// Bitonic sort of one tile of kTile keys in LDS; grid.y = orientation.
-__global__ __launch_bounds__(kBlock) void k_tile_sort(uint64_t *k0, uint64_t *k1, uint32_t len)
+// Sort tiles of up to kTile keys, in -> out; grid.y = orientation.  Rank
+// sort: workgroup (t, q) loads tile t into LDS and ranks keys
+// q * kBlock .. q * kBlock + kBlock - 1 of it, one per thread, by counting the
+// keys that order before it (equal keys by position, so the sort is
+// stable); each key is stored at its rank.  No barriers inside the count,
+// and kTile / kBlock workgroups share a tile.
+__global__ __launch_bounds__(kBlock) void k_tile_sort(const uint64_t *in0, uint64_t *out0,
+                                                      const uint64_t *in1, uint64_t *out1,
+                                                      uint32_t len)
 {
+    constexpr uint32_t kParts = kTile / kBlock;
+    constexpr int kStep = 8;
     __shared__ uint64_t s[kTile];
-    uint64_t *keys = blockIdx.y ? k1 : k0;
-    const uint32_t base = blockIdx.x * kTile;
-    for (uint32_t i = threadIdx.x; i < kTile; i += kBlock)
-        s[i] = base + i < len ? keys[base + i] : kSentinel;
+    const uint64_t *in = blockIdx.y ? in1 : in0;
+    uint64_t *out = blockIdx.y ? out1 : out0;
+    const uint32_t base = (blockIdx.x / kParts) * kTile;
+    const uint32_t cnt = min((uint32_t)kTile, len - base);
+    const uint32_t i = (blockIdx.x % kParts) * kBlock + threadIdx.x;
+    if ((blockIdx.x % kParts) * kBlock >= cnt) return;      // uniform
+    for (uint32_t k = threadIdx.x; k < cnt; k += kBlock) s[k] = in[base + k];
     __syncthreads();
-    for (uint32_t k = 2; k <= kTile; k <<= 1) {
-        for (uint32_t j = k >> 1; j > 0; j >>= 1) {
-            for (uint32_t i = threadIdx.x; i < kTile; i += kBlock) {
-                uint32_t ixj = i ^ j;
-                if (ixj > i) {
-                    uint64_t x = s[i], y = s[ixj];
-                    bool up = (i & k) == 0;
-                    if ((x > y) == up) {
-                        s[i] = y;
-                        s[ixj] = x;
-                    }
-                }
-            }
-            __syncthreads();
-        }
+    if (i >= cnt) return;
+    const uint64_t mine = s[i];
+    uint32_t rank = 0;
+    uint32_t j0 = 0;
+    for (; j0 + kStep <= cnt; j0 += kStep) {
+        uint64_t y[kStep];
+#pragma unroll
+        for (int u = 0; u < kStep; u++) y[u] = s[j0 + u];
+#pragma unroll
+        for (int u = 0; u < kStep; u++)
+            rank += (y[u] < mine || (y[u] == mine && j0 + u < i)) ? 1u : 0u;
     }
-    for (uint32_t i = threadIdx.x; i < kTile; i += kBlock)
-        if (base + i < len) keys[base + i] = s[i];
+    for (uint32_t j = j0; j < cnt; j++) {
+        const uint64_t y = s[j];
+        rank += (y < mine || (y == mine && j < i)) ? 1u : 0u;
+    }
+    out[base + rank] = mine;
 }
 
 // Merge sorted runs of `width` keys pairwise: in -> out.
@@ -529,8 +541,14 @@ int stage_batch(dfpr_graph *g, int64_t n_del, const int32_t *ds, const int32_t *
                 const int32_t **did)
 {
     ApplyBufs &ap = g->ap;
+    hipStream_t s = g->stream;
     // the batch, then room for the two source lists of the initial marking
     const uint64_t need = 4 * (uint64_t)(n_del + n_ins);
+    const int64_t tot = 2 * (n_del + n_ins);
+    // work still reading the staging buffers is finished before they are
+    // replaced or refilled
+    if (need > ap.batch_cap || !ap.batch_dev || (!on_device && tot > 0))
+        DFPR_HIP(hipStreamSynchronize(s));
     if (need > ap.batch_cap || !ap.batch_dev) {
         (void)hipFree(ap.batch_dev);
         ap.batch_dev = nullptr;
@@ -542,15 +560,26 @@ int stage_batch(dfpr_graph *g, int64_t n_del, const int32_t *ds, const int32_t *
     int32_t *dst[4] = {p, p + n_del, p + 2 * n_del, p + 2 * n_del + n_ins};
     const int32_t *src[4] = {ds, dd, is, id};
     const int64_t len[4] = {n_del, n_del, n_ins, n_ins};
-    hipStream_t s = g->stream;
-    for (int k = 0; k < 4; k++) {
-        if (!len[k]) continue;
-        const int32_t *from = src[k];
-        if (!on_device) {
-            DFPR_HIP(hipMemcpyAsync(dst[k], src[k], len[k] * 4, hipMemcpyHostToDevice, s));
-            from = dst[k];
+    if (!on_device && tot > 0) {
+        // one copy through a pinned buffer, then the ids mapped in place
+        if ((uint64_t)tot > ap.batch_host_cap || !ap.batch_host) {
+            if (ap.batch_host) (void)hipHostFree(ap.batch_host);
+            ap.batch_host = nullptr;
+            ap.batch_host_cap = 0;
+            const uint64_t cap = std::max<uint64_t>(tot, 8192);
+            DFPR_HIP(hipHostMalloc((void **)&ap.batch_host, cap * 4, hipHostMallocDefault));
+            ap.batch_host_cap = cap;
         }
-        const int rc = map_ids(g, from, dst[k], len[k]);
+        int64_t at = 0;
+        for (int k = 0; k < 4; k++) {
+            if (len[k]) std::memcpy(ap.batch_host + at, src[k], (size_t)len[k] * 4);
+            at += len[k];
+        }
+        DFPR_HIP(hipMemcpyAsync(p, ap.batch_host, (size_t)tot * 4, hipMemcpyHostToDevice, s));
+        const int rc = map_ids(g, p, p, tot);
+        if (rc) return rc;
+    } else if (tot > 0) {
+        const int rc = map_ids4(g, src, len, p);
         if (rc) return rc;
     }
     *dds = dst[0];
@@ -667,8 +696,9 @@ int apply_batch_impl(dfpr_graph *g, int64_t n_del, const int32_t *ds, const int3
     k_apply_reset<<<1, 1, 0, s>>>(g->ctl);
     k_apply_keys<<<grid_for(B), kBlock, 0, s>>>(a);
     const unsigned tiles = (B + kTile - 1) / kTile;
-    k_tile_sort<<<dim3(tiles, 2), kBlock, 0, s>>>(a.keys[0], a.keys[1], B);
-    int pp = 0;
+    k_tile_sort<<<dim3(tiles * (kTile / kBlock), 2), kBlock, 0, s>>>(
+        g->ap.keys[0][0], g->ap.keys[0][1], g->ap.keys[1][0], g->ap.keys[1][1], B);
+    int pp = 1;
     for (uint32_t w = kTile; w < B; w *= 2) {
         k_merge_pass<<<dim3(grid_for(B), 2), kBlock, 0, s>>>(
             g->ap.keys[0][pp], g->ap.keys[0][pp ^ 1], g->ap.keys[1][pp], g->ap.keys[1][pp ^ 1], B,

@@ -102,8 +102,10 @@ struct ApplyBufs {
     int32_t *slab = nullptr;        // row copies of big rows
     uint64_t slab_ints = 0;
     uint64_t slab_stride = 0;
-    int32_t *batch_dev = nullptr;   // staging for host batches (4 arrays)
+    int32_t *batch_dev = nullptr;   // batch in internal ids (4 arrays) + marking lists
     uint64_t batch_cap = 0;
+    int32_t *batch_host = nullptr;  // pinned staging of a host batch (4 arrays)
+    uint64_t batch_host_cap = 0;
 };
 
 }  // namespace dfpr
@@ -135,7 +137,8 @@ struct dfpr_graph {
     uint32_t *sched_tmp = nullptr;    // per-workgroup class counts for the build
     int sched_dirty = 1;              // in-degrees changed since the build
     dfpr::Ctl *ctl = nullptr;         // device
-    dfpr::Ctl *ctl_host = nullptr;    // pinned mirror
+    dfpr::Ctl *ctl_host = nullptr;    // pinned, coherent mirror (written by the kernels
+                                      // that end a loop step, or copied)
     dfpr::IterBufs it;
     dfpr::ApplyBufs ap;
     float *C32[2] = {};               // FP32 contributions (precision form)
@@ -175,6 +178,7 @@ int check_ids_host(int32_t n, int64_t len, const int32_t *a, const int32_t *b);
 
 // renumbering at the boundary (graph.hip); enqueued on g->stream
 int map_ids(dfpr_graph *g, const int32_t *in, int32_t *out, int64_t len);
+int map_ids4(dfpr_graph *g, const int32_t *const in[4], const int64_t len[4], int32_t *out);
 int ranks_to_caller(const dfpr_graph *g, const double *Rint, double *out, int out_dev);
 int ranks_from_caller(const dfpr_graph *g, const double *in, int in_dev, double *Rint);
 

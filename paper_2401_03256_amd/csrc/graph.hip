@@ -154,6 +154,32 @@ static inline unsigned grid_of(int64_t items)
     return (unsigned)std::max<int64_t>(1, (items + kBlock - 1) / kBlock);
 }
 
+// Four arrays of lengths l0..l3 mapped into consecutive ranges of `out`.
+__global__ void k_map_ids4(int32_t n, const int32_t *ext2int, const int32_t *i0,
+                           const int32_t *i1, const int32_t *i2, const int32_t *i3, int64_t l0,
+                           int64_t l1, int64_t l2, int64_t l3, int32_t *out)
+{
+    int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= l0 + l1 + l2 + l3) return;
+    const int64_t k = i;
+    const int32_t *src = i0;
+    if (i >= l0) { i -= l0; src = i1;
+        if (i >= l1) { i -= l1; src = i2;
+            if (i >= l2) { i -= l2; src = i3; } } }
+    const int32_t x = src[i];
+    out[k] = (x >= 0 && x < n) ? ext2int[x] : -1;
+}
+
+int map_ids4(dfpr_graph *g, const int32_t *const in[4], const int64_t len[4], int32_t *out)
+{
+    const int64_t tot = len[0] + len[1] + len[2] + len[3];
+    if (tot <= 0) return DFPR_OK;
+    k_map_ids4<<<grid_of(tot), kBlock, 0, g->stream>>>(g->n, g->ext2int, in[0], in[1], in[2],
+                                                       in[3], len[0], len[1], len[2], len[3], out);
+    DFPR_HIP(hipGetLastError());
+    return DFPR_OK;
+}
+
 // Ids outside [0, n) become -1, which every later check rejects.  `in` may
 // equal `out`.
 int map_ids(dfpr_graph *g, const int32_t *in, int32_t *out, int64_t len)
@@ -270,6 +296,7 @@ void dfpr_free_graph(dfpr_graph *g)
     (void)hipFree(g->ext2int);
     (void)hipFree(g->int2ext);
     if (g->ctl_host) (void)hipHostFree(g->ctl_host);
+    if (g->ap.batch_host) (void)hipHostFree(g->ap.batch_host);
     (void)hipFree(g->it.dr_part);
     (void)hipFree(g->it.rmax_part);
     (void)hipFree(g->it.cnt_part);
@@ -345,7 +372,7 @@ int dfpr_load_graph(int32_t n, int64_t m, const int32_t *src, const int32_t *dst
             rc = set_error(DFPR_E_DEVICE, "map upload failed");
     }
     if (!rc) {
-        hipError_t e = hipHostMalloc((void **)&g->ctl_host, sizeof(Ctl), hipHostMallocDefault);
+        hipError_t e = hipHostMalloc((void **)&g->ctl_host, sizeof(Ctl), hipHostMallocCoherent);
         if (e != hipSuccess) rc = hip_fail(e, "hipHostMalloc");
     }
     if (!rc) {

@@ -52,6 +52,7 @@ struct IterArgs {
     const int32_t *sched;       // class schedule of all vertices
     const uint32_t *sched_off;  // kBins + 1 offsets
     Ctl *ctl;
+    Ctl *mirror;                // host-visible copy written after each step, or NULL
     double *dr_part;
     double *rmax_part;          // per-workgroup largest new rank
     unsigned long long *cnt_part;   // kCounters per workgroup
@@ -570,6 +571,7 @@ __device__ inline void final_body(const IterArgs &a, uint32_t active, bool df, b
             if (conv || a.it + 1 >= a.max_iters) ctl->done = 1;
         }
         ctl->prev_linf = dr;
+        if (a.mirror) __builtin_memcpy(a.mirror, ctl, sizeof(Ctl));
     }
 }
 

@@ -107,7 +107,7 @@ __global__ void k_reset(Ctl *ctl)
 
 // Freeze the lists built by the marking as iteration 0's snapshot and pick
 // the walk of the first iteration.
-__global__ void k_snap(Ctl *ctl, int32_t max_iters, uint32_t sparse_limit, int dense)
+__global__ void k_snap(Ctl *ctl, int32_t max_iters, uint32_t sparse_limit, int dense, Ctl *mirror)
 {
     if (threadIdx.x == 0 && blockIdx.x == 0) {
         unsigned long long tot = 0;
@@ -117,6 +117,7 @@ __global__ void k_snap(Ctl *ctl, int32_t max_iters, uint32_t sparse_limit, int d
         }
         ctl->dense = (dense || ctl->dense || tot > sparse_limit) ? 1 : 0;
         ctl->done = (ctl->err || max_iters <= 0) ? 1 : 0;
+        if (mirror) __builtin_memcpy(mirror, ctl, sizeof(Ctl));
     }
 }
 
@@ -149,34 +150,34 @@ __global__ void k_copy2(int32_t n, const double *a, double *a2, const double *b,
     }
 }
 
-// Class schedule of all vertices: a stable counting sort by class, in three
-// passes (per-workgroup class counts, one scan, scatter).  Thread t of
-// workgroup w owns the kSchedChunk/kBlock consecutive vertices starting at
-// w * kSchedChunk + t * (kSchedChunk / kBlock).
-__device__ inline void sched_thread_counts(int32_t n, const uint32_t *in_cnt, uint32_t v0,
-                                           uint32_t (&cnt)[kBins])
-{
-#pragma unroll
-    for (int b = 0; b < kBins; b++) cnt[b] = 0;
-    for (int j = 0; j < kSchedChunk / kBlock; j++) {
-        const uint32_t v = v0 + j;
-        if (v < (uint32_t)n) cnt[bin_of(in_cnt[v])]++;
-    }
-}
+// Schedule build: a stable counting sort of the vertices by in-degree
+// class.  Workgroup w owns vertices [w * kSchedChunk, (w + 1) * kSchedChunk)
+// and visits them in rounds of kBlock consecutive ids, so loads and the
+// per-class runs of stores are coalesced.
+constexpr int kScanThreads = 1024;
 
 __global__ __launch_bounds__(kBlock) void k_sched_count(int32_t n, const uint32_t *in_cnt,
                                                         uint32_t *tmp, uint32_t nblocks)
 {
-    __shared__ uint32_t s[kBins][kBlock];
+    __shared__ uint32_t s[kWavesPerBlock][kBins];
+    const int lane = lane_id(), wave = threadIdx.x / kWave;
     uint32_t cnt[kBins];
-    sched_thread_counts(n, in_cnt, blockIdx.x * kSchedChunk + threadIdx.x * (kSchedChunk / kBlock),
-                        cnt);
 #pragma unroll
-    for (int b = 0; b < kBins; b++) s[b][threadIdx.x] = cnt[b];
+    for (int b = 0; b < kBins; b++) cnt[b] = 0;
+    const uint32_t base = blockIdx.x * (uint32_t)kSchedChunk;
+    for (uint32_t r = 0; r < (uint32_t)kSchedChunk; r += kBlock) {
+        const uint32_t v = base + r + threadIdx.x;
+        const int c = v < (uint32_t)n ? bin_of(in_cnt[v]) : kBins;
+#pragma unroll
+        for (int b = 0; b < kBins; b++) cnt[b] += (uint32_t)__popcll(__ballot(c == b));
+    }
+    if (lane == 0)
+#pragma unroll
+        for (int b = 0; b < kBins; b++) s[wave][b] = cnt[b];
     __syncthreads();
     if (threadIdx.x < kBins) {
         uint32_t t = 0;
-        for (int i = 0; i < kBlock; i++) t += s[threadIdx.x][i];
+        for (int w = 0; w < kWavesPerBlock; w++) t += s[w][threadIdx.x];
         tmp[threadIdx.x * nblocks + blockIdx.x] = t;
     }
 }
@@ -184,62 +185,82 @@ __global__ __launch_bounds__(kBlock) void k_sched_count(int32_t n, const uint32_
 // Exclusive scan of the class-major count table; off[b] = start of class b.
 // Each thread sums a contiguous run of the table, the run totals are
 // scanned across the workgroup, and each thread then rewrites its run.
-__global__ __launch_bounds__(kBlock) void k_sched_scan(uint32_t *tmp, uint32_t nblocks,
-                                                       uint32_t *off)
+__global__ __launch_bounds__(kScanThreads) void k_sched_scan(uint32_t *tmp, uint32_t nblocks,
+                                                             uint32_t *off)
 {
-    __shared__ uint32_t s[kBlock];
+    __shared__ uint32_t s[kScanThreads];
     const uint32_t len = nblocks * kBins;
-    const uint32_t run = (len + kBlock - 1) / kBlock;
+    const uint32_t run = (len + kScanThreads - 1) / kScanThreads;
     const uint32_t lo = min(len, threadIdx.x * run), hi = min(len, lo + run);
+    // eight loads in flight per thread
     uint32_t tot = 0;
-    for (uint32_t i = lo; i < hi; i++) tot += tmp[i];
+    for (uint32_t i0 = lo; i0 < hi; i0 += 8) {
+        uint32_t x[8];
+#pragma unroll
+        for (int u = 0; u < 8; u++) x[u] = i0 + u < hi ? tmp[i0 + u] : 0u;
+#pragma unroll
+        for (int u = 0; u < 8; u++) tot += x[u];
+    }
     s[threadIdx.x] = tot;
     __syncthreads();
-    for (int o = 1; o < kBlock; o <<= 1) {
+    for (int o = 1; o < kScanThreads; o <<= 1) {
         const uint32_t t = threadIdx.x >= (uint32_t)o ? s[threadIdx.x - o] : 0;
         __syncthreads();
         s[threadIdx.x] += t;
         __syncthreads();
     }
     uint32_t acc = s[threadIdx.x] - tot;
-    for (uint32_t i = lo; i < hi; i++) {
-        const uint32_t v = tmp[i];
-        tmp[i] = acc;
-        if (i % nblocks == 0) off[i / nblocks] = acc;
-        acc += v;
+    for (uint32_t i0 = lo; i0 < hi; i0 += 8) {
+        uint32_t x[8];
+#pragma unroll
+        for (int u = 0; u < 8; u++) x[u] = i0 + u < hi ? tmp[i0 + u] : 0u;
+#pragma unroll
+        for (int u = 0; u < 8; u++) {
+            const uint32_t i = i0 + u;
+            if (i < hi) {
+                tmp[i] = acc;
+                if (i % nblocks == 0) off[i / nblocks] = acc;
+            }
+            acc += x[u];
+        }
     }
-    if (threadIdx.x == kBlock - 1) off[kBins] = s[kBlock - 1];
+    if (threadIdx.x == kScanThreads - 1) off[kBins] = s[kScanThreads - 1];
 }
 
 __global__ __launch_bounds__(kBlock) void k_sched_scatter(int32_t n, const uint32_t *in_cnt,
                                                           const uint32_t *tmp, uint32_t nblocks,
                                                           int32_t *sched)
 {
-    __shared__ uint32_t s[kBins][kBlock];
-    const uint32_t v0 = blockIdx.x * kSchedChunk + threadIdx.x * (kSchedChunk / kBlock);
-    uint32_t cnt[kBins];
-    sched_thread_counts(n, in_cnt, v0, cnt);
-#pragma unroll
-    for (int b = 0; b < kBins; b++) s[b][threadIdx.x] = cnt[b];
+    __shared__ uint32_t s_w[kWavesPerBlock][kBins];   // per-wave class counts of a round
+    __shared__ uint32_t s_run[kBins];                 // next position of each class
+    const int lane = lane_id(), wave = threadIdx.x / kWave;
+    const unsigned long long below = (1ull << lane) - 1ull;
+    if (threadIdx.x < kBins) s_run[threadIdx.x] = tmp[threadIdx.x * nblocks + blockIdx.x];
     __syncthreads();
-    // inclusive scan per class over the threads of the workgroup
-    for (int o = 1; o < kBlock; o <<= 1) {
-        uint32_t t[kBins];
+    const uint32_t base = blockIdx.x * (uint32_t)kSchedChunk;
+    for (uint32_t r = 0; r < (uint32_t)kSchedChunk; r += kBlock) {
+        const uint32_t v = base + r + threadIdx.x;
+        const int c = v < (uint32_t)n ? bin_of(in_cnt[v]) : kBins;
+        uint32_t rank = 0;
 #pragma unroll
-        for (int b = 0; b < kBins; b++)
-            t[b] = threadIdx.x >= (uint32_t)o ? s[b][threadIdx.x - o] : 0;
+        for (int b = 0; b < kBins; b++) {
+            const unsigned long long m = __ballot(c == b);
+            if (c == b) rank = (uint32_t)__popcll(m & below);
+            if (lane == 0) s_w[wave][b] = (uint32_t)__popcll(m);
+        }
         __syncthreads();
-#pragma unroll
-        for (int b = 0; b < kBins; b++) s[b][threadIdx.x] += t[b];
+        if (c < kBins) {
+            uint32_t pos = s_run[c] + rank;
+            for (int w = 0; w < wave; w++) pos += s_w[w][c];
+            sched[pos] = (int32_t)v;
+        }
         __syncthreads();
-    }
-    uint32_t pos[kBins];
-#pragma unroll
-    for (int b = 0; b < kBins; b++)
-        pos[b] = tmp[b * nblocks + blockIdx.x] + s[b][threadIdx.x] - cnt[b];
-    for (int j = 0; j < kSchedChunk / kBlock; j++) {
-        const uint32_t v = v0 + j;
-        if (v < (uint32_t)n) sched[pos[bin_of(in_cnt[v])]++] = (int32_t)v;
+        if (threadIdx.x < kBins) {
+            uint32_t t = 0;
+            for (int w = 0; w < kWavesPerBlock; w++) t += s_w[w][threadIdx.x];
+            s_run[threadIdx.x] += t;
+        }
+        __syncthreads();
     }
 }
 
@@ -366,20 +387,43 @@ __global__ __launch_bounds__(kBlock) void k_mark_initial(IterArgs a, int64_t nd,
 
 // End of a Dynamic Frontier call: copy the rows processed in this call from
 // the result buffer into the other buffer and count the marked vertices.
+// A call that stayed on the class lists visits the listed vertices (every
+// mark of the call was appended); otherwise all vertices by stamp.
 __global__ __launch_bounds__(kBlock) void k_finish(int32_t n, const uint32_t *stamp, uint32_t lo,
                                                    uint32_t hi, const double *Rres, double *Roth,
-                                                   const double *Cres, double *Coth, Ctl *ctl)
+                                                   const double *Cres, double *Coth, Ctl *ctl,
+                                                   const int32_t *bins, int32_t n_stride)
 {
     __shared__ unsigned long long s_cnt;
     if (threadIdx.x == 0) s_cnt = 0;
     __syncthreads();
     unsigned long long mine = 0;
-    for (int32_t v = blockIdx.x * blockDim.x + threadIdx.x; v < n; v += gridDim.x * blockDim.x) {
-        const uint32_t st = stamp[v];
-        if (st >= lo && st <= hi) {
+    const int64_t t0 = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    const int64_t step = (int64_t)gridDim.x * blockDim.x;
+    if (!ctl->dense) {
+        uint32_t len[kBins];
+        int64_t tot = 0;
+        for (int b = 0; b < kBins; b++) {
+            len[b] = ctl->live[b];
+            tot += len[b];
+        }
+        for (int64_t t = t0; t < tot; t += step) {
+            int b = 0;
+            int64_t r = t;
+            while (r >= len[b]) r -= len[b++];
+            const int32_t v = bins[(int64_t)b * n_stride + r];
             mine++;
             Roth[v] = Rres[v];
             Coth[v] = Cres[v];
+        }
+    } else {
+        for (int64_t v = t0; v < n; v += step) {
+            const uint32_t st = stamp[v];
+            if (st >= lo && st <= hi) {
+                mine++;
+                Roth[v] = Rres[v];
+                Coth[v] = Cres[v];
+            }
         }
     }
     for (int off = kWave / 2; off > 0; off >>= 1) mine += __shfl_xor(mine, off, kWave);
@@ -520,6 +564,7 @@ IterArgs iter_args(dfpr_graph *g, const dfpr_params &p, uint32_t sbase)
     a.sched = g->sched;
     a.sched_off = g->sched_off;
     a.ctl = g->ctl;
+    a.mirror = g->ctl_host;
     a.dr_part = g->it.dr_part;
     a.rmax_part = g->it.rmax_part;
     a.cnt_part = g->it.cnt_part;
@@ -541,7 +586,7 @@ static int ensure_schedule(dfpr_graph *g)
     const uint32_t nb = (uint32_t)((g->n + kSchedChunk - 1) / kSchedChunk);
     hipStream_t s = g->stream;
     k_sched_count<<<nb, kBlock, 0, s>>>(g->n, g->csr[0].cnt, g->sched_tmp, nb);
-    k_sched_scan<<<1, kBlock, 0, s>>>(g->sched_tmp, nb, g->sched_off);
+    k_sched_scan<<<1, kScanThreads, 0, s>>>(g->sched_tmp, nb, g->sched_off);
     k_sched_scatter<<<nb, kBlock, 0, s>>>(g->n, g->csr[0].cnt, g->sched_tmp, nb, g->sched);
     DFPR_HIP(hipGetLastError());
     g->sched_dirty = 0;
@@ -570,11 +615,29 @@ static int take_base(dfpr_graph *g, int32_t max_iters, uint32_t *base)
 // chunks; between chunks the host reads the control block once and sizes
 // the next chunk from the observed geometric decay of Delta R, so few
 // launches run after convergence.
+// Workgroups for the next chunk of a call still on the class lists: what
+// the current lists need, times four and plus 64 for the frontier to grow
+// within the chunk, at least one per CU.  Any grid gives the same result
+// (the work is grid-strided); a small frontier just skips empty workgroups.
+static uint32_t sparse_grid(const dfpr_graph *g, const Ctl &c)
+{
+    uint64_t nwu = 0;
+    for (int b = 0; b < kBins - 1; b++) {
+        const uint64_t rows = kWave / group_of(b);
+        nwu += (c.live[b] + rows - 1) / rows;
+    }
+    const uint64_t need = std::max<uint64_t>(c.live[kBins - 1], (nwu + kWavesPerBlock - 1) /
+                                                                     kWavesPerBlock);
+    const uint64_t lo = std::min<uint64_t>(256, (uint64_t)g->grid);
+    return (uint32_t)std::min<uint64_t>(g->grid, std::max<uint64_t>(lo, need * 4 + 64));
+}
+
 static int run_loop(dfpr_graph *g, const dfpr_params &p, bool df, bool f32, uint32_t sbase,
                     int it0, int base, int *res_buf)
 {
     IterArgs a = iter_args(g, p, sbase);
     int it = it0, chunk = 4;
+    uint32_t gsz = (uint32_t)g->grid;
     double prev_dr = -1.0;
     int prev_it = it0;
     *res_buf = base;
@@ -591,14 +654,15 @@ static int run_loop(dfpr_graph *g, const dfpr_params &p, bool df, bool f32, uint
             a.C32c = g->C32[src];
             a.C32n = g->C32[src ^ 1];
             a.it = i;
-            if (!df) k_iter<false, false><<<g->grid, kBlock, 0, g->stream>>>(a);
-            else if (f32) k_iter<true, true><<<g->grid, kBlock, 0, g->stream>>>(a);
-            else k_iter<true, false><<<g->grid, kBlock, 0, g->stream>>>(a);
-            k_final<<<1, kBlock, 0, g->stream>>>(a, (uint32_t)g->grid, df ? 1 : 0, f32 ? 1 : 0);
+            if (!df) k_iter<false, false><<<gsz, kBlock, 0, g->stream>>>(a);
+            else if (f32) k_iter<true, true><<<gsz, kBlock, 0, g->stream>>>(a);
+            else k_iter<true, false><<<gsz, kBlock, 0, g->stream>>>(a);
+            k_final<<<1, kBlock, 0, g->stream>>>(a, gsz, df ? 1 : 0, f32 ? 1 : 0);
         }
         DFPR_HIP(hipGetLastError());
         if (g->prof.enabled) DFPR_HIP(hipEventRecord(g->evk1, g->stream));
-        DFPR_HIP(hipMemcpyAsync(g->ctl_host, g->ctl, sizeof(Ctl), hipMemcpyDeviceToHost, g->stream));
+        // k_snap and every k_final that ran an iteration left the control
+        // block in the host mirror
         DFPR_HIP(hipStreamSynchronize(g->stream));
         if (g->prof.enabled) {
             float ms = 0.f;
@@ -608,6 +672,7 @@ static int run_loop(dfpr_graph *g, const dfpr_params &p, bool df, bool f32, uint
         }
         if (g->ctl_host->done || (f32 && g->ctl_host->phase_end)) break;
         it += k;
+        gsz = df && !g->ctl_host->dense ? sparse_grid(g, *g->ctl_host) : (uint32_t)g->grid;
         const double dr = g->ctl_host->final_linf;
         const int its = g->ctl_host->iterations;
         int next = std::min(chunk * 2, 32);
@@ -697,7 +762,7 @@ static int full_sweeps(dfpr_graph *g, const dfpr_params *pp, const double *prev,
     rc = ensure_schedule(g);
     if (rc) return rc;
     k_reset<<<1, 1, 0, s>>>(g->ctl);
-    k_snap<<<1, 1, 0, s>>>(g->ctl, p.max_iters, g->sparse_limit, 1);
+    k_snap<<<1, 1, 0, s>>>(g->ctl, p.max_iters, g->sparse_limit, 1, g->ctl_host);
     DFPR_HIP(hipGetLastError());
     int res = cur;
     g->refine_sweeps = 0;
@@ -748,7 +813,7 @@ int df_begin(dfpr_graph *g, const dfpr_params &p, int64_t nd, const int32_t *bds
         k_validate<<<blocks_for(nd + ni), kBlock, 0, s>>>(n, nd, bds, bdd, ni, bis, bid, g->ctl);
         launch_initial_marking(g, a, nd, bds, bdd, ni, bis, dense);
     }
-    k_snap<<<1, 1, 0, s>>>(g->ctl, p.max_iters, g->sparse_limit, dense);
+    k_snap<<<1, 1, 0, s>>>(g->ctl, p.max_iters, g->sparse_limit, dense, g->ctl_host);
     if (p.precision == DFPR_FP32_KAHAN)
         k_c32_init<<<blocks_for(n), kBlock, 0, s>>>(n, g->C[cur], g->C32[0], g->C32[1]);
     DFPR_HIP(hipGetLastError());
@@ -787,7 +852,7 @@ int df_finish(dfpr_graph *g, uint32_t sbase, int res, int32_t iters)
     const int32_t n = g->n;
     k_finish<<<std::min(blocks_for(n), 2048), kBlock, 0, g->stream>>>(
         n, g->stamp, sbase, sbase + (uint32_t)iters, g->R[res], g->R[res ^ 1], g->C[res],
-        g->C[res ^ 1], g->ctl);
+        g->C[res ^ 1], g->ctl, g->bins, g->n);
     DFPR_HIP(hipGetLastError());
     g->cur = res;
     g->last_base = sbase;

@@ -245,6 +245,7 @@ static int launch_chunk(dfpr_server *srv, std::vector<Slot *> &cs, int K)
             GraphEntry &ge = srv->graphs[q.gid];
             dfpr_graph *g = ge.g;
             IterArgs a = iter_args(g, ge.p, sl.sbase);
+            a.mirror = nullptr;       // the slots' blocks come back gathered
             const int it = sl.it + j;
             const int src = sl.base ^ ((it - sl.it0) & 1);
             a.Rc = g->R[src];
