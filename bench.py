@@ -32,9 +32,10 @@ sys.path.insert(0, ROOT)
 METRIC = "GTEPS (edges/s) + update latency p50/p99 per batch; FP32 vs FP64 at 1e-9 L∞"
 HBM_PEAK_GBS = 8000.0
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_iter_traffic.json")
-# sources whose text fixes the iteration kernel's code
+# sources whose text fixes the iteration kernel's code, launch shape and
+# the vertex numbering it runs on (all of which move its memory traffic)
 KERNEL_SRC = [os.path.join(ROOT, "paper_2401_03256_amd", "csrc", f)
-              for f in ("iter.h", "common.h", "rank.hip")]
+              for f in ("iter.h", "common.h", "rank.hip", "graph.hip")]
 
 
 def log(*a):
@@ -220,10 +221,14 @@ def main():
     copy_gbs = copy_bandwidth(torch)
     log(f"achievable copy bandwidth {copy_gbs:.0f} GB/s")
     roofline = {
-        "bound": "hbm", "kernel": "k_iter<true> (pull + Delta r + L-inf + expand)",
+        "bound": "hbm", "kernel": "k_iter<true, false> (FP64 pull + Delta r + L-inf + expand)",
         "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
         "frac": round(achieved / HBM_PEAK_GBS, 4),
-        "traffic": None if tb is None else round(tb, 1),
+        # measured HBM bytes per launch (committed counter runs on these
+        # sources) over the same per-launch time as `achieved`
+        "traffic": (None if tb is None or prof.ms <= 0 else
+                    round(tb / (prof.ms / 1e3 / max(prof.launches, 1)) / 1e9, 1)),
+        "traffic_bytes_per_launch": None if tb is None else round(tb, 1),
         "launches": prof.launches, "avg_launch_us": round(prof.ms * 1e3 / max(prof.launches, 1), 2),
         "algorithmic_bytes_per_launch": round(prof.bytes / max(prof.launches, 1), 1),
         "kernel_gteps": round(prof.edges / prof.ms / 1e6, 2) if prof.ms > 0 else None,

@@ -18,6 +18,7 @@ constexpr int kBins = 7;               // in-degree classes of the pull
 constexpr int kMaxGrid = 8192;         // upper bound on iteration-kernel grids
 constexpr uint64_t kSentinel = ~0ull;  // batch key of an entry that changes nothing
 constexpr int kCounters = 4;           // rows, in-edges, expanded rows, their out-edges
+constexpr int kLoopChunk = 64;         // most iteration launches between two host looks
 
 // In-degree classes.  A row of class b < 6 is reduced by a group of
 // group_of(b) lanes of one wave; class 6 rows take a whole workgroup.
@@ -146,7 +147,7 @@ struct dfpr_graph {
     hipStream_t stream = nullptr;
     hipStream_t own_stream = nullptr;
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
-    hipEvent_t evk0 = nullptr, evk1 = nullptr;   // around chunks of iteration launches
+    hipEvent_t evk[2 * dfpr::kLoopChunk] = {};   // around each iteration launch (profiling)
     dfpr::Profile prof;
     int64_t prof_base[4] = {0, 0, 0, 0};   // counters already added to prof
     int32_t refine_sweeps = 0;        // FP64 iterations after the FP32 phase

@@ -311,8 +311,8 @@ void dfpr_free_graph(dfpr_graph *g)
     (void)hipFree(g->ap.batch_dev);
     if (g->ev0) (void)hipEventDestroy(g->ev0);
     if (g->ev1) (void)hipEventDestroy(g->ev1);
-    if (g->evk0) (void)hipEventDestroy(g->evk0);
-    if (g->evk1) (void)hipEventDestroy(g->evk1);
+    for (hipEvent_t e : g->evk)
+        if (e) (void)hipEventDestroy(e);
     if (g->own_stream) (void)hipStreamDestroy(g->own_stream);
     delete g;
 }
@@ -379,8 +379,8 @@ int dfpr_load_graph(int32_t n, int64_t m, const int32_t *src, const int32_t *dst
         hipError_t e = hipStreamCreateWithFlags(&g->own_stream, hipStreamNonBlocking);
         if (e == hipSuccess) e = hipEventCreate(&g->ev0);
         if (e == hipSuccess) e = hipEventCreate(&g->ev1);
-        if (e == hipSuccess) e = hipEventCreate(&g->evk0);
-        if (e == hipSuccess) e = hipEventCreate(&g->evk1);
+        for (hipEvent_t &ev : g->evk)
+            if (e == hipSuccess) e = hipEventCreate(&ev);
         if (e != hipSuccess) rc = hip_fail(e, "stream/event");
         g->stream = g->own_stream;
     }

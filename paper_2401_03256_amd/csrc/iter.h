@@ -17,14 +17,13 @@ namespace dfpr {
 #ifndef DFPR_ITER_WAVES_PER_SIMD
 #define DFPR_ITER_WAVES_PER_SIMD 5
 #endif
+// Index loads are streamed once per iteration; marking them non-temporal
+// leaves more of L2 to the gathered contributions (4% on R-MAT scale 22;
+// the same marking on the gathers themselves halves the speed).
 #ifndef DFPR_NT_IDX
-#define DFPR_NT_IDX 0
-#endif
-#ifndef DFPR_XCD_MAP
-#define DFPR_XCD_MAP 0
+#define DFPR_NT_IDX 1
 #endif
 constexpr int kUnroll = DFPR_UNROLL;   // loads in flight per lane and round
-constexpr int kXcds = 8;               // workgroup i runs on XCD i mod 8
 
 // Streamed index loads: marked non-temporal so that they do not displace
 // gathered contributions from L2.
@@ -445,44 +444,13 @@ __device__ inline void iter_body(const IterArgs &a, uint32_t blk, uint32_t G, It
         default: wave_unit<64, DF, F32>(a, list, cnt, first, check, sparse, acc); break;
         }
     };
-    bool xcd = false;
-#if DFPR_XCD_MAP
-    // Every workgroup has work and the grid is a multiple of the XCD count:
-    // the workgroups of XCD x take the x-th eighth of every class, so that
-    // each XCD's L2 serves a contiguous id range of every class.
-    xcd = (G % kXcds) == 0 && (nwu + kWavesPerBlock - 1) / kWavesPerBlock >= G;
-#endif
-    if (!xcd) {
-        for (uint32_t u = blk; u < nbu; u += G)
-            block_row<DF, F32>(a, sh.plan.list[kBins - 1][u], check, sparse, acc, sh.red,
-                               &sh.flag);
-        for (uint32_t u = blk * kWavesPerBlock + wave; u < nwu; u += G * kWavesPerBlock) {
-            int k = 0;
-            while (k + 1 < kBins - 1 && u >= sh.plan.ustart[k + 1]) k++;
-            run_unit(u, k);
-        }
-    } else {
-        const uint32_t x = blk % kXcds, lb = blk / kXcds, GX = G / kXcds;
-        const uint32_t b0 = (uint32_t)((uint64_t)nbu * x / kXcds);
-        const uint32_t b1 = (uint32_t)((uint64_t)nbu * (x + 1) / kXcds);
-        for (uint32_t u = b0 + lb; u < b1; u += GX)
-            block_row<DF, F32>(a, sh.plan.list[kBins - 1][u], check, sparse, acc, sh.red,
-                               &sh.flag);
-        uint32_t lo[kBins - 1], len[kBins - 1], total = 0;
-        for (int k = 0; k < kBins - 1; k++) {
-            const uint32_t us = sh.plan.ustart[k];
-            const uint32_t ue = k + 1 < kBins - 1 ? sh.plan.ustart[k + 1] : nwu;
-            const uint64_t nu = ue - us;
-            lo[k] = us + (uint32_t)(nu * x / kXcds);
-            len[k] = us + (uint32_t)(nu * (x + 1) / kXcds) - lo[k];
-            total += len[k];
-        }
-        for (uint32_t j = lb * kWavesPerBlock + wave; j < total; j += GX * kWavesPerBlock) {
-            int k = 0;
-            uint32_t r = j;
-            while (r >= len[k]) r -= len[k++];
-            run_unit(lo[k] + r, k);
-        }
+    for (uint32_t u = blk; u < nbu; u += G)
+        block_row<DF, F32>(a, sh.plan.list[kBins - 1][u], check, sparse, acc, sh.red,
+                           &sh.flag);
+    for (uint32_t u = blk * kWavesPerBlock + wave; u < nwu; u += G * kWavesPerBlock) {
+        int k = 0;
+        while (k + 1 < kBins - 1 && u >= sh.plan.ustart[k + 1]) k++;
+        run_unit(u, k);
     }
 
     double dr = acc.dr_max, rm = acc.r_max;

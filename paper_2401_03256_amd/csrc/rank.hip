@@ -643,7 +643,6 @@ static int run_loop(dfpr_graph *g, const dfpr_params &p, bool df, bool f32, uint
     *res_buf = base;
     while (it < p.max_iters) {
         const int k = std::min(chunk, p.max_iters - it);
-        if (g->prof.enabled) DFPR_HIP(hipEventRecord(g->evk0, g->stream));
         for (int j = 0; j < k; j++) {
             const int i = it + j;
             const int src = base ^ ((i - it0) & 1);
@@ -654,20 +653,24 @@ static int run_loop(dfpr_graph *g, const dfpr_params &p, bool df, bool f32, uint
             a.C32c = g->C32[src];
             a.C32n = g->C32[src ^ 1];
             a.it = i;
+            if (g->prof.enabled) DFPR_HIP(hipEventRecord(g->evk[2 * j], g->stream));
             if (!df) k_iter<false, false><<<gsz, kBlock, 0, g->stream>>>(a);
             else if (f32) k_iter<true, true><<<gsz, kBlock, 0, g->stream>>>(a);
             else k_iter<true, false><<<gsz, kBlock, 0, g->stream>>>(a);
+            if (g->prof.enabled) DFPR_HIP(hipEventRecord(g->evk[2 * j + 1], g->stream));
             k_final<<<1, kBlock, 0, g->stream>>>(a, gsz, df ? 1 : 0, f32 ? 1 : 0);
         }
         DFPR_HIP(hipGetLastError());
-        if (g->prof.enabled) DFPR_HIP(hipEventRecord(g->evk1, g->stream));
         // k_snap and every k_final that ran an iteration left the control
         // block in the host mirror
         DFPR_HIP(hipStreamSynchronize(g->stream));
         if (g->prof.enabled) {
-            float ms = 0.f;
-            DFPR_HIP(hipEventElapsedTime(&ms, g->evk0, g->evk1));
-            g->prof.ms += ms;
+            // the iteration kernel alone, launch by launch
+            for (int j = 0; j < k; j++) {
+                float ms = 0.f;
+                DFPR_HIP(hipEventElapsedTime(&ms, g->evk[2 * j], g->evk[2 * j + 1]));
+                g->prof.ms += ms;
+            }
             g->prof.launches += k;
         }
         if (g->ctl_host->done || (f32 && g->ctl_host->phase_end)) break;
@@ -679,7 +682,8 @@ static int run_loop(dfpr_graph *g, const dfpr_params &p, bool df, bool f32, uint
         if (!f32 && prev_dr > 0.0 && dr > 0.0 && dr < prev_dr && its > prev_it && p.tol > 0.0) {
             const double rate = std::pow(dr / prev_dr, 1.0 / (its - prev_it));
             const double need = std::ceil(std::log(p.tol / dr) / std::log(rate));
-            if (std::isfinite(need)) next = (int)std::min(64.0, std::max(1.0, need));
+            if (std::isfinite(need))
+                next = (int)std::min<double>(kLoopChunk, std::max(1.0, need));
         }
         prev_dr = dr;
         prev_it = its;
