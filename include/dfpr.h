@@ -97,6 +97,9 @@ void dfpr_params_default(dfpr_params *p);
  * src[i] -> dst[i] (host arrays).  Repeated edges count once and a
  * self-loop is added to every vertex (Section 3.1).  The ranks held by the
  * graph start at 1/n.  Rows get slack of max(2, deg/8) entries.
+ * Internally the library renumbers the vertices by decreasing in-degree;
+ * every id, rank and flag passed to or returned by any call stays in the
+ * caller's numbering.
  * *out receives a handle owned by the library (free with dfpr_free_graph).
  * Errors: DFPR_E_ARG, DFPR_E_RANGE (id outside [0, n)), DFPR_E_NOMEM,
  * DFPR_E_LIMIT (more than 2^32 - 1 edge slots). */
@@ -234,7 +237,10 @@ int dfpr_profile_read(const dfpr_graph *g, dfpr_profile *out);
  * (96 bytes per batch entry).  Admission applies the batch (as
  * dfpr_apply_batch) and runs the initial marking; then every step runs one
  * Dynamic Frontier iteration of every admitted request in one coalesced
- * launch, and a finished request frees its slot at once.  A request's
+ * launch.  Steps run in chunks between two looks by the host (kept to about
+ * a millisecond while requests wait), and a finished request frees its
+ * slot at the end of its chunk; admissions run on a second stream while a
+ * chunk is on the device.  A request's
  * result equals that of dfpr_apply_batch followed by
  * dfpr_pagerank_dynamic_frontier with the graph's parameters, whatever else
  * is in flight.  The server borrows its graphs; they must stay alive and
@@ -263,7 +269,9 @@ typedef struct {
     double final_linf;
 } dfpr_request_result;
 
-/* max_slots in [1, 8]; hbm_budget_bytes > 0. */
+/* max_slots in [1, 8]; hbm_budget_bytes > 0.  *out receives a handle owned
+ * by the library (free with dfpr_server_free).  DFPR_E_ARG, DFPR_E_NOMEM,
+ * DFPR_E_DEVICE. */
 int dfpr_server_create(int32_t max_slots, int64_t hbm_budget_bytes, dfpr_server **out);
 void dfpr_server_free(dfpr_server *s);
 
@@ -273,16 +281,20 @@ void dfpr_server_free(dfpr_server *s);
 int dfpr_server_add_graph(dfpr_server *s, dfpr_graph *g, const dfpr_params *p,
                           int32_t *graph_id);
 
-/* Queue a request (host arrays, copied) arriving arrival_ms after the start
- * of dfpr_server_run.  *request_id receives its index. */
+/* Queue a request (host arrays, copied) arriving arrival_ms >= 0 after the
+ * start of dfpr_server_run.  *request_id receives its index.  DFPR_E_ARG for
+ * an unknown graph or bad arrays, DFPR_E_NOMEM if the request alone can
+ * never fit the budget. */
 int dfpr_server_submit(dfpr_server *s, int32_t graph_id, double arrival_ms,
                        int64_t n_del, const int32_t *del_src, const int32_t *del_dst,
                        int64_t n_ins, const int32_t *ins_src, const int32_t *ins_dst,
                        int64_t *request_id);
 
-/* Serve every queued request, admitting each no earlier than its arrival
- * time, and return when all are done.  A request whose batch holds an id
- * outside [0, n) fails (status DFPR_E_RANGE) without changing its graph. */
+/* Serve every request queued since the last run, admitting each no earlier
+ * than its arrival time, and return when all are done.  A request whose
+ * batch holds an id outside [0, n) fails (status DFPR_E_RANGE) without
+ * changing its graph.  DFPR_E_BUSY if a graph is in use by another call;
+ * device errors end the run with DFPR_E_DEVICE. */
 int dfpr_server_run(dfpr_server *s, dfpr_server_stats *st);
 
 /* Outcome of one request after dfpr_server_run. */
