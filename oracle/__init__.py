@@ -87,6 +87,9 @@ def lib():
             _P, _D, _D, _D, _I32, _I64, _P, _P, _I64, _P, _P, _P, _P, _P, _P, _P]
         L.oracle_mark_initial_csr.argtypes = [_I32, _P, _P, _I64, _P, _P, _I64, _P, _P, _P]
         L.oracle_expand_csr.argtypes = [_I32, _P, _P, _P, _P, _D, _P]
+        L.oracle_mark_reachable_csr.argtypes = [_I32, _P, _P, _I64, _P, _P, _I64, _P, _P, _P]
+        L.oracle_pagerank_dynamic_traversal.argtypes = [
+            _P, _D, _D, _I32, _I64, _P, _P, _I64, _P, _P, _P, _P, _P, _P]
         L.oracle_num_threads.argtypes = []
         _lib = L
     return _lib
@@ -195,6 +198,37 @@ class OracleGraph:
     def mark_initial(self, batch):
         off, idx = self.csr(out=True)
         return mark_initial_csr(self.n, off, idx, batch)
+
+    def mark_reachable(self, batch):
+        off, idx = self.csr(out=True)
+        return mark_reachable_csr(self.n, off, idx, batch)
+
+    def dynamic_traversal(self, batch, prev, alpha=ALPHA, tol=TOL, max_iters=MAX_ITERS,
+                          return_flags=False):
+        """Dynamic Traversal PageRank (Section 3.3.2) on the current graph."""
+        prev = np.ascontiguousarray(prev, np.float64)
+        ds, dd = _i32(batch.del_src), _i32(batch.del_dst)
+        is_, id_ = _i32(batch.ins_src), _i32(batch.ins_dst)
+        R = np.zeros(self.n, np.float64)
+        f = np.zeros(self.n, np.uint8)
+        st = _Stats()
+        _check(lib().oracle_pagerank_dynamic_traversal(
+            self._h, alpha, tol, max_iters, ds.size, _ptr(ds), _ptr(dd), is_.size, _ptr(is_),
+            _ptr(id_), _ptr(prev), _ptr(R), ctypes.byref(st), _ptr(f)), "dynamic_traversal")
+        return (R, _stats(st), f) if return_flags else (R, _stats(st))
+
+
+def mark_reachable_csr(n, out_off, out_idx, batch):
+    """Dynamic Traversal marking (Section 3.3.2) on any out-CSR."""
+    off = np.ascontiguousarray(out_off, np.int64)
+    idx = _i32(out_idx) if len(out_idx) else np.zeros(1, np.int32)
+    ds, dd = _i32(batch.del_src), _i32(batch.del_dst)
+    is_, id_ = _i32(batch.ins_src), _i32(batch.ins_dst)
+    flags = np.zeros(n, np.uint8)
+    _check(lib().oracle_mark_reachable_csr(int(n), _ptr(off), _ptr(idx), ds.size, _ptr(ds),
+                                           _ptr(dd), is_.size, _ptr(is_), _ptr(id_),
+                                           _ptr(flags)), "mark_reachable_csr")
+    return flags
 
 
 def mark_initial_csr(n, out_off, out_idx, batch):

@@ -392,3 +392,111 @@ int oracle_pagerank_dynamic_frontier(
     free(aff); free(nxt); free(R); free(Rn); free(dr);
     return 0;
 }
+
+/* Section 3.3.2 (Dynamic Traversal): for each deleted or inserted edge
+ * (u, v), every vertex reachable from u in G^{t-1} or in G^t is affected.
+ * Reachability is taken in the union graph G^{t-1} union G^t, whose
+ * out-edges are those of G^t plus the deleted batch edges (every deleted
+ * edge leaves a batch source); a vertex reaches itself.  A plain
+ * first-in-first-out breadth-first search. */
+static int cmp_pair(const void *a, const void *b)
+{
+    const int64_t x = *(const int64_t *)a, y = *(const int64_t *)b;
+    return (x > y) - (x < y);
+}
+
+int oracle_mark_reachable_csr(int32_t n, const int64_t *out_off,
+                              const int32_t *out_idx,
+                              int64_t n_del, const int32_t *del_src, const int32_t *del_dst,
+                              int64_t n_ins, const int32_t *ins_src, const int32_t *ins_dst,
+                              uint8_t *flags)
+{
+    if (n <= 0 || !out_off || !flags || n_del < 0 || n_ins < 0) return -1;
+    if ((n_del && (!del_src || !del_dst)) || (n_ins && (!ins_src || !ins_dst))) return -1;
+    if (!ids_ok(n, n_del, del_src, del_dst) || !ids_ok(n, n_ins, ins_src, ins_dst))
+        return -2;
+    /* deleted edges as (source, target) keys, sorted, for their out-rows */
+    int64_t *del = malloc((size_t)(n_del ? n_del : 1) * sizeof(int64_t));
+    int32_t *queue = malloc((size_t)n * sizeof(int32_t));
+    if (!del || !queue) { free(del); free(queue); return -3; }
+    for (int64_t i = 0; i < n_del; i++) del[i] = (int64_t)del_src[i] * n + del_dst[i];
+    qsort(del, (size_t)n_del, sizeof(int64_t), cmp_pair);
+    memset(flags, 0, (size_t)n);
+    int64_t head = 0, tail = 0;
+    for (int64_t i = 0; i < n_del + n_ins; i++) {
+        int32_t u = i < n_del ? del_src[i] : ins_src[i - n_del];
+        if (!flags[u]) { flags[u] = 1; queue[tail++] = u; }
+    }
+    while (head < tail) {
+        int32_t x = queue[head++];
+        for (int64_t k = out_off[x]; k < out_off[x + 1]; k++) {
+            int32_t w = out_idx[k];
+            if (!flags[w]) { flags[w] = 1; queue[tail++] = w; }
+        }
+        /* deleted edges leaving x: first key >= x * n */
+        int64_t lo = 0, hi = n_del;
+        while (lo < hi) {
+            int64_t mid = (lo + hi) / 2;
+            if (del[mid] < (int64_t)x * n) lo = mid + 1; else hi = mid;
+        }
+        for (int64_t j = lo; j < n_del && del[j] / n == x; j++) {
+            int32_t w = (int32_t)(del[j] % n);
+            if (!flags[w]) { flags[w] = 1; queue[tail++] = w; }
+        }
+    }
+    free(del);
+    free(queue);
+    return 0;
+}
+
+/* Dynamic Traversal PageRank (Section 3.3.2) in the synchronous form: mark
+ * the reachable set once, then iterate Eq. 1 over the marked vertices only,
+ * from the previous ranks, until Delta R <= tol.  No vertex is marked
+ * during the iterations. */
+int oracle_pagerank_dynamic_traversal(
+    const oracle_graph *g, double alpha, double tol, int32_t max_iters,
+    int64_t n_del, const int32_t *del_src, const int32_t *del_dst,
+    int64_t n_ins, const int32_t *ins_src, const int32_t *ins_dst,
+    const double *prev, double *ranks_out, oracle_stats *st, uint8_t *affected)
+{
+    if (!g || !prev || !ranks_out || max_iters < 0) return -1;
+    int32_t n = g->n;
+    uint8_t *aff = malloc((size_t)n);
+    double *R = malloc((size_t)n * sizeof(double));
+    double *Rn = malloc((size_t)n * sizeof(double));
+    if (!aff || !R || !Rn) { free(aff); free(R); free(Rn); return -3; }
+    int rc = oracle_mark_reachable_csr(n, g->out_off, g->out_idx, n_del, del_src, del_dst,
+                                       n_ins, ins_src, ins_dst, aff);
+    if (rc) { free(aff); free(R); free(Rn); return rc; }
+    memcpy(R, prev, (size_t)n * sizeof(double));
+    memcpy(Rn, prev, (size_t)n * sizeof(double));
+    oracle_stats s = {0};
+    for (int32_t v = 0; v < n; v++) s.affected_initial += aff[v];
+    s.affected_final = s.affected_initial;
+    if (affected) memcpy(affected, aff, (size_t)n);
+    double *cur = R, *out = Rn;
+    for (int32_t it = 0; it < max_iters; it++) {
+        double dR = 0.0;
+        int64_t edges = 0, verts = 0;
+#pragma omp parallel for schedule(dynamic, 2048) reduction(max : dR) reduction(+ : edges, verts)
+        for (int32_t v = 0; v < n; v++) {
+            if (!aff[v]) continue;
+            double r = rank_of(g, cur, v, alpha);
+            double d = fabs(r - cur[v]);
+            out[v] = r;
+            if (d > dR) dR = d;
+            verts += 1;
+            edges += g->in_off[v + 1] - g->in_off[v];
+        }
+        double *t = cur; cur = out; out = t;
+        s.iterations = it + 1;
+        s.final_linf = dR;
+        s.vertices_processed += verts;
+        s.edges_processed += edges;
+        if (dR <= tol) { s.converged = 1; break; }
+    }
+    memcpy(ranks_out, cur, (size_t)n * sizeof(double));
+    if (st) *st = s;
+    free(aff); free(R); free(Rn);
+    return 0;
+}

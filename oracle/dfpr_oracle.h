@@ -14,7 +14,9 @@
  *     (Section 3.3.1);
  *   - Dynamic Frontier = initial marking, restricted rank updates and
  *     incremental marking (Section 4.1, Algorithm 1), in the synchronous
- *     form of Section 4.2 (separate input and output rank vectors).
+ *     form of Section 4.2 (separate input and output rank vectors);
+ *   - Dynamic Traversal = the vertices reachable from the batch sources,
+ *     iterated alone (Section 3.3.2).
  * Vertex loops run under OpenMP with a dynamic schedule of 2048 as in
  * Section 5.1.2; every result is independent of the thread count.
  *
@@ -103,6 +105,25 @@ int oracle_mark_initial_csr(int32_t n, const int64_t *out_off,
 int oracle_expand_csr(int32_t n, const int64_t *out_off, const int32_t *out_idx,
                       const uint8_t *affected, const double *dr,
                       double frontier_tol, uint8_t *next);
+
+/* Dynamic Traversal marking on an arbitrary out-CSR (Section 3.3.2):
+ * flags[w] = 1 for every w reachable, in the union of the given graph and
+ * the deleted edges, from the source u of any batch edge (u itself
+ * included).  flags (n bytes) is cleared first. */
+int oracle_mark_reachable_csr(int32_t n, const int64_t *out_off,
+                              const int32_t *out_idx,
+                              int64_t n_del, const int32_t *del_src, const int32_t *del_dst,
+                              int64_t n_ins, const int32_t *ins_src, const int32_t *ins_dst,
+                              uint8_t *flags);
+
+/* Dynamic Traversal PageRank on G^t: mark the reachable set, then iterate
+ * Eq. 1 over it from prev until Delta R <= tol or max_iters.  affected
+ * (nullable, n bytes) receives the marks. */
+int oracle_pagerank_dynamic_traversal(
+    const oracle_graph *g, double alpha, double tol, int32_t max_iters,
+    int64_t n_del, const int32_t *del_src, const int32_t *del_dst,
+    int64_t n_ins, const int32_t *ins_src, const int32_t *ins_dst,
+    const double *prev, double *ranks_out, oracle_stats *st, uint8_t *affected);
 
 /* Number of OpenMP threads the oracle's parallel loops use. */
 int oracle_num_threads(void);

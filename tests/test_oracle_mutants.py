@@ -38,6 +38,13 @@ MUTANTS = {
     "insert_duplicates": ("else { nk[w++] = g->keys[a++]; b++; }",
                           "else { nk[w++] = g->keys[a++]; nk[w++] = ik[b++]; }"),
     "uniform_start_wrong": ("ranks_out[v] = 1.0 / (double)g->n;", "ranks_out[v] = 1.0;"),
+    "dt_deleted_edges_ignored": ("for (int64_t j = lo; j < n_del && del[j] / n == x; j++) {",
+                                 "for (int64_t j = lo; j < lo; j++) {"),
+    "dt_stops_after_first_level": (
+        "if (!flags[w]) { flags[w] = 1; queue[tail++] = w; }\n        }\n        /* deleted",
+        "if (!flags[w]) { flags[w] = 1; }\n        }\n        /* deleted"),
+    "dt_iterates_every_vertex": ("v < n; v++) {\n            if (!aff[v]) continue;",
+                                 "v < n; v++) {\n            if (0) continue;"),
 }
 
 

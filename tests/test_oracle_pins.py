@@ -458,3 +458,103 @@ def test_results_do_not_depend_on_thread_count():
         outs.append(subprocess.run([sys.executable, "-c", code], env=env, check=True,
                                    capture_output=True, text=True).stdout)
     assert outs[0] == outs[1]
+
+
+# ---------------------------------------------------------------------------
+# Dynamic Traversal (Section 3.3.2)
+# ---------------------------------------------------------------------------
+
+def _closure(roots, edges):
+    """Every vertex reachable from `roots` along `edges`, by fixpoint
+    iteration over the edge set (no queue, no CSR)."""
+    S = set(roots)
+    while True:
+        grow = {w for (a, w) in edges if a in S} - S
+        if not grow:
+            return S
+        S |= grow
+
+
+@settings(max_examples=80, deadline=None)
+@given(graph_and_batch())
+def test_reachable_marking_matches_definition(case):
+    # reachable from each batch source u in G^{t-1} or in G^t
+    n, pairs, dels, ins = case
+    src, dst = _arr(pairs)
+    E0 = brute.edge_set(n, src, dst)
+    E1 = (E0 - set(dels)) | set(ins)
+    roots = [u for u, _ in dels + ins]
+    expect = set()
+    for u in roots:
+        expect |= _closure([u], E0) | _closure([u], E1)
+    g = OracleGraph(n, src, dst)
+    b = _batch(dels, ins)
+    g.apply_batch(b)
+    f = g.mark_reachable(b)
+    assert set(np.flatnonzero(f).tolist()) == expect
+    # the same set as reachability in the union graph
+    assert expect == _closure(roots, E0 | E1)
+
+
+def test_reachable_marking_on_a_path():
+    # 0 -> 1 -> ... -> 9 (plus self-loops); deleting (2, 3) keeps 3..9
+    # reachable from 2 through G^{t-1}; inserting (7, 9) reaches 7, 8, 9
+    n = 10
+    src = np.arange(9, dtype=np.int32)
+    dst = src + 1
+    g = OracleGraph(n, src, dst)
+    b = _batch([(2, 3)], [(7, 9)])
+    g.apply_batch(b)
+    assert np.flatnonzero(g.mark_reachable(b)).tolist() == [2, 3, 4, 5, 6, 7, 8, 9]
+    b2 = _batch([], [(7, 9)])
+    assert np.flatnonzero(g.mark_reachable(b2)).tolist() == [7, 8, 9]
+    assert not g.mark_reachable(synth.Batch.empty()).any()
+
+
+@settings(max_examples=30, deadline=None)
+@given(tiny_graph(), st.integers(0, 2**31 - 1))
+def test_dynamic_traversal_matches_dense_solve_of_updated_graph(gr, seed):
+    n, pairs = gr
+    src, dst = _arr(pairs)
+    g = OracleGraph(n, src, dst)
+    R0, _ = g.static(tol=1e-14)
+    rng = np.random.default_rng(seed)
+    E = brute.edge_set(n, src, dst)
+    nonloop = sorted(e for e in E if e[0] != e[1])
+    dels = [nonloop[i] for i in rng.permutation(len(nonloop))[: rng.integers(0, 4)]]
+    absent = [(u, v) for u in range(n) for v in range(n) if u != v and (u, v) not in E]
+    ins = [absent[i] for i in rng.permutation(len(absent))[: rng.integers(0, 4)]]
+    b = _batch(dels, ins)
+    g.apply_batch(b)
+    x = brute.pagerank_dense(n, (E - set(dels)) | set(ins))
+    Rt, _ = g.dynamic_traversal(b, R0, tol=1e-13)
+    assert np.max(np.abs(Rt - x)) < 1e-10
+
+
+def test_dynamic_traversal_equals_from_scratch_static_and_covers_frontier():
+    n = 2000
+    src, dst = synth.gnm(n, 16000, seed=5)
+    g = OracleGraph(n, src, dst)
+    R0, _ = g.static()
+    b = synth.random_batch(src, dst, n, 3, 12, seed=9)
+    g.apply_batch(b)
+    Rref, _ = g.reference()
+    Rt, st_t, ft = g.dynamic_traversal(b, R0, return_flags=True)
+    Rd, st_d, _, fd = g.dynamic_frontier(b, R0, return_flags=True)
+    assert st_t.converged and np.max(np.abs(Rt - Rref)) < 1e-9
+    # every Dynamic Frontier mark is reachable from a batch source
+    assert not (fd.astype(bool) & ~ft.astype(bool)).any()
+    assert st_t.affected_initial == st_t.affected_final == int(ft.sum())
+
+
+def test_dynamic_traversal_leaves_unreached_component_bitwise():
+    n, nA, src, dst, (sa, da) = _two_components()
+    g = OracleGraph(n, src, dst)
+    R0, _ = g.static()
+    b = synth.random_batch(sa, da, nA, 3, 10, seed=4)
+    g.apply_batch(b)
+    R, st_, f = g.dynamic_traversal(b, R0, return_flags=True)
+    assert f[:nA].any() and not f[nA:].any()
+    assert np.array_equal(R[nA:], R0[nA:])
+    R, st_ = g.dynamic_traversal(synth.Batch.empty(), R0)
+    assert np.array_equal(R, R0) and st_.iterations == 1 and st_.affected_final == 0
