@@ -193,6 +193,9 @@ def main():
         g.set_ranks(R_prev)
         _, st_nv = g.naive_dynamic(None, p=p, out=False)
         R_nv = g.ranks()
+        g.set_ranks(R_prev)
+        _, st_dt = g.dynamic_traversal(seq[i], p=p, out=False)
+        R_dt = g.ranks()
         _, st_st = g.static(p, out=False)
         R_st = g.ranks()
         comparators["by_frac"][str(f)] = {
@@ -202,6 +205,10 @@ def main():
             "static_ms": round(st_st.ms_device, 3), "static_iterations": st_st.iterations,
             "speedup_vs_static": round(st_st.ms_device / st_df.ms_device, 2),
             "speedup_vs_naive": round(st_nv.ms_device / st_df.ms_device, 2),
+            "dt_ms": round(st_dt.ms_device, 3), "dt_iterations": st_dt.iterations,
+            "dt_affected": st_dt.affected_final,
+            "speedup_vs_dt": round(st_dt.ms_device / st_df.ms_device, 2),
+            "linf_dt_vs_static": float(np.max(np.abs(R_dt - R_st))),
             "fp32_form_ms": round(st_32.ms_device, 3),
             "fp32_form_iterations": st_32.iterations,
             "fp32_form_refine_sweeps": st_32.refine_sweeps,
@@ -212,7 +219,7 @@ def main():
         }
         g.set_ranks(R_df)
         log(f"comparators {f}: DF {st_df.ms_device:.2f} ms, naive {st_nv.ms_device:.2f} ms, "
-            f"static {st_st.ms_device:.2f} ms")
+            f"DT {st_dt.ms_device:.2f} ms, static {st_st.ms_device:.2f} ms")
     comparators["df_ms_mean_by_frac_timed"] = {
         str(f): round(float(np.mean([x[0] for x in v])), 3) for f, v in sorted(per.items())}
 
@@ -330,22 +337,33 @@ def grid_bench(args, dfpr, synth, side=4096, kinds=("uniform", "localised"), per
     for kind, batches in (("uniform", uni), ("localised", loc)):
         rows = []
         for b in batches:
+            R_prev = g.ranks()
             g.apply_batch(b)
             _, st = g.dynamic_frontier(b, p=p, out=False)
             rows.append(st)
             log(f"{kind}: batch {b.size}, {st.iterations} it, affected {st.affected_final}, "
                 f"{st.ms_device:.2f} ms")
         ms = [r.ms_device for r in rows]
-        R_prev = g.ranks()
-        _, st_nv = g.naive_dynamic(R_prev, p=p, out=False)
+        # Naive-dynamic and Dynamic Traversal for the last batch, from the
+        # same previous ranks as its Dynamic Frontier call
+        R_df = g.ranks()
+        g.set_ranks(R_prev)
+        _, st_nv = g.naive_dynamic(None, p=p, out=False)
+        g.set_ranks(R_prev)
+        _, st_dt = g.dynamic_traversal(batches[-1], p=p, out=False)
+        g.set_ranks(R_df)
         res[kind] = {
             "df_ms_p50": round(pct(ms, 50), 3), "df_ms_p99": round(pct(ms, 99), 3),
             "df_iterations_mean": round(float(np.mean([r.iterations for r in rows])), 1),
             "df_affected_mean": int(np.mean([r.affected_final for r in rows])),
             "df_us_per_iteration": round(float(np.sum(ms) * 1e3 / np.sum([r.iterations for r in rows])), 1),
             "df_gteps": round(float(np.sum([r.edges_processed for r in rows]) / np.sum(ms) / 1e6), 2),
+            "df_ms_last": round(rows[-1].ms_device, 3),
             "naive_ms": round(st_nv.ms_device, 3), "naive_iterations": st_nv.iterations,
-            "speedup_vs_naive": round(st_nv.ms_device / pct(ms, 50), 2),
+            "speedup_vs_naive": round(st_nv.ms_device / rows[-1].ms_device, 2),
+            "dt_ms": round(st_dt.ms_device, 3), "dt_iterations": st_dt.iterations,
+            "dt_affected": st_dt.affected_final,
+            "speedup_vs_dt": round(st_dt.ms_device / rows[-1].ms_device, 2),
         }
     out = {"metric": METRIC, "workload": f"grid{side}_diag5_df_fp64", "n": n, "m": m,
            "batch": [nd, ni], "static_ms": round(st0.ms_device, 3),

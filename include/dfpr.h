@@ -178,6 +178,28 @@ int dfpr_pagerank_dynamic_frontier_device(dfpr_graph *g, const dfpr_params *p,
                                           const int32_t *ins_dst, const double *prev,
                                           double *ranks_out, dfpr_stats *st);
 
+/* Dynamic Traversal PageRank (Section 3.3.2), a comparator: every vertex
+ * reachable from the source of a batch edge in G^{t-1} or in G^t is
+ * updated, from prev (NULL = the resident ranks), until Delta R <= tol or
+ * max_iters; no vertex joins during the iterations.  G^t must already hold
+ * the batch (dfpr_apply_batch).  Arguments, errors and outputs as
+ * dfpr_pagerank_dynamic_frontier (host arrays); frontier_tol and precision
+ * are ignored (FP64).  st->affected_initial = affected_final = the
+ * reachable count. */
+int dfpr_pagerank_dynamic_traversal(dfpr_graph *g, const dfpr_params *p, int64_t n_del,
+                                    const int32_t *del_src, const int32_t *del_dst,
+                                    int64_t n_ins, const int32_t *ins_src,
+                                    const int32_t *ins_dst, const double *prev,
+                                    double *ranks_out, dfpr_stats *st);
+
+/* The reachable set of Dynamic Traversal alone: flags_out[v] = 1 (n bytes,
+ * caller's numbering) for every v reachable from a batch source along G^t's
+ * out-edges and the batch's deleted edges, the sources included.  Host
+ * arrays; DFPR_E_RANGE for an id outside [0, n). */
+int dfpr_mark_reachable(dfpr_graph *g, int64_t n_del, const int32_t *del_src,
+                        const int32_t *del_dst, int64_t n_ins, const int32_t *ins_src,
+                        const int32_t *ins_dst, uint8_t *flags_out);
+
 /* Initial marking only (Section 4.1.1, first rule): flags_out (host, n
  * bytes) receives 1 for every w in G^t.out(u) of each batch edge (u, v) and
  * for the v of each deletion, 0 elsewhere.  Ranks are not touched. */

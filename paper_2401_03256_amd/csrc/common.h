@@ -54,6 +54,8 @@ struct Ctl {
     unsigned long long affected0;   // marks after the initial marking
     unsigned long long affected;    // marks when the call ended
     uint32_t err;               // an id outside [0, n) was seen
+    uint32_t qn[3];             // traversal: lengths of the three level queues
+    uint32_t qhn[3];            //   ... and of the three queues of heavy vertices
     uint32_t mk_light;          // initial marking: claimed sources scanned by one wave
     uint32_t mk_heavy;          //   ... and by the whole grid
     unsigned long long reach;   //   out-edges of the claimed sources
@@ -133,6 +135,7 @@ struct dfpr_graph {
     uint32_t last_base = 0;           // stamp base and iterations of the last
     int32_t last_iters = -1;          //   Dynamic Frontier call
     int32_t *bins = nullptr;          // kBins appended lists of n entries (sparse mode)
+    int32_t *bfs_q = nullptr;         // traversal: 3 light + 3 heavy level queues, n each
     int32_t *sched = nullptr;         // all vertices by class, sorted (dense mode)
     uint32_t *sched_off = nullptr;    // kBins + 1 offsets into sched (device)
     uint32_t *sched_tmp = nullptr;    // per-workgroup class counts for the build

@@ -287,6 +287,7 @@ void dfpr_free_graph(dfpr_graph *g)
     (void)hipFree(g->stamp);
     (void)hipFree(g->xstamp);
     (void)hipFree(g->bins);
+    (void)hipFree(g->bfs_q);
     (void)hipFree(g->sched);
     (void)hipFree(g->sched_off);
     (void)hipFree(g->sched_tmp);

@@ -102,6 +102,7 @@ __global__ void k_reset(Ctl *ctl)
         ctl->err = 0;
         ctl->mk_light = ctl->mk_heavy = 0;
         ctl->reach = 0;
+        for (int k = 0; k < 3; k++) ctl->qn[k] = ctl->qhn[k] = 0;
     }
 }
 
@@ -383,6 +384,135 @@ __global__ __launch_bounds__(kBlock) void k_mark_initial(IterArgs a, int64_t nd,
     if (lane == 0 && mine) atomicAdd(&s_new, mine);
     __syncthreads();
     if (threadIdx.x == 0 && s_new) atomicAdd(&ctl->affected0, s_new);
+}
+
+// Dynamic Traversal (Section 3.3.2): every vertex reachable from the
+// source of a batch edge in G^{t-1} or in G^t is affected.  Every deleted
+// edge leaves a batch source, so the vertices reachable in either graph are
+// those reachable along G^t's out-edges from the batch sources and the
+// deletion targets.  A level-synchronous breadth-first search claims each
+// vertex once through its stamp (the call's base, so that it is processed
+// from the first iteration) and appends it to the next level's queue and,
+// with `append`, to its class list.  Vertices with more than kHeavyRow
+// out-edges go to a separate queue whose out-rows the whole grid walks in
+// workgroup-sized chunks; the others are walked by waves, 64 at a time.
+// Three queues (of each kind) rotate: level L reads queue L mod 3, fills
+// queue L+1 mod 3 and clears the lengths of queue L+2 mod 3.
+
+struct BfsQueues {
+    const int32_t *in, *hin;          // this level: light and heavy vertices
+    const uint32_t *nin, *nhin;
+    int32_t *out, *hout;              // next level
+    uint32_t *nout, *nhout;
+    uint32_t *clear, *hclear;         // the level after next
+};
+
+// Every lane of the wave calls it; x < 0 claims nothing.
+__device__ inline void bfs_claim(const IterArgs &a, int32_t x, const BfsQueues &q, bool append,
+                                 unsigned long long &mine)
+{
+    bool nw = false;
+    if (x >= 0 && a.stamp[x] < a.sbase) nw = atomicMax(&a.stamp[x], a.sbase) < a.sbase;
+    const bool big = nw && a.out_cnt[x] > kHeavyRow;
+    const unsigned long long ml = __ballot(nw && !big), mh = __ballot(big);
+    const int lane = lane_id();
+    const unsigned long long below = (1ull << lane) - 1ull;
+    if (ml | mh) {
+        uint32_t bl = 0, bh = 0;
+        if (lane == 0) {
+            if (ml) bl = atomicAdd(q.nout, (uint32_t)__popcll(ml));
+            if (mh) bh = atomicAdd(q.nhout, (uint32_t)__popcll(mh));
+            mine += __popcll(ml | mh);
+        }
+        bl = __shfl(bl, 0);
+        bh = __shfl(bh, 0);
+        if (nw && !big) q.out[bl + __popcll(ml & below)] = x;
+        if (big) q.hout[bh + __popcll(mh & below)] = x;
+    }
+    if (append) {
+        const int cls = nw ? bin_of(a.in_cnt[x]) : 0;
+        append_to_bins(nw, x, cls, a.ctl, a.bins, a.n_stride);
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_bfs_seed(IterArgs a, int64_t nd, const int32_t *ds,
+                                                     const int32_t *dd, int64_t ni,
+                                                     const int32_t *is, BfsQueues q, int append)
+{
+    __shared__ unsigned long long s_new;
+    if (a.ctl->err) return;
+    if (threadIdx.x == 0) s_new = 0;
+    __syncthreads();
+    const int lane = lane_id();
+    const int64_t wave = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) / kWave;
+    const int64_t waves = (int64_t)gridDim.x * kWavesPerBlock;
+    unsigned long long mine = 0;
+    for (int64_t b0 = wave * kWave; b0 < nd + ni; b0 += waves * kWave) {
+        const int64_t i = b0 + lane;
+        const int32_t u = i < nd + ni ? (i < nd ? ds[i] : is[i - nd]) : -1;
+        bfs_claim(a, u, q, append != 0, mine);
+        bfs_claim(a, i < nd ? dd[i] : -1, q, append != 0, mine);
+    }
+    if (lane == 0 && mine) atomicAdd(&s_new, mine);
+    __syncthreads();
+    if (threadIdx.x == 0 && s_new) atomicAdd(&a.ctl->affected0, s_new);
+}
+
+// One level.  Light vertices: each wave takes 64 and walks their out-edges
+// together, one out-edge per lane and round.  Heavy vertices: every
+// workgroup takes chunks of kBlock out-edges of each of them.
+__global__ __launch_bounds__(kBlock) void k_bfs_level(IterArgs a, BfsQueues q, int append)
+{
+    __shared__ unsigned long long s_new;
+    if (a.ctl->err) return;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        *q.clear = 0;
+        *q.hclear = 0;
+    }
+    const uint32_t nin = *q.nin, nh = *q.nhin;
+    if (threadIdx.x == 0) s_new = 0;
+    __syncthreads();
+    const int lane = lane_id();
+    const int64_t wave = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) / kWave;
+    const int64_t waves = (int64_t)gridDim.x * kWavesPerBlock;
+    unsigned long long mine = 0;
+    for (int64_t b0 = wave * kWave; b0 < nin; b0 += waves * kWave) {
+        const int64_t i = b0 + lane;
+        const int32_t x = i < nin ? q.in[i] : -1;
+        const uint32_t deg = x >= 0 ? a.out_cnt[x] : 0u;
+        const uint32_t ob = x >= 0 ? a.out_beg[x] : 0u;
+        uint32_t incl = deg;
+#pragma unroll
+        for (int d = 1; d < kWave; d <<= 1) {
+            const uint32_t y = __shfl_up(incl, d);
+            if (lane >= d) incl += y;
+        }
+        const uint32_t total = __shfl(incl, kWave - 1);
+        for (uint32_t t0 = 0; t0 < total; t0 += kWave) {
+            const uint32_t t = t0 + lane;
+            const uint32_t tt = min(t, total - 1);
+            int j = 0;
+#pragma unroll
+            for (int step = kWave / 2; step > 0; step >>= 1)
+                if (__shfl(incl, j + step - 1) <= tt) j += step;
+            const uint32_t first = __shfl(incl, j) - __shfl(deg, j);
+            const uint32_t base = __shfl(ob, j);
+            const int32_t y = t < total ? a.out_idx[base + (tt - first)] : -1;
+            bfs_claim(a, y, q, append != 0, mine);
+        }
+    }
+    for (uint32_t h = 0; h < nh; h++) {
+        const int32_t u = q.hin[h];
+        const uint32_t ob = a.out_beg[u], oc = a.out_cnt[u];
+        const uint32_t chunks = (oc + kBlock - 1) / kBlock;
+        for (uint32_t c = blockIdx.x; c < chunks; c += gridDim.x) {
+            const uint32_t k = c * kBlock + threadIdx.x;
+            bfs_claim(a, k < oc ? a.out_idx[ob + k] : -1, q, append != 0, mine);
+        }
+    }
+    if (lane == 0 && mine) atomicAdd(&s_new, mine);
+    __syncthreads();
+    if (threadIdx.x == 0 && s_new) atomicAdd(&a.ctl->affected0, s_new);
 }
 
 // End of a Dynamic Frontier call: copy the rows processed in this call from
@@ -924,6 +1054,137 @@ static int df_impl(dfpr_graph *g, const dfpr_params *pp, int64_t nd, const int32
     return DFPR_OK;
 }
 
+// Workgroups for a traversal level of `q` light vertices (a wave per 64),
+// with room for the queue to grow sixteenfold within a chunk of levels; a
+// level with heavy vertices gets the whole grid.
+static uint32_t bfs_grid(const dfpr_graph *g, uint64_t q, uint64_t heavy)
+{
+    if (heavy) return (uint32_t)g->grid;
+    const uint64_t blocks = (q + (uint64_t)kBlock - 1) / kBlock;
+    return (uint32_t)std::min<uint64_t>(g->grid, std::max<uint64_t>(256, blocks * 16));
+}
+
+static BfsQueues bfs_queues(dfpr_graph *g, int64_t L)
+{
+    const size_t n = (size_t)g->n;
+    int32_t *light = g->bfs_q, *heavy = g->bfs_q + 3 * n;
+    uint32_t *qn = g->ctl->qn, *qhn = g->ctl->qhn;   // device addresses
+    const int r0 = (int)(L % 3), r1 = (int)((L + 1) % 3), r2 = (int)((L + 2) % 3);
+    BfsQueues q;
+    q.in = light + r0 * n;
+    q.hin = heavy + r0 * n;
+    q.nin = qn + r0;
+    q.nhin = qhn + r0;
+    q.out = light + r1 * n;
+    q.hout = heavy + r1 * n;
+    q.nout = qn + r1;
+    q.nhout = qhn + r1;
+    q.clear = qn + r2;
+    q.hclear = qhn + r2;
+    return q;
+}
+
+// The traversal on the graph's stream: seed with the batch sources and
+// deletion targets, then levels in chunks between host looks, until a
+// level queues nothing.  Reached vertices end with stamp a.sbase.
+static int traverse(dfpr_graph *g, const IterArgs &a, int64_t nd, const int32_t *bds,
+                    const int32_t *bdd, int64_t ni, const int32_t *bis, bool append)
+{
+    const int32_t n = g->n;
+    hipStream_t s = g->stream;
+    if (!g->bfs_q) DFPR_HIP(hipMalloc(&g->bfs_q, (size_t)6 * n * sizeof(int32_t)));
+    // the seed fills the queues that level 0 reads: those of a level -1
+    // (which reads and clears nothing)
+    BfsQueues q0 = bfs_queues(g, 2);
+    k_bfs_seed<<<std::min(blocks_for(nd + ni), 2048), kBlock, 0, s>>>(a, nd, bds, bdd, ni, bis,
+                                                                   q0, append ? 1 : 0);
+    DFPR_HIP(hipGetLastError());
+    uint32_t grid = (uint32_t)g->grid;
+    int chunk = 1;
+    for (int64_t L = 0; L <= (int64_t)n;) {
+        for (int j = 0; j < chunk; j++, L++)
+            k_bfs_level<<<grid, kBlock, 0, s>>>(a, bfs_queues(g, L), append ? 1 : 0);
+        DFPR_HIP(hipGetLastError());
+        DFPR_HIP(hipMemcpyAsync(g->ctl_host, g->ctl, sizeof(Ctl), hipMemcpyDeviceToHost, s));
+        DFPR_HIP(hipStreamSynchronize(s));
+        const Ctl &c = *g->ctl_host;
+        const uint32_t next = c.qn[L % 3], nexth = c.qhn[L % 3];
+        if (c.err || (next == 0 && nexth == 0)) break;
+        grid = bfs_grid(g, next, nexth);
+        chunk = std::min(chunk * 2, 16);
+    }
+    return DFPR_OK;
+}
+
+// Dynamic Traversal PageRank (Section 3.3.2): the reachable set is marked
+// before the first iteration and never grows, so the iterations are those
+// of Dynamic Frontier with no expansion.  Always FP64.
+static int dt_impl(dfpr_graph *g, const dfpr_params *pp, int64_t nd, const int32_t *ds,
+                   const int32_t *dd, int64_t ni, const int32_t *is, const int32_t *id,
+                   int on_device, const double *prev, double *ranks_out, dfpr_stats *st)
+{
+    dfpr_params p;
+    int rc = check_params(pp, p);
+    if (rc) return rc;
+    p.precision = DFPR_FP64;
+    p.frontier_tol = INFINITY;   // no vertex joins during the iterations
+    if (nd < 0 || ni < 0 || (nd && (!ds || !dd)) || (ni && (!is || !id)))
+        return set_error(DFPR_E_ARG, "bad batch arrays");
+    if (!on_device) {
+        rc = check_ids_host(g->n, nd, ds, dd);
+        if (!rc) rc = check_ids_host(g->n, ni, is, id);
+        if (rc) return rc;
+    }
+    BusyGuard guard(g);
+    if (!guard.ok) return set_error(DFPR_E_BUSY, "graph in use");
+    const int32_t n = g->n;
+    hipStream_t s = g->stream;
+    DFPR_HIP(hipEventRecord(g->ev0, s));
+    const int32_t *bds, *bdd, *bis, *bid;
+    rc = stage_batch(g, nd, ds, dd, ni, is, id, on_device, &bds, &bdd, &bis, &bid);
+    if (rc) return rc;
+    const int cur = g->cur;
+    if (prev) {
+        rc = ranks_from_caller(g, prev, on_device, g->R[cur]);
+        if (rc) return rc;
+        k_init_ranks<<<blocks_for(n), kBlock, 0, s>>>(n, g->R[cur], g->R[0], g->R[1], g->C[0],
+                                                      g->C[1], g->csr[1].cnt);
+    }
+    rc = ensure_schedule(g);
+    uint32_t sbase = 0;
+    if (!rc) rc = take_base(g, p.max_iters, &sbase);
+    if (rc) return rc;
+    IterArgs a = iter_args(g, p, sbase);
+    k_reset<<<1, 1, 0, s>>>(g->ctl);
+    if (nd + ni > 0) {
+        k_validate<<<blocks_for(nd + ni), kBlock, 0, s>>>(n, nd, bds, bdd, ni, bis, bid, g->ctl);
+        rc = traverse(g, a, nd, bds, bdd, ni, bis, false);
+        if (rc) return rc;
+    }
+    // the reachable set is usually most of the graph: the iterations walk
+    // the full schedule and read the stamps, no class lists are built
+    k_snap<<<1, 1, 0, s>>>(g->ctl, p.max_iters, g->sparse_limit, 1, g->ctl_host);
+    DFPR_HIP(hipGetLastError());
+    g->refine_sweeps = 0;
+    std::memset(g->prof_base, 0, sizeof(g->prof_base));
+    int res = cur;
+    rc = run_loop(g, p, true, false, sbase, 0, cur, &res);
+    if (rc) return rc;
+    const int32_t iters = g->ctl_host->iterations;
+    if (g->ctl_host->err) return set_error(DFPR_E_RANGE, "vertex id outside [0, n) in the batch");
+    rc = df_finish(g, sbase, res, iters);
+    if (rc) return rc;
+    DFPR_HIP(hipEventRecord(g->ev1, s));
+    if (ranks_out) {
+        rc = ranks_to_caller(g, g->R[res], ranks_out, on_device);
+        if (rc) return rc;
+    }
+    DFPR_HIP(hipMemcpyAsync(g->ctl_host, g->ctl, sizeof(Ctl), hipMemcpyDeviceToHost, s));
+    DFPR_HIP(hipStreamSynchronize(s));
+    fill_stats(g, st, true);
+    return DFPR_OK;
+}
+
 }  // namespace dfpr
 
 using namespace dfpr;
@@ -977,6 +1238,53 @@ int dfpr_pagerank_dynamic_frontier_device(dfpr_graph *g, const dfpr_params *p, i
 {
     if (!g) return set_error(DFPR_E_ARG, "graph is NULL");
     return df_impl(g, p, n_del, del_src, del_dst, n_ins, ins_src, ins_dst, 1, prev, ranks_out, st);
+}
+
+int dfpr_pagerank_dynamic_traversal(dfpr_graph *g, const dfpr_params *p, int64_t n_del,
+                                    const int32_t *del_src, const int32_t *del_dst,
+                                    int64_t n_ins, const int32_t *ins_src,
+                                    const int32_t *ins_dst, const double *prev,
+                                    double *ranks_out, dfpr_stats *st)
+{
+    if (!g) return set_error(DFPR_E_ARG, "graph is NULL");
+    return dt_impl(g, p, n_del, del_src, del_dst, n_ins, ins_src, ins_dst, 0, prev, ranks_out, st);
+}
+
+int dfpr_mark_reachable(dfpr_graph *g, int64_t n_del, const int32_t *del_src,
+                        const int32_t *del_dst, int64_t n_ins, const int32_t *ins_src,
+                        const int32_t *ins_dst, uint8_t *flags_out)
+{
+    if (!g || !flags_out) return set_error(DFPR_E_ARG, "NULL argument");
+    if (n_del < 0 || n_ins < 0 || (n_del && (!del_src || !del_dst)) ||
+        (n_ins && (!ins_src || !ins_dst)))
+        return set_error(DFPR_E_ARG, "bad batch arrays");
+    int rc = check_ids_host(g->n, n_del, del_src, del_dst);
+    if (!rc) rc = check_ids_host(g->n, n_ins, ins_src, ins_dst);
+    if (rc) return rc;
+    BusyGuard guard(g);
+    if (!guard.ok) return set_error(DFPR_E_BUSY, "graph in use");
+    const int32_t n = g->n;
+    hipStream_t s = g->stream;
+    const int32_t *bds, *bdd, *bis, *bid;
+    rc = stage_batch(g, n_del, del_src, del_dst, n_ins, ins_src, ins_dst, 0, &bds, &bdd, &bis,
+                     &bid);
+    dfpr_params p;
+    dfpr_params_default(&p);
+    uint32_t sbase = 0;
+    if (!rc) rc = take_base(g, 0, &sbase);
+    if (rc) return rc;
+    IterArgs a = iter_args(g, p, sbase);
+    k_reset<<<1, 1, 0, s>>>(g->ctl);
+    DFPR_HIP(hipGetLastError());
+    if (n_del + n_ins > 0) {
+        rc = traverse(g, a, n_del, bds, bdd, n_ins, bis, false);
+        if (rc) return rc;
+    }
+    std::vector<uint32_t> st(n);
+    DFPR_HIP(hipMemcpyAsync(st.data(), g->stamp, (size_t)n * 4, hipMemcpyDeviceToHost, s));
+    DFPR_HIP(hipStreamSynchronize(s));
+    for (int32_t v = 0; v < n; v++) flags_out[v] = st[g->ext2int_h[v]] == sbase ? 1 : 0;
+    return DFPR_OK;
 }
 
 int dfpr_mark_affected(dfpr_graph *g, int64_t n_del, const int32_t *del_src,

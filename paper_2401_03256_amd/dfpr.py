@@ -34,6 +34,7 @@ EXPORTED = [
     "dfpr_pagerank_dynamic_frontier", "dfpr_pagerank_dynamic_frontier_device",
     "dfpr_mark_affected", "dfpr_get_affected", "dfpr_get_ranks", "dfpr_set_ranks",
     "dfpr_export_csr", "dfpr_last_error", "dfpr_profile_reset", "dfpr_profile_read",
+    "dfpr_pagerank_dynamic_traversal", "dfpr_mark_reachable",
     "dfpr_server_create", "dfpr_server_free", "dfpr_server_add_graph", "dfpr_server_submit",
     "dfpr_server_run", "dfpr_server_result",
 ]
@@ -149,6 +150,8 @@ def lib():
     L.dfpr_pagerank_dynamic_frontier.argtypes = [_P, _P, *batch, _P, _P, _P]
     L.dfpr_pagerank_dynamic_frontier_device.argtypes = [_P, _P, *batch, _P, _P, _P]
     L.dfpr_mark_affected.argtypes = [_P, *batch, _P]
+    L.dfpr_pagerank_dynamic_traversal.argtypes = [_P, _P, *batch, _P, _P, _P]
+    L.dfpr_mark_reachable.argtypes = [_P, *batch, _P]
     L.dfpr_get_affected.argtypes = [_P, _P]
     L.dfpr_get_ranks.argtypes = [_P, _P, ctypes.c_int]
     L.dfpr_set_ranks.argtypes = [_P, _P, ctypes.c_int]
@@ -302,6 +305,26 @@ class Graph:
         return _stats(st)
 
     # -- inspection ---------------------------------------------------------
+    def dynamic_traversal(self, batch, prev=None, p: Params | None = None, out=True):
+        """Dynamic Traversal PageRank (comparator) after apply_batch(batch)."""
+        ds, dd, is_, id_ = (_i32(batch.del_src), _i32(batch.del_dst), _i32(batch.ins_src),
+                            _i32(batch.ins_dst))
+        prev = None if prev is None else np.ascontiguousarray(prev, np.float64)
+        R = np.empty(self.n, np.float64) if out else None
+        st = _Stats()
+        _check(lib().dfpr_pagerank_dynamic_traversal(
+            self._h, ctypes.byref(p) if p else None, ds.size, _hp(ds), _hp(dd), is_.size,
+            _hp(is_), _hp(id_), _hp(prev), _hp(R), ctypes.byref(st)))
+        return R, _stats(st)
+
+    def mark_reachable(self, batch):
+        ds, dd, is_, id_ = (_i32(batch.del_src), _i32(batch.del_dst), _i32(batch.ins_src),
+                            _i32(batch.ins_dst))
+        flags = np.zeros(self.n, np.uint8)
+        _check(lib().dfpr_mark_reachable(self._h, ds.size, _hp(ds), _hp(dd), is_.size, _hp(is_),
+                                         _hp(id_), _hp(flags)))
+        return flags
+
     def mark_affected(self, batch):
         ds, dd, is_, id_ = (_i32(batch.del_src), _i32(batch.del_dst), _i32(batch.ins_src),
                             _i32(batch.ins_dst))

@@ -60,6 +60,7 @@ def _run_sequence(dfpr, g, o, batches, tag):
         assert np.max(np.abs(R - Ro)) < TOL_RANK, f"batch {i}"
         assert abs(st.affected_initial - sto.affected_initial) == 0
     _same_csr(g, o)
+    return Ro
 
 
 def test_rmat22_static_and_dynamic_frontier(dfpr):
@@ -70,7 +71,16 @@ def test_rmat22_static_and_dynamic_frontier(dfpr):
     m = o.m
     counts = [synth.batch_counts(f, m) for f in (1e-7, 1e-5, 1e-3)]
     batches = synth.batch_sequence(src, dst, n, counts, seed=2)
-    _run_sequence(dfpr, g, o, batches, "rmat22")
+    Ro = _run_sequence(dfpr, g, o, batches, "rmat22")
+    # Dynamic Traversal on one more batch, each side from its own ranks
+    b = synth.random_batch(src, dst, n, *counts[1], seed=3)
+    _say("rmat22: dynamic traversal")
+    assert g.apply_batch(b) == o.apply_batch(b)
+    assert np.array_equal(g.mark_reachable(b), o.mark_reachable(b))
+    R, st = g.dynamic_traversal(b, p=dfpr.params(frontier_tol=FTOL))
+    Rt, sto = o.dynamic_traversal(b, Ro)
+    assert st.converged and st.affected_final == sto.affected_final
+    assert np.max(np.abs(R - Rt)) < TOL_RANK
 
 
 def test_grid4096_uniform_and_localised(dfpr):

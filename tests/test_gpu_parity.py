@@ -516,3 +516,64 @@ def test_serving_arrivals_one_writer_and_bad_requests(dfpr):
     for r0, r1 in zip(good, good[1:]):
         assert r1["admit_ms"] >= r0["done_ms"]         # one writer per graph
     assert np.array_equal(g.ranks(), ref.ranks())
+
+
+# ---------------------------------------------------------------------------
+# Dynamic Traversal (comparator)
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("case", ["gnm", "rmat11", "grid", "dag"])
+def test_reachable_set_bit_exact(dfpr, case):
+    _say(f"reachable {case}")
+    if case == "gnm":
+        n = 3000
+        src, dst = synth.gnm(n, 6000, seed=21)
+    elif case == "rmat11":
+        n, src, dst = synth.rmat(11, 4, seed=22)
+    elif case == "grid":
+        n, src, dst = synth.grid2d(64, 0.05, seed=23)
+    else:
+        # a forward-only random graph: small reachable sets
+        n = 4000
+        s0, d0 = synth.gnm(n, 8000, seed=24)
+        src, dst = np.minimum(s0, d0), np.maximum(s0, d0)
+        keep = src != dst
+        src, dst = src[keep], dst[keep]
+    g, o = _pair(dfpr, n, src, dst)
+    for k, (nd, ni) in enumerate([(0, 1), (2, 6), (20, 80)]):
+        # batches drawn against the current edge set
+        es, ed = _non_loop_edges(o)
+        b = synth.random_batch(es, ed, n, nd, ni, seed=30 + k)
+        assert g.apply_batch(b) == o.apply_batch(b)
+        assert np.array_equal(g.mark_reachable(b), o.mark_reachable(b))
+    assert not g.mark_reachable(synth.Batch.empty()).any()
+
+
+def _non_loop_edges(o):
+    off, idx = o.csr(out=True)
+    src = np.repeat(np.arange(o.n, dtype=np.int32), np.diff(off))
+    keep = src != idx
+    return src[keep], idx[keep].astype(np.int32)
+
+
+def test_dynamic_traversal_matches_oracle(dfpr):
+    n, nA = 5000, 3000
+    sa, da = synth.gnm(nA, 20000, seed=25)
+    sb, db = synth.gnm(n - nA, 9000, seed=26)
+    src = np.concatenate([sa, sb + nA])
+    dst = np.concatenate([da, db + nA])
+    g, o = _pair(dfpr, n, src, dst)
+    p = dfpr.params(frontier_tol=1e-13)
+    R0, _ = g.static(p)
+    Ro, _ = o.static()
+    b = synth.random_batch(sa, da, nA, 4, 16, seed=27)
+    g.apply_batch(b)
+    o.apply_batch(b)
+    R, st = g.dynamic_traversal(b, p=p)
+    Rt, sto, ft = o.dynamic_traversal(b, Ro, return_flags=True)
+    assert st.converged and abs(st.iterations - sto.iterations) <= 1
+    assert st.affected_initial == st.affected_final == int(ft.sum())
+    assert np.max(np.abs(R - Rt)) < TOL_RANK
+    assert np.array_equal(R[nA:], R0[nA:])           # unreached component untouched
+    Rref, _ = o.reference()
+    assert np.max(np.abs(R - Rref)) < TOL_RANK

@@ -29,8 +29,11 @@ MUTANTS = {
                             "affected[v] && dr[v] >= frontier_tol"),
     "deleted_target_unmarked": ("if (i < n_del) flags[del_dst[i]] = 1;", ";"),
     "self_loop_deletable": ("if (del_src[i] != del_dst[i]) dk[nd++]", "if (1) dk[nd++]"),
-    "second_buffer_not_prev": ("memcpy(Rn, prev, (size_t)n * sizeof(double));",
-                               "memset(Rn, 0, (size_t)n * sizeof(double));"),
+    "second_buffer_not_prev": (
+        "memcpy(Rn, prev, (size_t)n * sizeof(double));\n    oracle_stats s = {0};\n"
+        "    for (int32_t v = 0; v < n; v++) s.affected_initial += aff[v];\n    if (affected_initial)",
+        "memset(Rn, 0, (size_t)n * sizeof(double));\n    oracle_stats s = {0};\n"
+        "    for (int32_t v = 0; v < n; v++) s.affected_initial += aff[v];\n    if (affected_initial)"),
     "marks_not_kept": ("memcpy(next, affected, (size_t)n);", "memset(next, 0, (size_t)n);"),
     "loose_convergence": ("        if (dR <= tol) { s.converged = 1; break; }\n    }\n    if (cur != R)",
                           "        if (dR <= tol * 1e6) { s.converged = 1; break; }\n    }\n    if (cur != R)"),
