@@ -139,6 +139,7 @@ def main():
     torch.cuda.synchronize()
     p = dfpr.params(frontier_tol=args.frontier_tol)
     p32 = dfpr.params(frontier_tol=args.frontier_tol, precision=dfpr.FP32_KAHAN)
+    pa = dfpr.params(frontier_tol=args.frontier_tol, mode=dfpr.ASYNC)
 
     t = time.time()
     R0, st0 = g.static(p)
@@ -196,6 +197,9 @@ def main():
         g.set_ranks(R_prev)
         _, st_dt = g.dynamic_traversal(seq[i], p=p, out=False)
         R_dt = g.ranks()
+        g.set_ranks(R_prev)
+        st_as = g.dynamic_frontier_device(*dev[i], p=pa)
+        R_as = g.ranks()
         _, st_st = g.static(p, out=False)
         R_st = g.ranks()
         comparators["by_frac"][str(f)] = {
@@ -209,6 +213,8 @@ def main():
             "dt_affected": st_dt.affected_final,
             "speedup_vs_dt": round(st_dt.ms_device / st_df.ms_device, 2),
             "linf_dt_vs_static": float(np.max(np.abs(R_dt - R_st))),
+            "df_async_ms": round(st_as.ms_device, 3), "df_async_iterations": st_as.iterations,
+            "linf_df_async_vs_static": float(np.max(np.abs(R_as - R_st))),
             "fp32_form_ms": round(st_32.ms_device, 3),
             "fp32_form_iterations": st_32.iterations,
             "fp32_form_refine_sweeps": st_32.refine_sweeps,
@@ -218,7 +224,8 @@ def main():
             "linf_naive_vs_static": float(np.max(np.abs(R_nv - R_st))),
         }
         g.set_ranks(R_df)
-        log(f"comparators {f}: DF {st_df.ms_device:.2f} ms, naive {st_nv.ms_device:.2f} ms, "
+        log(f"comparators {f}: DF {st_df.ms_device:.2f} ms ({st_df.iterations} it), async DF "
+            f"{st_as.ms_device:.2f} ms ({st_as.iterations} it), naive {st_nv.ms_device:.2f} ms, "
             f"DT {st_dt.ms_device:.2f} ms, static {st_st.ms_device:.2f} ms")
     comparators["df_ms_mean_by_frac_timed"] = {
         str(f): round(float(np.mean([x[0] for x in v])), 3) for f, v in sorted(per.items())}

@@ -62,6 +62,10 @@ extern "C" {
                                FP64 L-inf, renormalisation and final FP64
                                sweeps (see dfpr_pagerank_dynamic_frontier)    */
 
+/* iteration forms (dfpr_params.mode) */
+#define DFPR_SYNC 0         /* separate input and output rank vectors          */
+#define DFPR_ASYNC 1        /* one rank vector updated in place                 */
+
 typedef struct dfpr_graph dfpr_graph;
 
 typedef struct {
@@ -73,6 +77,16 @@ typedef struct {
                               neighbours; default tol/1e5 (Section 4.3)         */
     int32_t max_iters;     /* iteration cap; default 500 (Section 5.1.2)       */
     int32_t precision;     /* DFPR_FP64 (default) or DFPR_FP32_KAHAN           */
+    int32_t mode;          /* DFPR_SYNC (default): every iteration reads the
+                              previous iteration's ranks (Section 4.2's
+                              synchronous form); DFPR_ASYNC: one rank vector
+                              updated in place, so an iteration may read ranks
+                              written earlier in the same iteration (the
+                              asynchronous form, Section 4.2).  ASYNC results
+                              are not bitwise reproducible; it applies to the
+                              FP64 iterations (not to the FP32 phase) and is
+                              ignored by the serving calls.                    */
+    int32_t reserved;      /* 0                                                */
 } dfpr_params;
 
 typedef struct {

@@ -271,6 +271,8 @@ void dfpr_params_default(dfpr_params *p)
     p->frontier_tol = 1e-10 / 1e5;
     p->max_iters = 500;
     p->precision = DFPR_FP64;
+    p->mode = DFPR_SYNC;
+    p->reserved = 0;
 }
 
 void dfpr_free_graph(dfpr_graph *g)

@@ -673,7 +673,8 @@ int check_params(const dfpr_params *p, dfpr_params &out)
     else dfpr_params_default(&out);
     if (!(out.alpha >= 0.0 && out.alpha < 1.0) || !(out.tol >= 0.0) ||
         !(out.frontier_tol >= 0.0) || out.max_iters < 0 || out.max_iters > 100000 ||
-        (out.precision != DFPR_FP64 && out.precision != DFPR_FP32_KAHAN))
+        (out.precision != DFPR_FP64 && out.precision != DFPR_FP32_KAHAN) ||
+        (out.mode != DFPR_SYNC && out.mode != DFPR_ASYNC))
         return set_error(DFPR_E_ARG, "invalid parameters");
     return DFPR_OK;
 }
@@ -740,8 +741,9 @@ static int take_base(dfpr_graph *g, int32_t max_iters, uint32_t *base)
 
 // Run iterations it0, it0+1, ... until the device sets the stop flag (or,
 // in the FP32 phase, the phase-end flag).  The phase starts on buffer
-// `base`; iteration i reads buffer base ^ ((i - it0) & 1).  *res_buf
-// receives the buffer holding the result.  Iterations are enqueued in
+// `base`; iteration i reads buffer base ^ ((i - it0) & 1), or, in the
+// asynchronous form (FP64 only), reads and writes buffer `base` in place.
+// *res_buf receives the buffer holding the result.  Iterations are enqueued in
 // chunks; between chunks the host reads the control block once and sizes
 // the next chunk from the observed geometric decay of Delta R, so few
 // launches run after convergence.
@@ -766,6 +768,7 @@ static int run_loop(dfpr_graph *g, const dfpr_params &p, bool df, bool f32, uint
                     int it0, int base, int *res_buf)
 {
     IterArgs a = iter_args(g, p, sbase);
+    const bool async = p.mode == DFPR_ASYNC && !f32;
     int it = it0, chunk = 4;
     uint32_t gsz = (uint32_t)g->grid;
     double prev_dr = -1.0;
@@ -775,11 +778,12 @@ static int run_loop(dfpr_graph *g, const dfpr_params &p, bool df, bool f32, uint
         const int k = std::min(chunk, p.max_iters - it);
         for (int j = 0; j < k; j++) {
             const int i = it + j;
-            const int src = base ^ ((i - it0) & 1);
+            const int src = async ? base : base ^ ((i - it0) & 1);
+            const int dst = async ? base : src ^ 1;
             a.Rc = g->R[src];
             a.Cc = g->C[src];
-            a.Rn = g->R[src ^ 1];
-            a.Cn = g->C[src ^ 1];
+            a.Rn = g->R[dst];
+            a.Cn = g->C[dst];
             a.C32c = g->C32[src];
             a.C32n = g->C32[src ^ 1];
             a.it = i;
@@ -824,7 +828,7 @@ static int run_loop(dfpr_graph *g, const dfpr_params &p, bool df, bool f32, uint
         DFPR_HIP(hipStreamSynchronize(g->stream));
     }
     const Ctl &c = *g->ctl_host;
-    *res_buf = base ^ ((c.iterations - it0) & 1);
+    *res_buf = async ? base : base ^ ((c.iterations - it0) & 1);
     if (g->prof.enabled) {
         const int64_t dv = (int64_t)c.verts - g->prof_base[0];
         const int64_t de = (int64_t)c.edges - g->prof_base[1];

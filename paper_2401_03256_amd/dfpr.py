@@ -26,6 +26,8 @@ DFPR_E_BUSY = -5
 DFPR_E_LIMIT = -6
 FP64 = 0
 FP32_KAHAN = 1
+SYNC = 0
+ASYNC = 1
 
 EXPORTED = [
     "dfpr_params_default", "dfpr_load_graph", "dfpr_free_graph", "dfpr_set_stream",
@@ -49,7 +51,8 @@ class DfprError(RuntimeError):
 class Params(ctypes.Structure):
     _fields_ = [("alpha", ctypes.c_double), ("tol", ctypes.c_double),
                 ("frontier_tol", ctypes.c_double), ("max_iters", ctypes.c_int32),
-                ("precision", ctypes.c_int32)]
+                ("precision", ctypes.c_int32), ("mode", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
 
 
 class _Stats(ctypes.Structure):
@@ -184,7 +187,8 @@ def _i32(a):
     return np.ascontiguousarray(a, dtype=np.int32)
 
 
-def params(alpha=None, tol=None, frontier_tol=None, max_iters=None, precision=None) -> Params:
+def params(alpha=None, tol=None, frontier_tol=None, max_iters=None, precision=None,
+           mode=None) -> Params:
     p = Params()
     lib().dfpr_params_default(ctypes.byref(p))
     if alpha is not None:
@@ -199,6 +203,8 @@ def params(alpha=None, tol=None, frontier_tol=None, max_iters=None, precision=No
         p.max_iters = max_iters
     if precision is not None:
         p.precision = precision
+    if mode is not None:
+        p.mode = mode
     return p
 
 

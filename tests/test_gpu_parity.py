@@ -577,3 +577,38 @@ def test_dynamic_traversal_matches_oracle(dfpr):
     assert np.array_equal(R[nA:], R0[nA:])           # unreached component untouched
     Rref, _ = o.reference()
     assert np.max(np.abs(R - Rref)) < TOL_RANK
+
+
+# ---------------------------------------------------------------------------
+# asynchronous form (tolerance-only parity: in-place updates race)
+# ---------------------------------------------------------------------------
+
+def test_async_form_reaches_the_reference(dfpr):
+    n, src, dst = synth.rmat(13, 16, seed=31)
+    g, o = _pair(dfpr, n, src, dst)
+    pa = dfpr.params(frontier_tol=1e-13, mode=dfpr.ASYNC)
+    ps = dfpr.params(frontier_tol=1e-13)
+    Ra, sa = g.static(pa)
+    Rref, _ = o.reference()
+    assert sa.converged and np.max(np.abs(Ra - Rref)) < TOL_RANK
+    counts = [synth.batch_counts(f, o.m) for f in (1e-4, 1e-3)]
+    for i, b in enumerate(synth.batch_sequence(src, dst, n, counts, seed=32)):
+        _say(f"async batch {i}")
+        R_prev = g.ranks()
+        g.apply_batch(b)
+        o.apply_batch(b)
+        Rref, _ = o.reference()
+        Rs, ss = g.dynamic_frontier(b, p=ps)
+        g.set_ranks(R_prev)
+        Rd, sd = g.dynamic_frontier(b, p=pa)
+        g.set_ranks(R_prev)
+        Rt, st_ = g.dynamic_traversal(b, p=pa)
+        g.set_ranks(R_prev)
+        Rn, sn = g.naive_dynamic(p=pa)
+        for R, s_ in ((Rd, sd), (Rt, st_), (Rn, sn)):
+            assert s_.converged
+            assert np.max(np.abs(R - Rref)) < TOL_RANK
+        assert np.max(np.abs(Rd - Rs)) < TOL_RANK
+        g.set_ranks(Rd)
+    with pytest.raises(dfpr.DfprError):
+        g.static(dfpr.params(mode=7))
