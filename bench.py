@@ -83,10 +83,12 @@ def main():
     ap.add_argument("--frontier-tol", type=float, default=1e-13)
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--workload", default="rmat22", choices=["rmat22", "grid", "fp32", "serve"],
+    ap.add_argument("--workload", default="rmat22",
+                    choices=["rmat22", "grid", "fp32", "serve", "sweep"],
                     help="rmat22: the headline line; grid: 4096x4096 grid, uniform and "
                          "localised batches; fp32: R-MAT scale 24, FP32 storage form vs FP64; "
-                         "serve: 12 resident R-MAT graphs, Poisson update stream")
+                         "serve: 12 resident R-MAT graphs, Poisson update stream; sweep: "
+                         "frontier tolerance and insertion/deletion mixes on R-MAT scale 22")
     ap.add_argument("--serve", action="store_true", help="same as --workload serve")
     ap.add_argument("--serve-requests", type=int, default=96)
     ap.add_argument("--serve-load", type=float, default=0.9,
@@ -117,6 +119,9 @@ def main():
         return
     if args.workload == "fp32":
         fp32_bench(args, dfpr, synth)
+        return
+    if args.workload == "sweep":
+        sweep_bench(args, dfpr, synth)
         return
     fracs = [float(x) for x in args.fracs.split(",")]
     workload = f"rmat{args.scale}_ef{args.edge_factor}_df_fp64"
@@ -440,6 +445,91 @@ def fp32_bench(args, dfpr, synth, scale=24, per_size=5):
                    "max_rel_linf_fp32_phase": max(r["rel_linf_fp32_phase"] for r in rows)}
     print(json.dumps({"metric": METRIC, "workload": f"rmat{scale}_ef16_fp32_form_vs_fp64",
                       "n": n, "m": m, "by_frac": summ}), flush=True)
+
+
+def sweep_bench(args, dfpr, synth, scale=22):
+    """Frontier tolerance sweep (Section 4.3, Figure 3) and batch mixes
+    (Section 5.2: insertions only, deletions only, 80/20) on R-MAT scale 22.
+    Errors are L1 against a reference Static on the updated graph (tolerance
+    0, at most 500 iterations: Section 5.1.5), computed on the GPU."""
+    t = time.time()
+    n, src, dst = synth.rmat(scale, 16, seed=1)
+    g = dfpr.Graph(n, src, dst)
+    m = g.m
+    log(f"R-MAT scale {scale}: n={n} m={m} ({time.time() - t:.1f}s)")
+    tol = 1e-10
+    pref = dfpr.params(tol=0.0, max_iters=500)
+    g.static(dfpr.params(), out=False)
+
+    def reference():
+        R_keep = g.ranks()
+        Rr, sr = g.static(pref)
+        g.set_ranks(R_keep)
+        return Rr
+
+    def l1(R, Rr):
+        return float(np.sum(np.abs(R - Rr)))
+
+    out = {"metric": METRIC, "workload": f"rmat{scale}_ef16_sweep", "n": n, "m": m}
+    # frontier tolerance, three 1e-5 |E| batches
+    ftols = [tol / 10 ** k for k in range(6)]
+    seq = synth.batch_sequence(src, dst, n, [synth.batch_counts(1e-5, m)] * 3, seed=40)
+    sweep = {str(f): {"ms": [], "l1": [], "affected": [], "iterations": []} for f in ftols}
+    nv = {"ms": [], "l1": []}
+    for b in seq:
+        R_prev = g.ranks()
+        g.apply_batch(b)
+        Rr = reference()
+        for f in ftols:
+            g.set_ranks(R_prev)
+            R, st = g.dynamic_frontier(b, p=dfpr.params(tol=tol, frontier_tol=f))
+            d = sweep[str(f)]
+            d["ms"].append(st.ms_device)
+            d["l1"].append(l1(R, Rr))
+            d["affected"].append(st.affected_final)
+            d["iterations"].append(st.iterations)
+        g.set_ranks(R_prev)
+        R, st = g.naive_dynamic(p=dfpr.params(tol=tol))
+        nv["ms"].append(st.ms_device)
+        nv["l1"].append(l1(R, Rr))
+        g.set_ranks(R)
+    out["frontier_tol_sweep"] = {
+        f: {"df_ms_mean": round(float(np.mean(d["ms"])), 3),
+            "l1_mean": float(np.mean(d["l1"])),
+            "affected_mean": int(np.mean(d["affected"])),
+            "iterations_mean": round(float(np.mean(d["iterations"])), 1)}
+        for f, d in sweep.items()}
+    out["frontier_tol_sweep"]["naive_dynamic"] = {"ms_mean": round(float(np.mean(nv["ms"])), 3),
+                                                  "l1_mean": float(np.mean(nv["l1"]))}
+    for f, d in out["frontier_tol_sweep"].items():
+        log(f"tau_f {f}: {d}")
+    # batch mixes
+    mixes = {}
+    fp = dfpr.params(tol=tol, frontier_tol=args.frontier_tol)
+    for frac in (1e-7, 1e-5, 1e-3):
+        bsz = max(1, int(round(frac * m)))
+        for kind, cnt in (("insertions", (0, bsz)), ("deletions", (bsz, 0)),
+                          ("mixed_80_20", synth.batch_counts(frac, m))):
+            b = synth.batch_sequence(src, dst, n, [cnt], seed=50 + len(mixes))[0]
+            R_prev = g.ranks()
+            g.apply_batch(b)
+            Rr = reference()
+            g.set_ranks(R_prev)
+            Rd, sd = g.dynamic_frontier(b, p=fp)
+            g.set_ranks(R_prev)
+            Rn, sn = g.naive_dynamic(p=fp)
+            Rs, ss = g.static(fp)
+            key = f"{kind}_{frac}"
+            mixes[key] = {"df_ms": round(sd.ms_device, 3), "naive_ms": round(sn.ms_device, 3),
+                          "static_ms": round(ss.ms_device, 3),
+                          "speedup_vs_static": round(ss.ms_device / sd.ms_device, 2),
+                          "speedup_vs_naive": round(sn.ms_device / sd.ms_device, 2),
+                          "df_l1": l1(Rd, Rr), "naive_l1": l1(Rn, Rr), "static_l1": l1(Rs, Rr),
+                          "df_affected": sd.affected_final}
+            g.set_ranks(Rd)
+            log(f"{key}: {mixes[key]}")
+    out["batch_mixes"] = mixes
+    print(json.dumps(out), flush=True)
 
 
 def serve_bench(args, dfpr, synth):

@@ -612,3 +612,26 @@ def test_async_form_reaches_the_reference(dfpr):
         g.set_ranks(Rd)
     with pytest.raises(dfpr.DfprError):
         g.static(dfpr.params(mode=7))
+
+
+# ---------------------------------------------------------------------------
+# frontier tolerance and batch mixes (against the oracle with the same tau_f)
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("ftol", [1e-10, 1e-12, 1e-15])
+@pytest.mark.parametrize("mix", ["insertions", "deletions"])
+def test_frontier_tolerance_and_batch_mix(dfpr, ftol, mix):
+    n, src, dst = synth.rmat(12, 16, seed=41)
+    g, o = _pair(dfpr, n, src, dst)
+    R0, _ = g.static()
+    Ro, _ = o.static()
+    bsz = 60
+    cnt = (0, bsz) if mix == "insertions" else (bsz, 0)
+    b = synth.batch_sequence(src, dst, n, [cnt], seed=42)[0]
+    assert g.apply_batch(b) == o.apply_batch(b)
+    R, st = g.dynamic_frontier(b, p=dfpr.params(frontier_tol=ftol))
+    Rd, sto, _, f1 = o.dynamic_frontier(b, Ro, frontier_tol=ftol, return_flags=True)
+    assert st.converged and np.max(np.abs(R - Rd)) < TOL_RANK
+    assert abs(st.iterations - sto.iterations) <= 1
+    # marks near tau_f may differ with summation order, only by a few rows
+    assert abs(st.affected_final - int(f1.sum())) <= max(5, int(f1.sum()) // 100)
