@@ -377,8 +377,35 @@ def grid_bench(args, dfpr, synth, side=4096, kinds=("uniform", "localised"), per
             "dt_affected": st_dt.affected_final,
             "speedup_vs_dt": round(st_dt.ms_device / rows[-1].ms_device, 2),
         }
+    # frontier tolerance on localised batches (the paper leaves an adaptive
+    # tau_f to future work; this compares fixed values): one more localised
+    # batch, each tau_f from the same previous ranks, L1 against a reference
+    # Static of the updated graph
+    # Each variant starts from the reference ranks of the graph before the
+    # batch: on this graph (mean rank 6e-8) ranks that stopped at an L-inf
+    # change of tau carry an L1 error of ~1e-4 that would hide tau_f.
+    extra = synth.localized_batch(src, dst, side, nd, ni, seed=99)
+    pref = dfpr.params(tol=0.0, max_iters=500)
+    R_df_end = g.ranks()
+    R_prev, _ = g.static(pref)
+    g.apply_batch(extra)
+    Rr, _ = g.static(pref)
+    ftol_cmp = {}
+    for f in (1e-11, 1e-12, 1e-13, 1e-15):
+        g.set_ranks(R_prev)
+        R, st = g.dynamic_frontier(extra, p=dfpr.params(frontier_tol=f))
+        ftol_cmp[str(f)] = {"df_ms": round(st.ms_device, 3), "iterations": st.iterations,
+                            "affected": st.affected_final,
+                            "l1": float(np.sum(np.abs(R - Rr)))}
+        log(f"localised, tau_f {f}: {ftol_cmp[str(f)]}")
+    g.set_ranks(R_prev)
+    R, st = g.naive_dynamic(p=dfpr.params())
+    ftol_cmp["naive_dynamic"] = {"ms": round(st.ms_device, 3), "iterations": st.iterations,
+                                 "l1": float(np.sum(np.abs(R - Rr)))}
+    g.set_ranks(R_df_end)
     out = {"metric": METRIC, "workload": f"grid{side}_diag5_df_fp64", "n": n, "m": m,
            "batch": [nd, ni], "static_ms": round(st0.ms_device, 3),
+           "localised_frontier_tol": ftol_cmp,
            "static_iterations": st0.iterations,
            "static_gteps": round(st0.edges_processed / st0.ms_device / 1e6, 2), "kinds": res}
     for kind in res:
