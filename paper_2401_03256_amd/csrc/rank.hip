@@ -290,6 +290,69 @@ __global__ void k_validate(int32_t n, int64_t nd, const int32_t *ds, const int32
 // light list (out-row scanned by one wave) or a heavy list (scanned by the
 // whole grid in workgroup-sized chunks), and their out-degrees are summed.
 constexpr uint32_t kHeavyRow = 2048;   // out-rows longer than this use the grid
+constexpr uint32_t kHeavySeg = 2048;   // heavy vertices whose chunk offsets sit in LDS at once
+
+struct HeavyShared {
+    uint32_t pre[kHeavySeg + 1];       // chunk offsets of a segment of heavy vertices
+    uint32_t part[kBlock];
+};
+
+// Walk the out-rows of the heavy vertices list[0 .. nh) in chunks of kBlock
+// out-edges: chunk c of the concatenated rows goes to workgroup
+// c mod gridDim.x.  Each workgroup finds the vertex of a chunk by binary
+// search over the chunk offsets, which it builds in LDS for up to
+// kHeavySeg vertices at a time, so no workgroup walks the list serially.
+// visit(x) is called by every thread of the workgroup with the same trip
+// count (x < 0: no vertex).
+template <class F>
+__device__ inline void walk_heavy(const IterArgs &a, const int32_t *list, uint32_t nh,
+                                  HeavyShared &sh, F &&visit)
+{
+    constexpr uint32_t per = kHeavySeg / kBlock;
+    for (uint32_t h0 = 0; h0 < nh; h0 += kHeavySeg) {
+        const uint32_t seg = min(kHeavySeg, nh - h0);
+        // per thread: chunk counts of `per` consecutive vertices, then a scan
+        // of the thread totals
+        uint32_t cnt[per], tot = 0;
+#pragma unroll
+        for (uint32_t j = 0; j < per; j++) {
+            const uint32_t i = threadIdx.x * per + j;
+            cnt[j] = i < seg ? (a.out_cnt[list[h0 + i]] + kBlock - 1) / kBlock : 0u;
+            tot += cnt[j];
+        }
+        sh.part[threadIdx.x] = tot;
+        __syncthreads();
+        for (int o = 1; o < kBlock; o <<= 1) {
+            const uint32_t t = threadIdx.x >= (uint32_t)o ? sh.part[threadIdx.x - o] : 0u;
+            __syncthreads();
+            sh.part[threadIdx.x] += t;
+            __syncthreads();
+        }
+        uint32_t run = sh.part[threadIdx.x] - tot;
+#pragma unroll
+        for (uint32_t j = 0; j < per; j++) {
+            const uint32_t i = threadIdx.x * per + j;
+            if (i < seg) sh.pre[i] = run;
+            run += cnt[j];
+        }
+        if (threadIdx.x == kBlock - 1) sh.pre[seg] = sh.part[kBlock - 1];
+        __syncthreads();
+        const uint32_t total = sh.pre[seg];
+        for (uint32_t c = blockIdx.x; c < total; c += gridDim.x) {
+            uint32_t lo = 0, hi = seg;      // last h with pre[h] <= c
+            while (hi - lo > 1) {
+                const uint32_t mid = (lo + hi) / 2;
+                if (sh.pre[mid] <= c) lo = mid;
+                else hi = mid;
+            }
+            const int32_t u = list[h0 + lo];
+            const uint32_t k = (c - sh.pre[lo]) * kBlock + threadIdx.x;
+            const uint32_t oc = a.out_cnt[u];
+            visit(k < oc ? a.out_idx[a.out_beg[u] + k] : -1);
+        }
+        __syncthreads();
+    }
+}
 
 __global__ __launch_bounds__(kBlock) void k_mark_claim(IterArgs a, int64_t nd, const int32_t *ds,
                                                        int64_t ni, const int32_t *is,
@@ -372,15 +435,8 @@ __global__ __launch_bounds__(kBlock) void k_mark_initial(IterArgs a, int64_t nd,
             mark_one(a, k < oc ? a.out_idx[ob + k] : -1, append, mine);
         }
     }
-    for (uint32_t h = 0; h < nh; h++) {
-        const int32_t u = heavy[h];
-        const uint32_t ob = a.out_beg[u], oc = a.out_cnt[u];
-        const uint32_t chunks = (oc + kBlock - 1) / kBlock;
-        for (uint32_t c = blockIdx.x; c < chunks; c += gridDim.x) {
-            const uint32_t k = c * kBlock + threadIdx.x;
-            mark_one(a, k < oc ? a.out_idx[ob + k] : -1, append, mine);
-        }
-    }
+    __shared__ HeavyShared hs;
+    walk_heavy(a, heavy, nh, hs, [&](int32_t x) { mark_one(a, x, append, mine); });
     if (lane == 0 && mine) atomicAdd(&s_new, mine);
     __syncthreads();
     if (threadIdx.x == 0 && s_new) atomicAdd(&ctl->affected0, s_new);
@@ -501,15 +557,8 @@ __global__ __launch_bounds__(kBlock) void k_bfs_level(IterArgs a, BfsQueues q, i
             bfs_claim(a, y, q, append != 0, mine);
         }
     }
-    for (uint32_t h = 0; h < nh; h++) {
-        const int32_t u = q.hin[h];
-        const uint32_t ob = a.out_beg[u], oc = a.out_cnt[u];
-        const uint32_t chunks = (oc + kBlock - 1) / kBlock;
-        for (uint32_t c = blockIdx.x; c < chunks; c += gridDim.x) {
-            const uint32_t k = c * kBlock + threadIdx.x;
-            bfs_claim(a, k < oc ? a.out_idx[ob + k] : -1, q, append != 0, mine);
-        }
-    }
+    __shared__ HeavyShared hs;
+    walk_heavy(a, q.hin, nh, hs, [&](int32_t x) { bfs_claim(a, x, q, append != 0, mine); });
     if (lane == 0 && mine) atomicAdd(&s_new, mine);
     __syncthreads();
     if (threadIdx.x == 0 && s_new) atomicAdd(&a.ctl->affected0, s_new);
