@@ -68,7 +68,7 @@ struct ApplyArgs {
     int64_t nd, ni;
     const int32_t *ds, *dd, *is, *id;
     uint64_t *keys[2];          // unsorted / sorted keys per orientation
-    uint32_t *small_list[2], *big_list[2], *ovf_list[2];
+    uint32_t *tiny_list[2], *small_list[2], *big_list[2], *ovf_list[2];
     int32_t *ovf_need[2];
     uint32_t *beg[2], *cnt[2], *cap[2];
     int32_t *idx[2];
@@ -85,7 +85,7 @@ __global__ void k_apply_reset(Ctl *ctl)
         ctl->err = 0;
         ctl->cls_moved = 0;
         for (int o = 0; o < 2; o++) {
-            ctl->nsmall[o] = ctl->nbig[o] = ctl->novf[o] = 0;
+            ctl->ntiny[o] = ctl->nsmall[o] = ctl->nbig[o] = ctl->novf[o] = 0;
             ctl->applied[o] = 0;
         }
     }
@@ -176,27 +176,158 @@ __global__ void k_heads(ApplyArgs a, uint32_t len)
     const int o = blockIdx.y;
     const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
     const uint64_t *keys = a.keys[o];
-    bool head = false, big = false;
+    // rows by the capacity they had before the batch and their number of
+    // batch entries: 0 = at most kWave of each (one wave), 1 = copied to
+    // LDS (one workgroup), 2 = larger (workgroup with a global slab)
+    bool head = false;
+    int which_row = 1;
     if (i < len) {
         const uint64_t k = keys[i];
         if (k != kSentinel) {
             const uint32_t r = key_row(k);
             head = i == 0 || key_row(keys[i - 1]) != r;
-            if (head) big = a.cap[o][r] > (uint32_t)kRowLds;
+            if (head) {
+                const uint32_t cap = a.cap[o][r];
+                if (cap > (uint32_t)kRowLds) {
+                    which_row = 2;
+                } else if (cap <= (uint32_t)kWave) {
+                    // keys are sorted: at most kWave entries unless the
+                    // entry kWave places on is still in this row
+                    if (i + (uint32_t)kWave >= len || key_row(keys[i + kWave]) != r)
+                        which_row = 0;
+                }
+            }
         }
     }
     const int lane = __lane_id();
     const unsigned long long below = (1ull << lane) - 1ull;
-    for (int which = 0; which < 2; which++) {
-        const bool take = head && (big == (which == 1));
+    for (int which = 0; which < 3; which++) {
+        const bool take = head && which_row == which;
         const unsigned long long m = __ballot(take);
         if (!m) continue;
         const int leader = __ffsll((long long)m) - 1;
+        uint32_t *cnt = which == 0 ? &a.ctl->ntiny[o] : which == 1 ? &a.ctl->nsmall[o]
+                                                                    : &a.ctl->nbig[o];
+        uint32_t *list = which == 0 ? a.tiny_list[o] : which == 1 ? a.small_list[o]
+                                                                   : a.big_list[o];
         uint32_t base = 0;
-        if (lane == leader)
-            base = atomicAdd(which ? &a.ctl->nbig[o] : &a.ctl->nsmall[o], (uint32_t)__popcll(m));
+        if (lane == leader) base = atomicAdd(cnt, (uint32_t)__popcll(m));
         base = __shfl(base, leader);
-        if (take) (which ? a.big_list[o] : a.small_list[o])[base + __popcll(m & below)] = i;
+        if (take) list[base + __popcll(m & below)] = i;
+    }
+}
+
+// Lanes 0 .. len-1 hold v in ascending order: how many of them are below x.
+// Every lane of the wave calls it.
+template <class T>
+__device__ inline uint32_t lanes_below(T v, uint32_t len, T x)
+{
+    uint32_t pos = 0;
+#pragma unroll
+    for (uint32_t step = kWave; step > 0; step >>= 1) {
+        const T y = __shfl(v, (int)min(pos + step - 1, (uint32_t)kWave - 1));
+        if (pos + step <= len && y < x) pos += step;
+    }
+    return pos;
+}
+
+__device__ inline unsigned long long lanes_mask(uint32_t k)
+{
+    return k >= (uint32_t)kWave ? ~0ull : (1ull << k) - 1ull;
+}
+
+// Rows of at most kWave slots touched by at most kWave batch entries: one
+// wave per row, entries and operations one per lane, with the same rules as
+// the workgroup path below (distinct operations; a deletion takes effect if
+// the entry is present, an insertion if it is absent or deleted by the same
+// batch; survivors shift left past effective deletions and right past
+// effective insertions; a row that outgrows its slots moves to free space at
+// the top, or is left for a re-layout).
+__global__ __launch_bounds__(kBlock) void k_apply_tiny(ApplyArgs a, uint32_t len)
+{
+    const int o = blockIdx.y;
+    Ctl *ctl = a.ctl;
+    if (ctl->err) return;
+    const uint32_t count = ctl->ntiny[o];
+    const uint64_t *keys = a.keys[o];
+    uint32_t *beg_a = a.beg[o], *cnt_a = a.cnt[o], *cap_a = a.cap[o];
+    int32_t *idx = a.idx[o];
+    const int lane = __lane_id();
+    const unsigned long long below = (1ull << lane) - 1ull;
+    const uint32_t wave = (blockIdx.x * blockDim.x + threadIdx.x) / kWave;
+    const uint32_t waves = gridDim.x * kWavesPerBlock;
+    unsigned long long sum_del = 0, sum_ins = 0;
+    for (uint32_t t = wave; t < count; t += waves) {
+        const uint32_t start = a.tiny_list[o][t];
+        // operations (sorted by column, deletion before insertion)
+        const uint64_t kl = (uint32_t)lane < len - start ? keys[start + lane] : kSentinel;
+        const uint32_t row = key_row(__shfl(kl, 0));
+        const bool isop = kl != kSentinel && key_row(kl) == row;
+        const uint32_t nops = (uint32_t)__popcll(__ballot(isop));
+        const uint64_t k = isop ? kl : ~0ull;
+        const uint32_t beg = beg_a[row], cap = cap_a[row], c = cnt_a[row];
+        const uint64_t kp = __shfl_up(k, 1);
+        const bool first = isop && (lane == 0 || kp != k);
+        const int32_t col = isop ? key_col(k) : INT32_MAX;
+        const bool del = first && !(k & 1), ins = first && (k & 1);
+        // the row's entries (ascending)
+        const int32_t e = (uint32_t)lane < c ? idx[beg + lane] : INT32_MAX;
+        const uint32_t pb = lanes_below(e, c, col);
+        const int32_t at = __shfl(e, (int)min(pb, (uint32_t)kWave - 1));
+        const bool present = isop && pb < c && at == col;
+        const bool deleted_too = lane > 0 && isop && key_col(kp) == col && !(kp & 1);
+        const unsigned long long mdel = __ballot(del && present);
+        const unsigned long long mins = __ballot(ins && (!present || deleted_too));
+        const uint32_t ndel = (uint32_t)__popcll(mdel), nins = (uint32_t)__popcll(mins);
+        const uint32_t nc = c - ndel + nins;
+        uint32_t dest = beg, ncap = cap;
+        int ok = 1;
+        if (lane == 0 && nc > cap) {
+            const uint64_t want = (uint64_t)nc + (nc / 8 > 2 ? nc / 8 : 2);
+            const uint64_t top = atomicAdd(&ctl->top[o], (unsigned long long)want);
+            if (want <= 0xFFFFFFFFull && top + want <= a.slots[o]) {
+                dest = (uint32_t)top;
+                ncap = (uint32_t)want;
+                atomicMax(&ctl->max_cap[o], (uint32_t)want);
+            } else {
+                ok = 0;
+                const uint32_t slot = atomicAdd(&ctl->novf[o], 1u);
+                a.ovf_list[o][slot] = start;
+                a.ovf_need[o][slot] = (int32_t)(c + nops);
+            }
+        }
+        dest = __shfl(dest, 0);
+        ncap = __shfl(ncap, 0);
+        ok = __shfl(ok, 0);
+        if (!ok) continue;
+        // entry e: operations below it, and whether a deletion removes it
+        const uint32_t ob = lanes_below(col, nops, e);
+        const int32_t ocol = __shfl(col, (int)min(ob, (uint32_t)kWave - 1));
+        const bool gone = ob < nops && ((mdel >> ob) & 1ull) && ocol == e;
+        if ((uint32_t)lane < c && !gone)
+            idx[dest + lane - __popcll(mdel & lanes_mask(ob)) + __popcll(mins & lanes_mask(ob))] =
+                e;
+        // insertion: entries below it that survive, then earlier insertions
+        const uint32_t lo = lanes_below(col, nops, col);
+        if ((mins >> lane) & 1ull)
+            idx[dest + pb - __popcll(mdel & lanes_mask(lo)) + __popcll(mins & below)] = col;
+        if (lane == 0) {
+            if (o == 0 && bin_of(c) != bin_of(nc)) ctl->cls_moved = 1;
+            cnt_a[row] = nc;
+            beg_a[row] = dest;
+            cap_a[row] = ncap;
+            if (o == 1) {
+                sum_del += ndel;
+                sum_ins += nins;
+                // |out(row)| changed: refresh the stored contributions
+                a.C0[row] = a.R0[row] / (double)nc;
+                a.C1[row] = a.R1[row] / (double)nc;
+            }
+        }
+    }
+    if (lane == 0 && o == 1 && (sum_del | sum_ins)) {
+        atomicAdd(&ctl->applied[0], sum_del);
+        atomicAdd(&ctl->applied[1], sum_ins);
     }
 }
 
@@ -496,7 +627,8 @@ static int ensure_apply_bufs(dfpr_graph *g, uint64_t B)
             ap.keys[o][k] = nullptr;
             DFPR_HIP(hipMalloc(&ap.keys[o][k], cap * 8));
         }
-        uint32_t **lists[3] = {&ap.small_list[o], &ap.big_list[o], &ap.ovf_list[o]};
+        uint32_t **lists[4] = {&ap.tiny_list[o], &ap.small_list[o], &ap.big_list[o],
+                               &ap.ovf_list[o]};
         for (auto l : lists) {
             (void)hipFree(*l);
             *l = nullptr;
@@ -594,6 +726,7 @@ static ApplyArgs apply_args(dfpr_graph *g)
     ApplyArgs a{};
     a.n = g->n;
     for (int o = 0; o < 2; o++) {
+        a.tiny_list[o] = g->ap.tiny_list[o];
         a.small_list[o] = g->ap.small_list[o];
         a.big_list[o] = g->ap.big_list[o];
         a.ovf_list[o] = g->ap.ovf_list[o];
@@ -708,6 +841,8 @@ int apply_batch_impl(dfpr_graph *g, int64_t n_del, const int32_t *ds, const int3
     a.keys[0] = g->ap.keys[0][pp];
     a.keys[1] = g->ap.keys[1][pp];
     k_heads<<<dim3(grid_for(B), 2), kBlock, 0, s>>>(a, B);
+    k_apply_tiny<<<dim3(std::min<unsigned>(grid_for(B, kWavesPerBlock), 4096), 2), kBlock, 0, s>>>(
+        a, B);
     k_apply_rows<false><<<dim3(std::min<unsigned>(B, 8192), 2), kBlock, 0, s>>>(a, B, -1);
     k_apply_rows<true><<<dim3(kBigGrid, 2), kBlock, 0, s>>>(a, B, -1);
     DFPR_HIP(hipGetLastError());

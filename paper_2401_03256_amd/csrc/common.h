@@ -59,7 +59,8 @@ struct Ctl {
     uint32_t mk_light;          // initial marking: claimed sources scanned by one wave
     uint32_t mk_heavy;          //   ... and by the whole grid
     unsigned long long reach;   //   out-edges of the claimed sources
-    uint32_t nsmall[2];         // batch applier: touched rows per orientation
+    uint32_t ntiny[2];          // batch applier: touched rows of at most 64 slots and 64 ops
+    uint32_t nsmall[2];         //   ... touched rows copied to LDS
     uint32_t nbig[2];           //   ... rows whose capacity exceeds the LDS copy
     uint32_t novf[2];           //   ... rows that need a re-layout
     uint32_t max_cap[2];        //   largest row capacity
@@ -98,7 +99,8 @@ struct Profile {
 struct ApplyBufs {
     uint64_t cap = 0;               // batch entries the buffers hold
     uint64_t *keys[2][2] = {};      // [orientation][ping-pong]
-    uint32_t *small_list[2] = {};   // op index where each touched row starts
+    uint32_t *tiny_list[2] = {};    // op index where each touched row starts, by row size
+    uint32_t *small_list[2] = {};
     uint32_t *big_list[2] = {};
     uint32_t *ovf_list[2] = {};
     int32_t *ovf_need[2] = {};      // capacity an overflowed row needs

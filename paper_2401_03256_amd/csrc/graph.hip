@@ -305,6 +305,7 @@ void dfpr_free_graph(dfpr_graph *g)
     (void)hipFree(g->it.cnt_part);
     for (int o = 0; o < 2; o++) {
         for (int k = 0; k < 2; k++) (void)hipFree(g->ap.keys[o][k]);
+        (void)hipFree(g->ap.tiny_list[o]);
         (void)hipFree(g->ap.small_list[o]);
         (void)hipFree(g->ap.big_list[o]);
         (void)hipFree(g->ap.ovf_list[o]);
