@@ -35,6 +35,14 @@ constexpr int kTile = 2048;    // keys sorted per workgroup in LDS
 constexpr int kOpsLds = 1024;  // batch entries of one row per round
 constexpr int kRowLds = 4096;  // rows up to this capacity are copied to LDS
 constexpr int kBigGrid = 64;   // workgroups (and slabs) for larger rows
+// Workgroups of the three row kernels.  Each workgroup of the out-row pass
+// leaves its applied counts in its own pair of slots of ApplyBufs::part,
+// folded once afterwards: tens of thousands of atomics on one address
+// would serialise.
+constexpr int kCopyUnroll = 8;  // row entries loaded per thread before use
+constexpr int kTinyGrid = 4096;
+constexpr int kSmallGrid = 8192;
+constexpr int kPartSlots = 2 * (kTinyGrid + kSmallGrid + kBigGrid);
 
 __device__ inline uint32_t key_row(uint64_t k) { return (uint32_t)(k >> 33); }
 __device__ inline int32_t key_col(uint64_t k) { return (int32_t)((k >> 1) & 0xFFFFFFFFull); }
@@ -63,6 +71,23 @@ __device__ inline uint32_t upper_bound_dev(const T *a, uint32_t len, T x)
     return lo;
 }
 
+
+// First index at or after lo whose element is not below x, for a cursor that
+// only moves forward (every element before lo is below x): steps that double
+// from lo, then a binary search inside the last step.
+template <typename T>
+__device__ inline uint32_t gallop_dev(const T *a, uint32_t lo, uint32_t len, T x)
+{
+    uint32_t hi = lo, step = 1;
+    while (hi < len && a[hi] < x) {
+        lo = hi + 1;
+        hi += step;
+        step <<= 1;
+    }
+    if (hi > len) hi = len;
+    return lo + lower_bound_dev(a + lo, hi - lo, x);
+}
+
 struct ApplyArgs {
     int32_t n;
     int64_t nd, ni;
@@ -76,8 +101,56 @@ struct ApplyArgs {
     double *R0, *R1, *C0, *C1;
     int32_t *slab;
     uint64_t slab_stride;
+    unsigned long long *part;   // null: add applied counts to Ctl directly
     Ctl *ctl;
 };
+
+// Applied counts of one out-row workgroup: into its slots of part, or
+// straight into Ctl when there are no slots.  Thread 0 holds the sums.
+__device__ inline void put_applied(const ApplyArgs &a, uint32_t slot, unsigned long long d,
+                                   unsigned long long i)
+{
+    if (a.part) {
+        a.part[2 * slot] = d;
+        a.part[2 * slot + 1] = i;
+    } else if (d | i) {
+        atomicAdd(&a.ctl->applied[0], d);
+        atomicAdd(&a.ctl->applied[1], i);
+    }
+}
+
+// Sum the applied counts that the launched workgroups of the three row
+// kernels left in part into Ctl.
+constexpr int kFoldThreads = 1024;
+
+__global__ __launch_bounds__(kFoldThreads) void k_apply_fold(const unsigned long long *part,
+                                                       uint32_t tiny_grid, uint32_t small_grid,
+                                                       Ctl *ctl)
+{
+    __shared__ unsigned long long s[2][kFoldThreads];
+    const uint32_t base[3] = {0, kTinyGrid, kTinyGrid + kSmallGrid};
+    const uint32_t used[3] = {tiny_grid, small_grid, kBigGrid};
+    unsigned long long d = 0, i = 0;
+    for (int r = 0; r < 3; r++)
+        for (uint32_t k = base[r] + threadIdx.x; k < base[r] + used[r]; k += kFoldThreads) {
+            d += part[2 * k];
+            i += part[2 * k + 1];
+        }
+    s[0][threadIdx.x] = d;
+    s[1][threadIdx.x] = i;
+    __syncthreads();
+    for (int st = kFoldThreads / 2; st > 0; st >>= 1) {
+        if (threadIdx.x < st) {
+            s[0][threadIdx.x] += s[0][threadIdx.x + st];
+            s[1][threadIdx.x] += s[1][threadIdx.x + st];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        ctl->applied[0] += s[0][0];
+        ctl->applied[1] += s[1][0];
+    }
+}
 
 __global__ void k_apply_reset(Ctl *ctl)
 {
@@ -187,15 +260,12 @@ __global__ void k_heads(ApplyArgs a, uint32_t len)
             const uint32_t r = key_row(k);
             head = i == 0 || key_row(keys[i - 1]) != r;
             if (head) {
-                const uint32_t cap = a.cap[o][r];
-                if (cap > (uint32_t)kRowLds) {
-                    which_row = 2;
-                } else if (cap <= (uint32_t)kWave) {
-                    // keys are sorted: at most kWave entries unless the
-                    // entry kWave places on is still in this row
-                    if (i + (uint32_t)kWave >= len || key_row(keys[i + kWave]) != r)
-                        which_row = 0;
-                }
+                // a row can grow by its number of entries over the rounds
+                // of the merge: only rows that stay within kRowLds go to LDS
+                const uint64_t cap = a.cap[o][r];
+                const uint32_t nops = gallop_dev(keys, i, len, (uint64_t)(r + 1) << 33) - i;
+                if (cap + nops > (uint64_t)kRowLds) which_row = 2;
+                else if (cap <= (uint64_t)kWave && nops <= (uint32_t)kWave) which_row = 0;
             }
         }
     }
@@ -325,9 +395,21 @@ __global__ __launch_bounds__(kBlock) void k_apply_tiny(ApplyArgs a, uint32_t len
             }
         }
     }
-    if (lane == 0 && o == 1 && (sum_del | sum_ins)) {
-        atomicAdd(&ctl->applied[0], sum_del);
-        atomicAdd(&ctl->applied[1], sum_ins);
+    if (o == 1) {
+        __shared__ unsigned long long s_sum[2][kWavesPerBlock];
+        const int w = threadIdx.x / kWave;
+        if (lane == 0) {
+            s_sum[0][w] = sum_del;
+            s_sum[1][w] = sum_ins;
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            for (int k = 1; k < kWavesPerBlock; k++) {
+                sum_del += s_sum[0][k];
+                sum_ins += s_sum[1][k];
+            }
+            put_applied(a, blockIdx.x, sum_del, sum_ins);
+        }
     }
 }
 
@@ -335,6 +417,17 @@ __global__ __launch_bounds__(kBlock) void k_apply_tiny(ApplyArgs a, uint32_t len
 // out[len] = total.  All threads of the workgroup call it.
 __device__ inline void block_scan_u8(const uint8_t *in, uint32_t len, uint32_t *out, uint32_t *tmp)
 {
+    if (len <= (uint32_t)kWave) {
+        // one wave: a ballot holds every flag
+        if (threadIdx.x < kWave) {
+            const uint32_t lane = threadIdx.x;
+            const unsigned long long m = __ballot(lane < len && in[lane] != 0);
+            if (lane < len) out[lane] = (uint32_t)__popcll(m & ((1ull << lane) - 1ull));
+            if (lane == 0) out[len] = (uint32_t)__popcll(m);
+        }
+        __syncthreads();
+        return;
+    }
     const uint32_t t = threadIdx.x, b = t * 4;
     uint32_t v[4], sum = 0;
 #pragma unroll
@@ -360,8 +453,34 @@ __device__ inline void block_scan_u8(const uint8_t *in, uint32_t len, uint32_t *
     __syncthreads();
 }
 
-// Merge the batch entries of touched rows into their rows.  BIG selects the
-// global-slab copy for rows whose capacity exceeds kRowLds.
+// Position of the first entry of a sorted row in global memory (c entries)
+// not below x, given smp[k] = row[k * stride] for k < ns = ceil(c / stride):
+// a search in the samples leaves fewer than stride candidates, halved while
+// more than kCopyUnroll remain, then counted with independent loads.
+__device__ inline uint32_t sampled_lower_bound(const int32_t *row, uint32_t c, const int32_t *smp,
+                                               uint32_t ns, uint32_t stride, int32_t x)
+{
+    const uint32_t k = lower_bound_dev(smp, ns, x);
+    if (k == 0) return 0;
+    uint32_t lo = (k - 1) * stride + 1;  // row[lo - 1] < x
+    uint32_t hi = min(k * stride, c);    // hi == c or row[hi] >= x
+    while (hi - lo > (uint32_t)kCopyUnroll) {
+        const uint32_t mid = (lo + hi) >> 1;
+        if (row[mid] < x) lo = mid + 1;
+        else hi = mid;
+    }
+    uint32_t below = 0;
+#pragma unroll
+    for (int u = 0; u < kCopyUnroll; u++)
+        if (lo + u < hi) below += row[lo + u] < x;
+    return lo + below;
+}
+
+// Merge the batch entries of touched rows into their rows.  Rows up to
+// kRowLds entries are copied to LDS.  Larger rows (BIG) are searched through
+// LDS samples; a row that moves to fresh slots is read in place, and a row
+// that stays copies only the part from its first operation on to a global
+// slab, since the entries before it keep their slots.
 template <bool BIG>
 __global__ __launch_bounds__(kBlock) void k_apply_rows(ApplyArgs a, uint32_t len, int only_o)
 {
@@ -371,9 +490,10 @@ __global__ __launch_bounds__(kBlock) void k_apply_rows(ApplyArgs a, uint32_t len
     __shared__ uint8_t s_fi[kOpsLds];
     __shared__ uint32_t s_pd[kOpsLds + 1];
     __shared__ uint32_t s_pi[kOpsLds + 1];
+    __shared__ uint32_t s_ipos[kOpsLds];  // row position of each insertion
     __shared__ uint32_t s_tmp[kBlock];
-    __shared__ int32_t s_row[BIG ? 1 : kRowLds];
-    __shared__ uint32_t s_dest, s_ncap;
+    __shared__ int32_t s_row[kRowLds];    // the row, or (BIG) its samples
+    __shared__ uint32_t s_dest, s_ncap, s_first;
     __shared__ int s_ok;
 
     const int o = only_o >= 0 ? only_o : blockIdx.y;
@@ -386,33 +506,28 @@ __global__ __launch_bounds__(kBlock) void k_apply_rows(ApplyArgs a, uint32_t len
     uint32_t *beg_a = a.beg[o], *cnt_a = a.cnt[o], *cap_a = a.cap[o];
     int32_t *idx = a.idx[o];
     // one slab per (workgroup, orientation): both orientations run at once
-    int32_t *buf = BIG ? a.slab + ((uint64_t)blockIdx.y * kBigGrid + blockIdx.x) * a.slab_stride
-                       : s_row;
+    int32_t *slab = BIG ? a.slab + ((uint64_t)blockIdx.y * kBigGrid + blockIdx.x) * a.slab_stride
+                        : nullptr;
 
+    unsigned long long sum_del = 0, sum_ins = 0;  // thread 0, out-rows
     for (uint32_t t = blockIdx.x; t < count; t += gridDim.x) {
         // list entries point at the first batch key of the row, or, for a
         // re-run after a re-layout, at the first key of the round that did
         // not fit (earlier rounds were applied)
         const uint32_t start = list[t];
         const uint32_t row = key_row(keys[start]);
-        const uint32_t end =
-            start + lower_bound_dev(keys + start, len - start, (uint64_t)(row + 1) << 33);
+        const uint32_t end = gallop_dev(keys, start, len, (uint64_t)(row + 1) << 33);
         for (uint32_t j0 = start; j0 < end; j0 += kOpsLds) {
             const uint32_t beg = beg_a[row], cap = cap_a[row];
             const uint32_t nops = min((uint32_t)kOpsLds, end - j0);
             // distinct deletions / insertions of this round (keys are sorted
             // by col then type, so repeats are adjacent)
-            for (uint32_t q = threadIdx.x; q < kOpsLds; q += kBlock) {
-                uint8_t fd = 0, fi = 0;
-                if (q < nops) {
-                    const uint32_t j = j0 + q;
-                    const uint64_t k = keys[j];
-                    const bool first = j == 0 || keys[j - 1] != k;
-                    fd = first && !(k & 1);
-                    fi = first && (k & 1);
-                }
-                s_fd[q] = fd;
-                s_fi[q] = fi;
+            for (uint32_t q = threadIdx.x; q < nops; q += kBlock) {
+                const uint32_t j = j0 + q;
+                const uint64_t k = keys[j];
+                const bool first = j == 0 || keys[j - 1] != k;
+                s_fd[q] = first && !(k & 1);
+                s_fi[q] = first && (k & 1);
             }
             __syncthreads();
             block_scan_u8(s_fd, nops, s_pd, s_tmp);
@@ -434,20 +549,58 @@ __global__ __launch_bounds__(kBlock) void k_apply_rows(ApplyArgs a, uint32_t len
                 __syncthreads();
                 break;
             }
-            for (uint32_t p = threadIdx.x; p < c; p += kBlock) buf[p] = idx[beg + p];
+            const int32_t *grow = idx + beg;  // the row in global memory
+            // BIG: one sample every `stride` entries, at most kRowLds
+            const uint32_t stride = BIG ? max(1u, (c + kRowLds - 1) / kRowLds) : 1;
+            const uint32_t ns = BIG ? (c + stride - 1) / stride : c;
+            // kCopyUnroll loads in flight per thread
+            for (uint32_t k0 = threadIdx.x; k0 < ns; k0 += kBlock * kCopyUnroll) {
+                int32_t v[kCopyUnroll];
+#pragma unroll
+                for (int u = 0; u < kCopyUnroll; u++) {
+                    const uint32_t k = k0 + u * kBlock;
+                    v[u] = k < ns ? grow[k * stride] : 0;
+                }
+#pragma unroll
+                for (int u = 0; u < kCopyUnroll; u++) {
+                    const uint32_t k = k0 + u * kBlock;
+                    if (k < ns) s_row[k] = v[u];
+                }
+            }
+            if (threadIdx.x == 0) s_first = c;
             __syncthreads();
-            // which entries take effect
+            // which entries take effect; s_first: where the first operation
+            // falls in the row
             for (uint32_t q = threadIdx.x; q < nd; q += kBlock) {
-                const uint32_t pos = lower_bound_dev(buf, c, s_d[q]);
-                s_fd[q] = pos < c && buf[pos] == s_d[q];
+                const int32_t col = s_d[q];
+                uint32_t pos;
+                bool present;
+                if (BIG) {
+                    pos = sampled_lower_bound(grow, c, s_row, ns, stride, col);
+                    present = pos < c && grow[pos] == col;
+                } else {
+                    pos = lower_bound_dev(s_row, c, col);
+                    present = pos < c && s_row[pos] == col;
+                }
+                s_fd[q] = present;
+                if (q == 0) atomicMin(&s_first, pos);
             }
             for (uint32_t q = threadIdx.x; q < ni; q += kBlock) {
                 const int32_t col = s_i[q];
-                const uint32_t pos = lower_bound_dev(buf, c, col);
-                const bool present = pos < c && buf[pos] == col;
+                uint32_t pos;
+                bool present;
+                if (BIG) {
+                    pos = sampled_lower_bound(grow, c, s_row, ns, stride, col);
+                    present = pos < c && grow[pos] == col;
+                } else {
+                    pos = lower_bound_dev(s_row, c, col);
+                    present = pos < c && s_row[pos] == col;
+                }
                 const uint32_t pd = lower_bound_dev(s_d, nd, col);
                 const bool deleted = pd < nd && s_d[pd] == col;
                 s_fi[q] = !present || deleted;
+                s_ipos[q] = pos;
+                if (q == 0) atomicMin(&s_first, pos);
             }
             __syncthreads();
             block_scan_u8(s_fd, nd, s_pd, s_tmp);
@@ -477,18 +630,53 @@ __global__ __launch_bounds__(kBlock) void k_apply_rows(ApplyArgs a, uint32_t len
             __syncthreads();
             if (!s_ok) break;
             const uint32_t dest = s_dest;
-            // surviving entries shift left past deletions, right past insertions
-            for (uint32_t p = threadIdx.x; p < c; p += kBlock) {
-                const int32_t e = buf[p];
-                const uint32_t kd = lower_bound_dev(s_d, nd, e);
-                if (kd < nd && s_d[kd] == e) continue;
-                const uint32_t ki = lower_bound_dev(s_i, ni, e);
-                idx[dest + p - s_pd[kd] + s_pi[ki]] = e;
+            // Entries [lo, c) are rewritten: all of them when the row moves,
+            // else (BIG) those from the first operation on, staged in the
+            // slab so that no slot is written before it is read.
+            const bool moved = dest != beg;
+            const uint32_t lo = BIG && !moved ? s_first : 0;
+            if (BIG && !moved) {
+                for (uint32_t p0 = lo + threadIdx.x; p0 < c; p0 += kBlock * kCopyUnroll) {
+                    int32_t v[kCopyUnroll];
+#pragma unroll
+                    for (int u = 0; u < kCopyUnroll; u++) {
+                        const uint32_t p = p0 + u * kBlock;
+                        v[u] = p < c ? grow[p] : 0;
+                    }
+#pragma unroll
+                    for (int u = 0; u < kCopyUnroll; u++) {
+                        const uint32_t p = p0 + u * kBlock;
+                        if (p < c) slab[p - lo] = v[u];
+                    }
+                }
+                __syncthreads();
+            }
+            // surviving entries shift left past deletions, right past
+            // insertions; a thread's entries ascend, so its cursors into the
+            // sorted operations only move forward
+            uint32_t kd = 0, ki = 0;
+            for (uint32_t p0 = lo + threadIdx.x; p0 < c; p0 += kBlock * kCopyUnroll) {
+                int32_t v[kCopyUnroll];
+#pragma unroll
+                for (int u = 0; u < kCopyUnroll; u++) {
+                    const uint32_t p = p0 + u * kBlock;
+                    v[u] = p >= c ? 0 : !BIG ? s_row[p] : moved ? grow[p] : slab[p - lo];
+                }
+#pragma unroll
+                for (int u = 0; u < kCopyUnroll; u++) {
+                    const uint32_t p = p0 + u * kBlock;
+                    if (p >= c) break;
+                    const int32_t e = v[u];
+                    kd = gallop_dev(s_d, kd, nd, e);
+                    if (kd < nd && s_d[kd] == e) continue;
+                    ki = gallop_dev(s_i, ki, ni, e);
+                    idx[dest + p - s_pd[kd] + s_pi[ki]] = e;
+                }
             }
             for (uint32_t q = threadIdx.x; q < ni; q += kBlock) {
                 if (!s_fi[q]) continue;
                 const int32_t col = s_i[q];
-                const uint32_t below = lower_bound_dev(buf, c, col) - s_pd[lower_bound_dev(s_d, nd, col)];
+                const uint32_t below = s_ipos[q] - s_pd[lower_bound_dev(s_d, nd, col)];
                 idx[dest + s_pi[q] + below] = col;
             }
             __syncthreads();
@@ -498,8 +686,8 @@ __global__ __launch_bounds__(kBlock) void k_apply_rows(ApplyArgs a, uint32_t len
                 beg_a[row] = dest;
                 cap_a[row] = s_ncap;
                 if (o == 1) {
-                    atomicAdd(&ctl->applied[0], (unsigned long long)ndel);
-                    atomicAdd(&ctl->applied[1], (unsigned long long)nins);
+                    sum_del += ndel;
+                    sum_ins += nins;
                     // |out(row)| changed: refresh the stored contributions
                     a.C0[row] = a.R0[row] / (double)nc;
                     a.C1[row] = a.R1[row] / (double)nc;
@@ -508,6 +696,8 @@ __global__ __launch_bounds__(kBlock) void k_apply_rows(ApplyArgs a, uint32_t len
             __syncthreads();
         }
     }
+    if (o == 1 && threadIdx.x == 0)
+        put_applied(a, (BIG ? kTinyGrid + kSmallGrid : kTinyGrid) + blockIdx.x, sum_del, sum_ins);
 }
 
 // ---- re-layout of one orientation after slack overflow --------------------
@@ -638,6 +828,7 @@ static int ensure_apply_bufs(dfpr_graph *g, uint64_t B)
         ap.ovf_need[o] = nullptr;
         DFPR_HIP(hipMalloc(&ap.ovf_need[o], cap * 4));
     }
+    if (!ap.part) DFPR_HIP(hipMalloc(&ap.part, (size_t)kPartSlots * 8));
     ap.cap = cap;
     return DFPR_OK;
 }
@@ -841,10 +1032,15 @@ int apply_batch_impl(dfpr_graph *g, int64_t n_del, const int32_t *ds, const int3
     a.keys[0] = g->ap.keys[0][pp];
     a.keys[1] = g->ap.keys[1][pp];
     k_heads<<<dim3(grid_for(B), 2), kBlock, 0, s>>>(a, B);
-    k_apply_tiny<<<dim3(std::min<unsigned>(grid_for(B, kWavesPerBlock), 4096), 2), kBlock, 0, s>>>(
-        a, B);
-    k_apply_rows<false><<<dim3(std::min<unsigned>(B, 8192), 2), kBlock, 0, s>>>(a, B, -1);
+    // every workgroup writes its slots of part, so they need no clearing;
+    // the fold reads the slots of the workgroups launched
+    a.part = g->ap.part;
+    const unsigned tiny_grid = std::min<unsigned>(grid_for(B, kWavesPerBlock), kTinyGrid);
+    const unsigned small_grid = std::min<unsigned>(B, kSmallGrid);
+    k_apply_tiny<<<dim3(tiny_grid, 2), kBlock, 0, s>>>(a, B);
+    k_apply_rows<false><<<dim3(small_grid, 2), kBlock, 0, s>>>(a, B, -1);
     k_apply_rows<true><<<dim3(kBigGrid, 2), kBlock, 0, s>>>(a, B, -1);
+    k_apply_fold<<<1, kFoldThreads, 0, s>>>(a.part, tiny_grid, small_grid, a.ctl);
     DFPR_HIP(hipGetLastError());
     DFPR_HIP(hipMemcpyAsync(g->ctl_host, g->ctl, sizeof(Ctl), hipMemcpyDeviceToHost, s));
     DFPR_HIP(hipStreamSynchronize(s));

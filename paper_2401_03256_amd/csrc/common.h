@@ -104,6 +104,7 @@ struct ApplyBufs {
     uint32_t *big_list[2] = {};
     uint32_t *ovf_list[2] = {};
     int32_t *ovf_need[2] = {};      // capacity an overflowed row needs
+    unsigned long long *part = nullptr;  // per-workgroup applied counts (deletions, insertions)
     int32_t *slab = nullptr;        // row copies of big rows
     uint64_t slab_ints = 0;
     uint64_t slab_stride = 0;

@@ -311,6 +311,7 @@ void dfpr_free_graph(dfpr_graph *g)
         (void)hipFree(g->ap.ovf_list[o]);
         (void)hipFree(g->ap.ovf_need[o]);
     }
+    (void)hipFree(g->ap.part);
     (void)hipFree(g->ap.slab);
     (void)hipFree(g->ap.batch_dev);
     if (g->ev0) (void)hipEventDestroy(g->ev0);

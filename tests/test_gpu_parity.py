@@ -126,6 +126,35 @@ def test_apply_forces_overflow_and_big_rows(dfpr):
         _same_csr(g, o)
 
 
+def test_apply_row_growing_past_the_lds_copy(dfpr):
+    # out-row of vertex 1 and in-row of vertex 2 start below the 4096 entries
+    # a workgroup copies to LDS and take 3000 insertions in one batch: the
+    # merge runs in rounds of 1024 entries and the rows outgrow the LDS copy
+    # between rounds; deletions early in the rows, and rows with few changes,
+    # ride along
+    n = 9000
+    a = np.arange(3, 3103, dtype=np.int32)
+    src = np.concatenate([np.ones(3100, np.int32), a, np.arange(5000, 8999, dtype=np.int32)])
+    dst = np.concatenate([a, np.full(3100, 2, np.int32), np.arange(5001, 9000, dtype=np.int32)])
+    g, o = _pair(dfpr, n, src, dst)
+    rng = np.random.default_rng(11)
+    for step in range(2):
+        _say(f"lds growth batch {step}")
+        new = np.arange(3103 + 3000 * step, 3103 + 3000 * (step + 1), dtype=np.int32) % n
+        new = new[(new != 1) & (new != 2)]
+        dels = rng.choice(a[:50], 20, replace=False)
+        b = synth.Batch(
+            np.concatenate([np.ones(20, np.int32), dels]).astype(np.int32),
+            np.concatenate([dels, np.full(20, 2, np.int32)]).astype(np.int32),
+            np.concatenate([np.ones(new.size, np.int32), new, rng.integers(0, n, 40)]).astype(
+                np.int32),
+            np.concatenate([new, np.full(new.size, 2, np.int32), rng.integers(0, n, 40)]).astype(
+                np.int32))
+        assert g.apply_batch(b) == o.apply_batch(b)
+        assert g.m == o.m
+        _same_csr(g, o)
+
+
 def test_apply_rejects_out_of_range_unchanged(dfpr):
     n = 100
     src, dst = synth.gnm(n, 400, seed=1)
