@@ -51,7 +51,7 @@ struct IterArgs {
     const int32_t *sched;       // class schedule of all vertices
     const uint32_t *sched_off;  // kBins + 1 offsets
     Ctl *ctl;
-    Ctl *mirror;                // host-visible copy written after each step, or NULL
+    Ctl *mirror;                // host-visible copy of the control block, or NULL
     double *dr_part;
     double *rmax_part;          // per-workgroup largest new rank
     unsigned long long *cnt_part;   // kCounters per workgroup
@@ -333,9 +333,10 @@ __device__ inline void block_row(const IterArgs &a, int32_t v, bool check, bool 
     __syncthreads();
 }
 
-// Fold a max and kCounters sums over the workgroup; thread 0 gets the
-// result.  Waves fold with shuffles, then the four wave results are
-// combined in a fixed order.
+// Fold a max and kCounters sums over a workgroup of W waves; thread 0 gets
+// the result.  Waves fold with shuffles, then the wave results are combined
+// in a fixed order.
+template <int W = kWavesPerBlock>
 __device__ inline void block_fold(double &dr, double &rm, unsigned long long (&c)[kCounters],
                                   double *wdr, double *wrm, unsigned long long (*wc)[kCounters])
 {
@@ -355,7 +356,7 @@ __device__ inline void block_fold(double &dr, double &rm, unsigned long long (&c
     }
     __syncthreads();
     if (threadIdx.x == 0) {
-        for (int w = 1; w < kWavesPerBlock; w++) {
+        for (int w = 1; w < W; w++) {
             dr = fmax(dr, wdr[w]);
             rm = fmax(rm, wrm[w]);
 #pragma unroll
@@ -411,6 +412,20 @@ struct IterShared {
     int flag;
     double wdr[kWavesPerBlock], wrm[kWavesPerBlock];
     unsigned long long wc[kWavesPerBlock][kCounters];
+};
+
+// Threads of the per-iteration fold: with kFold partials in flight per
+// thread, one round covers the 8192 workgroups of a full-size iteration.
+constexpr int kFinalThreads = 1024;
+constexpr int kFinalWaves = kFinalThreads / kWave;
+
+// Shared memory of the per-iteration fold.
+struct FinalShared {
+    Plan plan;
+    uint32_t active;
+    int copy;
+    double wdr[kFinalWaves], wrm[kFinalWaves];
+    unsigned long long wc[kFinalWaves][kCounters];
 };
 
 // One workgroup's share of an iteration of one graph: workgroup blk of the
@@ -472,8 +487,11 @@ __device__ inline void iter_body(const IterArgs &a, uint32_t blk, uint32_t G, It
 // In the FP32 phase of the precision form, reaching tol or the FP32
 // resolution of the ranks ends the phase instead of the call.
 // `active` is the number of workgroups that wrote partials for this graph.
+// The control block goes to the host mirror when `last` (the last launch
+// the host queued before it next waits) or when this step ends the call or
+// the phase: later launches then return at once.
 __device__ inline void final_body(const IterArgs &a, uint32_t active, bool df, bool f32,
-                                  IterShared &sh)
+                                  FinalShared &sh, bool last)
 {
     Ctl *ctl = a.ctl;
     if (ctl->done || (f32 && ctl->phase_end)) return;
@@ -483,12 +501,12 @@ __device__ inline void final_body(const IterArgs &a, uint32_t active, bool df, b
     unsigned long long c[kCounters] = {0, 0, 0, 0};
     // kFold partials per thread and round, all loads issued before use
     constexpr int kFold = 8;
-    for (uint32_t i0 = threadIdx.x; i0 < active; i0 += kBlock * kFold) {
+    for (uint32_t i0 = threadIdx.x; i0 < active; i0 += kFinalThreads * kFold) {
         double pd[kFold], pr[kFold];
         unsigned long long pc[kFold][kCounters];
 #pragma unroll
         for (int u = 0; u < kFold; u++) {
-            const uint32_t i = i0 + u * kBlock;
+            const uint32_t i = i0 + u * kFinalThreads;
             const bool in = i < active;
             pd[u] = in ? a.dr_part[i] : 0.0;
             pr[u] = in ? a.rmax_part[i] : 0.0;
@@ -503,7 +521,7 @@ __device__ inline void final_body(const IterArgs &a, uint32_t active, bool df, b
             for (int j = 0; j < kCounters; j++) c[j] += pc[u][j];
         }
     }
-    block_fold(dr, rm, c, sh.wdr, sh.wrm, sh.wc);
+    block_fold<kFinalWaves>(dr, rm, c, sh.wdr, sh.wrm, sh.wc);
     if (threadIdx.x == 0) {
         ctl->verts += c[0];
         ctl->edges += c[1];
@@ -539,7 +557,16 @@ __device__ inline void final_body(const IterArgs &a, uint32_t active, bool df, b
             if (conv || a.it + 1 >= a.max_iters) ctl->done = 1;
         }
         ctl->prev_linf = dr;
-        if (a.mirror) __builtin_memcpy(a.mirror, ctl, sizeof(Ctl));
+        sh.copy = a.mirror && (last || ctl->done || (f32 && ctl->phase_end));
+    }
+    __syncthreads();
+    if (sh.copy && threadIdx.x < kWave) {
+        // one wave copies the words of the block (thread 0's updates are
+        // visible after the barrier)
+        constexpr int words = (int)(sizeof(Ctl) / 4);
+        const volatile uint32_t *src = reinterpret_cast<const volatile uint32_t *>(ctl);
+        uint32_t *dst = reinterpret_cast<uint32_t *>(a.mirror);
+        for (int i = threadIdx.x; i < words; i += kWave) dst[i] = src[i];
     }
 }
 

@@ -64,15 +64,15 @@ __global__ __launch_bounds__(kBlock, DFPR_ITER_WAVES_PER_SIMD) void k_iter(IterA
 // After each iteration (one workgroup): fold the partials of the
 // iteration's active workgroups, decide convergence or the cap, and prepare
 // the next iteration.  The launch boundary orders it after k_iter.
-__global__ __launch_bounds__(kBlock) void k_final(IterArgs a, uint32_t grid, int df, int f32)
+__global__ __launch_bounds__(kFinalThreads) void k_final(IterArgs a, uint32_t grid, int df, int f32,
+                                                        int last)
 {
-    __shared__ IterShared sh;
-    __shared__ uint32_t s_active;
+    __shared__ FinalShared sh;
     const Ctl *ctl = a.ctl;
     if (ctl->done || (f32 && ctl->phase_end)) return;
-    if (threadIdx.x == 0) s_active = single_graph_active(a, df != 0, grid, sh.plan);
+    if (threadIdx.x == 0) sh.active = single_graph_active(a, df != 0, grid, sh.plan);
     __syncthreads();
-    final_body(a, s_active, df != 0, f32 != 0, sh);
+    final_body(a, sh.active, df != 0, f32 != 0, sh, last != 0);
 }
 
 // ---------------------------------------------------------------------------
@@ -841,11 +841,12 @@ static int run_loop(dfpr_graph *g, const dfpr_params &p, bool df, bool f32, uint
             else if (f32) k_iter<true, true><<<gsz, kBlock, 0, g->stream>>>(a);
             else k_iter<true, false><<<gsz, kBlock, 0, g->stream>>>(a);
             if (g->prof.enabled) DFPR_HIP(hipEventRecord(g->evk[2 * j + 1], g->stream));
-            k_final<<<1, kBlock, 0, g->stream>>>(a, gsz, df ? 1 : 0, f32 ? 1 : 0);
+            k_final<<<1, kFinalThreads, 0, g->stream>>>(a, gsz, df ? 1 : 0, f32 ? 1 : 0,
+                                                         j == k - 1 ? 1 : 0);
         }
         DFPR_HIP(hipGetLastError());
-        // k_snap and every k_final that ran an iteration left the control
-        // block in the host mirror
+        // k_snap, the chunk's last k_final and a k_final that ended the
+        // call or the phase leave the control block in the host mirror
         DFPR_HIP(hipStreamSynchronize(g->stream));
         if (g->prof.enabled) {
             // the iteration kernel alone, launch by launch

@@ -67,17 +67,16 @@ __global__ __launch_bounds__(kBlock, DFPR_ITER_WAVES_PER_SIMD) void k_iter_multi
 }
 
 // One workgroup per slot.
-__global__ __launch_bounds__(kBlock) void k_final_multi(MultiArgs m)
+__global__ __launch_bounds__(kFinalThreads) void k_final_multi(MultiArgs m)
 {
-    __shared__ IterShared sh;
-    __shared__ uint32_t s_active;
+    __shared__ FinalShared sh;
     const int s = blockIdx.x;
     const IterArgs &a = m.s[s];
     const bool f32 = (m.f32_mask >> s) & 1u;
     if (a.ctl->done || (f32 && a.ctl->phase_end)) return;
-    if (threadIdx.x == 0) s_active = single_graph_active(a, true, m.off[s + 1] - m.off[s], sh.plan);
+    if (threadIdx.x == 0) sh.active = single_graph_active(a, true, m.off[s + 1] - m.off[s], sh.plan);
     __syncthreads();
-    final_body(a, s_active, true, f32, sh);
+    final_body(a, sh.active, true, f32, sh, false);
 }
 
 // Copy the control blocks of the slots into one array for one host copy.
@@ -258,7 +257,7 @@ static int launch_chunk(dfpr_server *srv, std::vector<Slot *> &cs, int K)
             m.s[i] = a;
         }
         k_iter_multi<<<at, kBlock, 0, srv->stream>>>(m);
-        k_final_multi<<<m.nslots, kBlock, 0, srv->stream>>>(m);
+        k_final_multi<<<m.nslots, kFinalThreads, 0, srv->stream>>>(m);
     }
     CtlGather cg{};
     cg.n = m.nslots;
