@@ -382,7 +382,7 @@ __global__ __launch_bounds__(kBlock) void k_apply_tiny(ApplyArgs a, uint32_t len
         if ((mins >> lane) & 1ull)
             idx[dest + pb - __popcll(mdel & lanes_mask(lo)) + __popcll(mins & below)] = col;
         if (lane == 0) {
-            if (o == 0 && bin_of(c) != bin_of(nc)) ctl->cls_moved = 1;
+            if (o == 0 && sched_bin_of(c) != sched_bin_of(nc)) ctl->cls_moved = 1;
             cnt_a[row] = nc;
             beg_a[row] = dest;
             cap_a[row] = ncap;
@@ -681,7 +681,7 @@ __global__ __launch_bounds__(kBlock) void k_apply_rows(ApplyArgs a, uint32_t len
             }
             __syncthreads();
             if (threadIdx.x == 0) {
-                if (o == 0 && bin_of(c) != bin_of(nc)) ctl->cls_moved = 1;
+                if (o == 0 && sched_bin_of(c) != sched_bin_of(nc)) ctl->cls_moved = 1;
                 cnt_a[row] = nc;
                 beg_a[row] = dest;
                 cap_a[row] = s_ncap;

@@ -33,6 +33,18 @@ __host__ __device__ constexpr int group_of(int bin)
            : bin == 5 ? 64 : kBlock;
 }
 
+// Schedule bins (dense mode): bin 0 holds the other rows of class 0, bin 1
+// the rows whose only in-entry is the self-loop, bin b + 1 class b >= 1.  A
+// self-loop-only row changes only if its own out-degree or rank does, so it
+// is walked without its row start and length.  Bins 0 and 1 together are
+// class 0 in id order, as a sweep of every row walks them.
+constexpr int kSchedBins = kBins + 1;
+__host__ __device__ inline int sched_bin_of(uint32_t deg)
+{
+    const int b = bin_of(deg);
+    return deg <= 1 ? 1 : b == 0 ? 0 : b + 1;
+}
+
 // Device control block of a graph (zeroed at creation).
 struct Ctl {
     uint32_t live[kBins];       // entries appended to each class list (sparse mode)
@@ -66,7 +78,7 @@ struct Ctl {
     uint32_t max_cap[2];        //   largest row capacity
     unsigned long long top[2];  //   first free slot of each index array
     unsigned long long applied[2];  // effective deletions, insertions
-    uint32_t cls_moved;         //   an in-row changed its in-degree class
+    uint32_t cls_moved;         //   an in-row changed its schedule bin
 };
 
 // One orientation of the graph: row r holds cnt[r] sorted ids in
@@ -139,8 +151,8 @@ struct dfpr_graph {
     int32_t last_iters = -1;          //   Dynamic Frontier call
     int32_t *bins = nullptr;          // kBins appended lists of n entries (sparse mode)
     int32_t *bfs_q = nullptr;         // traversal: 3 light + 3 heavy level queues, n each
-    int32_t *sched = nullptr;         // all vertices by class, sorted (dense mode)
-    uint32_t *sched_off = nullptr;    // kBins + 1 offsets into sched (device)
+    int32_t *sched = nullptr;         // all vertices by schedule bin, sorted (dense mode)
+    uint32_t *sched_off = nullptr;    // kSchedBins + 1 offsets into sched (device)
     uint32_t *sched_tmp = nullptr;    // per-workgroup class counts for the build
     int sched_dirty = 1;              // in-degrees changed since the build
     dfpr::Ctl *ctl = nullptr;         // device

@@ -357,8 +357,8 @@ int dfpr_load_graph(int32_t n, int64_t m, const int32_t *src, const int32_t *dst
         if (!rc) rc = al((void **)&g->xstamp, (size_t)n * 4);
         if (!rc) rc = al((void **)&g->bins, (size_t)kBins * n * 4);
         if (!rc) rc = al((void **)&g->sched, (size_t)n * 4);
-        if (!rc) rc = al((void **)&g->sched_off, (kBins + 1) * 4);
-        if (!rc) rc = al((void **)&g->sched_tmp, ((size_t)n / 4096 + 1) * kBins * 4);
+        if (!rc) rc = al((void **)&g->sched_off, (kSchedBins + 1) * 4);
+        if (!rc) rc = al((void **)&g->sched_tmp, ((size_t)n / 4096 + 1) * kSchedBins * 4);
         if (!rc) rc = al((void **)&g->ctl, sizeof(Ctl));
         if (!rc) rc = al((void **)&g->it.dr_part, kMaxGrid * 8);
         if (!rc) rc = al((void **)&g->it.rmax_part, kMaxGrid * 8);

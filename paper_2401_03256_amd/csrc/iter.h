@@ -49,7 +49,7 @@ struct IterArgs {
     uint32_t *stamp, *xstamp;
     int32_t *bins;              // class lists (sparse mode), n entries each
     const int32_t *sched;       // class schedule of all vertices
-    const uint32_t *sched_off;  // kBins + 1 offsets
+    const uint32_t *sched_off;  // kSchedBins + 1 offsets
     Ctl *ctl;
     Ctl *mirror;                // host-visible copy of the control block, or NULL
     double *dr_part;
@@ -232,8 +232,10 @@ __device__ inline bool finish_row(const IterArgs &a, int32_t v, uint32_t cnt, do
     return false;
 }
 
-// One wave unit: 64/G rows of a class list, G lanes per row.
-template <int G, bool DF, bool F32>
+// One wave unit: 64/G rows of a class list, G lanes per row.  LOOP (G = 1):
+// rows whose only in-entry is the self-loop, so the sum is the row's own
+// contribution and its start and length are not read.
+template <int G, bool DF, bool F32, bool LOOP = false>
 __device__ inline void wave_unit(const IterArgs &a, const int32_t *list, uint32_t count,
                                  uint32_t first, bool check, bool sparse, Acc &acc)
 {
@@ -247,19 +249,33 @@ __device__ inline void wave_unit(const IterArgs &a, const int32_t *list, uint32_
     if (pos < count) {
         v = list[pos];
         active = true;
-        // the row's start, length, rank and out-degree are loaded with its
-        // stamp, not after it: on the full schedule (dense mode) only
-        // marked rows are processed, but waiting for the stamp first would
-        // add a dependent load to every row (1.6% per call on R-MAT scale 22)
-        beg = a.in_beg[v];
-        cnt = a.in_cnt[v];
-        if (sub == 0) {
-            rc = a.Rc[v];
-            oc = a.out_cnt[v];
-        }
-        if (DF && check) {
-            const uint32_t st = a.stamp[v];
-            active = st >= a.sbase && st <= a.sbase + (uint32_t)a.it;
+        if (LOOP) {
+            // few of these rows are marked: the stamp decides first
+            cnt = 1;
+            if (DF && check) {
+                const uint32_t st = a.stamp[v];
+                active = st >= a.sbase && st <= a.sbase + (uint32_t)a.it;
+            }
+            if (active) {
+                rc = a.Rc[v];
+                oc = a.out_cnt[v];
+            }
+        } else {
+            // the row's start, length, rank and out-degree are loaded with
+            // its stamp, not after it: on the full schedule (dense mode)
+            // only marked rows are processed, but waiting for the stamp
+            // first would add a dependent load to every row (1.6% per call
+            // on R-MAT scale 22)
+            beg = a.in_beg[v];
+            cnt = a.in_cnt[v];
+            if (sub == 0) {
+                rc = a.Rc[v];
+                oc = a.out_cnt[v];
+            }
+            if (DF && check) {
+                const uint32_t st = a.stamp[v];
+                active = st >= a.sbase && st <= a.sbase + (uint32_t)a.it;
+            }
         }
     }
     double s = 0.0;
@@ -368,24 +384,39 @@ __device__ inline void block_fold(double &dr, double &rm, unsigned long long (&c
 }
 
 // Work of one iteration: per class, the list and its length; wave units
-// of classes 5..0 in that order; block units are the class-6 rows.
+// of classes 5..0 and then of the self-loop-only rows (their own schedule
+// bin; class lists hold them in class 0), in that order; block units are
+// the class-6 rows.
 struct Plan {
     uint32_t cnt[kBins];
     const int32_t *list[kBins];
-    uint32_t ustart[kBins];
+    uint32_t loop_cnt;
+    const int32_t *loop_list;
+    uint32_t ustart[kBins];     // k < kBins - 1: class kBins - 2 - k; kBins - 1: loop rows
     uint32_t nwu, nbu;
 };
 
-__device__ inline void make_plan(const IterArgs &a, const Ctl *ctl, bool sparse, int par, Plan &p)
+__device__ inline void make_plan(const IterArgs &a, const Ctl *ctl, bool sparse, bool df, int par,
+                                 Plan &p)
 {
     for (int b = 0; b < kBins; b++) {
         if (sparse) {
             p.cnt[b] = ctl->snap[par][b];
             p.list[b] = a.bins + (size_t)b * a.n_stride;
         } else {
-            p.cnt[b] = a.sched_off[b + 1] - a.sched_off[b];
-            p.list[b] = a.sched + a.sched_off[b];
+            // schedule bin 0: class 0 without the self-loop-only rows;
+            // bin b + 1: class b >= 1
+            const int sb = b == 0 ? 0 : b + 1;
+            p.cnt[b] = a.sched_off[sb + 1] - a.sched_off[sb];
+            p.list[b] = a.sched + a.sched_off[sb];
         }
+    }
+    p.loop_cnt = sparse ? 0u : a.sched_off[2] - a.sched_off[1];
+    p.loop_list = a.sched + a.sched_off[1];
+    if (!df) {
+        // every row is processed: bins 0 and 1 are one run, walked as class 0
+        p.cnt[0] += p.loop_cnt;
+        p.loop_cnt = 0;
     }
     uint32_t acc = 0;
     for (int k = 0; k < kBins - 1; k++) {
@@ -394,6 +425,8 @@ __device__ inline void make_plan(const IterArgs &a, const Ctl *ctl, bool sparse,
         p.ustart[k] = acc;
         acc += (p.cnt[b] + rows - 1) / rows;
     }
+    p.ustart[kBins - 1] = acc;
+    acc += (p.loop_cnt + kWave - 1) / kWave;
     p.nwu = acc;
     p.nbu = p.cnt[kBins - 1];
 }
@@ -439,7 +472,7 @@ __device__ inline void iter_body(const IterArgs &a, uint32_t blk, uint32_t G, It
     const int par = a.it & 1;
     const bool sparse = DF && !ctl->dense;
     const bool check = DF && !sparse;
-    if (threadIdx.x == 0) make_plan(a, ctl, sparse, par, sh.plan);
+    if (threadIdx.x == 0) make_plan(a, ctl, sparse, DF, par, sh.plan);
     __syncthreads();
     if (blk >= active_blocks(sh.plan, G)) return;
     const uint32_t nbu = sh.plan.nbu, nwu = sh.plan.nwu;
@@ -447,6 +480,12 @@ __device__ inline void iter_body(const IterArgs &a, uint32_t blk, uint32_t G, It
     Acc acc;
     const int wave = threadIdx.x / kWave;
     auto run_unit = [&](uint32_t u, int k) {
+        if (k == kBins - 1) {
+            const uint32_t first = (u - sh.plan.ustart[k]) * kWave;
+            wave_unit<1, DF, F32, true>(a, sh.plan.loop_list, sh.plan.loop_cnt, first, check,
+                                        sparse, acc);
+            return;
+        }
         const int b = kBins - 2 - k;
         const uint32_t first = (u - sh.plan.ustart[k]) * (kWave / group_of(b));
         const int32_t *list = sh.plan.list[b];
@@ -465,7 +504,7 @@ __device__ inline void iter_body(const IterArgs &a, uint32_t blk, uint32_t G, It
                            &sh.flag);
     for (uint32_t u = blk * kWavesPerBlock + wave; u < nwu; u += G * kWavesPerBlock) {
         int k = 0;
-        while (k + 1 < kBins - 1 && u >= sh.plan.ustart[k + 1]) k++;
+        while (k + 1 < kBins && u >= sh.plan.ustart[k + 1]) k++;
         run_unit(u, k);
     }
 
@@ -577,7 +616,7 @@ __device__ inline uint32_t single_graph_active(const IterArgs &a, bool df, uint3
                                                Plan &plan)
 {
     const bool sparse = df && !a.ctl->dense;
-    make_plan(a, a.ctl, sparse, a.it & 1, plan);
+    make_plan(a, a.ctl, sparse, df, a.it & 1, plan);
     return active_blocks(plan, grid);
 }
 

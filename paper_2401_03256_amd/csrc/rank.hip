@@ -151,8 +151,9 @@ __global__ void k_copy2(int32_t n, const double *a, double *a2, const double *b,
     }
 }
 
-// Schedule build: a stable counting sort of the vertices by in-degree
-// class.  Workgroup w owns vertices [w * kSchedChunk, (w + 1) * kSchedChunk)
+// Schedule build: a stable counting sort of the vertices by schedule bin
+// (sched_bin_of: self-loop-only rows, then the in-degree classes).
+// Workgroup w owns vertices [w * kSchedChunk, (w + 1) * kSchedChunk)
 // and visits them in rounds of kBlock consecutive ids, so loads and the
 // per-class runs of stores are coalesced.
 constexpr int kScanThreads = 1024;
@@ -160,37 +161,37 @@ constexpr int kScanThreads = 1024;
 __global__ __launch_bounds__(kBlock) void k_sched_count(int32_t n, const uint32_t *in_cnt,
                                                         uint32_t *tmp, uint32_t nblocks)
 {
-    __shared__ uint32_t s[kWavesPerBlock][kBins];
+    __shared__ uint32_t s[kWavesPerBlock][kSchedBins];
     const int lane = lane_id(), wave = threadIdx.x / kWave;
-    uint32_t cnt[kBins];
+    uint32_t cnt[kSchedBins];
 #pragma unroll
-    for (int b = 0; b < kBins; b++) cnt[b] = 0;
+    for (int b = 0; b < kSchedBins; b++) cnt[b] = 0;
     const uint32_t base = blockIdx.x * (uint32_t)kSchedChunk;
     for (uint32_t r = 0; r < (uint32_t)kSchedChunk; r += kBlock) {
         const uint32_t v = base + r + threadIdx.x;
-        const int c = v < (uint32_t)n ? bin_of(in_cnt[v]) : kBins;
+        const int c = v < (uint32_t)n ? sched_bin_of(in_cnt[v]) : kSchedBins;
 #pragma unroll
-        for (int b = 0; b < kBins; b++) cnt[b] += (uint32_t)__popcll(__ballot(c == b));
+        for (int b = 0; b < kSchedBins; b++) cnt[b] += (uint32_t)__popcll(__ballot(c == b));
     }
     if (lane == 0)
 #pragma unroll
-        for (int b = 0; b < kBins; b++) s[wave][b] = cnt[b];
+        for (int b = 0; b < kSchedBins; b++) s[wave][b] = cnt[b];
     __syncthreads();
-    if (threadIdx.x < kBins) {
+    if (threadIdx.x < kSchedBins) {
         uint32_t t = 0;
         for (int w = 0; w < kWavesPerBlock; w++) t += s[w][threadIdx.x];
         tmp[threadIdx.x * nblocks + blockIdx.x] = t;
     }
 }
 
-// Exclusive scan of the class-major count table; off[b] = start of class b.
+// Exclusive scan of the bin-major count table; off[b] = start of bin b.
 // Each thread sums a contiguous run of the table, the run totals are
 // scanned across the workgroup, and each thread then rewrites its run.
 __global__ __launch_bounds__(kScanThreads) void k_sched_scan(uint32_t *tmp, uint32_t nblocks,
                                                              uint32_t *off)
 {
     __shared__ uint32_t s[kScanThreads];
-    const uint32_t len = nblocks * kBins;
+    const uint32_t len = nblocks * kSchedBins;
     const uint32_t run = (len + kScanThreads - 1) / kScanThreads;
     const uint32_t lo = min(len, threadIdx.x * run), hi = min(len, lo + run);
     // eight loads in flight per thread
@@ -225,38 +226,38 @@ __global__ __launch_bounds__(kScanThreads) void k_sched_scan(uint32_t *tmp, uint
             acc += x[u];
         }
     }
-    if (threadIdx.x == kScanThreads - 1) off[kBins] = s[kScanThreads - 1];
+    if (threadIdx.x == kScanThreads - 1) off[kSchedBins] = s[kScanThreads - 1];
 }
 
 __global__ __launch_bounds__(kBlock) void k_sched_scatter(int32_t n, const uint32_t *in_cnt,
                                                           const uint32_t *tmp, uint32_t nblocks,
                                                           int32_t *sched)
 {
-    __shared__ uint32_t s_w[kWavesPerBlock][kBins];   // per-wave class counts of a round
-    __shared__ uint32_t s_run[kBins];                 // next position of each class
+    __shared__ uint32_t s_w[kWavesPerBlock][kSchedBins];   // per-wave class counts of a round
+    __shared__ uint32_t s_run[kSchedBins];                 // next position of each class
     const int lane = lane_id(), wave = threadIdx.x / kWave;
     const unsigned long long below = (1ull << lane) - 1ull;
-    if (threadIdx.x < kBins) s_run[threadIdx.x] = tmp[threadIdx.x * nblocks + blockIdx.x];
+    if (threadIdx.x < kSchedBins) s_run[threadIdx.x] = tmp[threadIdx.x * nblocks + blockIdx.x];
     __syncthreads();
     const uint32_t base = blockIdx.x * (uint32_t)kSchedChunk;
     for (uint32_t r = 0; r < (uint32_t)kSchedChunk; r += kBlock) {
         const uint32_t v = base + r + threadIdx.x;
-        const int c = v < (uint32_t)n ? bin_of(in_cnt[v]) : kBins;
+        const int c = v < (uint32_t)n ? sched_bin_of(in_cnt[v]) : kSchedBins;
         uint32_t rank = 0;
 #pragma unroll
-        for (int b = 0; b < kBins; b++) {
+        for (int b = 0; b < kSchedBins; b++) {
             const unsigned long long m = __ballot(c == b);
             if (c == b) rank = (uint32_t)__popcll(m & below);
             if (lane == 0) s_w[wave][b] = (uint32_t)__popcll(m);
         }
         __syncthreads();
-        if (c < kBins) {
+        if (c < kSchedBins) {
             uint32_t pos = s_run[c] + rank;
             for (int w = 0; w < wave; w++) pos += s_w[w][c];
             sched[pos] = (int32_t)v;
         }
         __syncthreads();
-        if (threadIdx.x < kBins) {
+        if (threadIdx.x < kSchedBins) {
             uint32_t t = 0;
             for (int w = 0; w < kWavesPerBlock; w++) t += s_w[w][threadIdx.x];
             s_run[threadIdx.x] += t;

@@ -95,12 +95,15 @@ __global__ __launch_bounds__(kBlock) void k_gather_ctl(CtlGather g)
 // bounds every frontier.
 static uint32_t blocks_bound(const uint32_t *off, uint32_t grid)
 {
-    uint64_t nwu = 0;
+    // schedule bin 1: self-loop-only rows, one per lane; bin 0: the rest of
+    // class 0; bin b + 1: class b >= 1
+    uint64_t nwu = ((uint64_t)(off[2] - off[1]) + kWave - 1) / kWave;
     for (int b = 0; b < kBins - 1; b++) {
+        const int sb = b == 0 ? 0 : b + 1;
         const uint64_t rows = kWave / group_of(b);
-        nwu += ((uint64_t)(off[b + 1] - off[b]) + rows - 1) / rows;
+        nwu += ((uint64_t)(off[sb + 1] - off[sb]) + rows - 1) / rows;
     }
-    const uint64_t nbu = off[kBins] - off[kBins - 1];
+    const uint64_t nbu = off[kSchedBins] - off[kSchedBins - 1];
     const uint64_t wblocks = (nwu + kWavesPerBlock - 1) / kWavesPerBlock;
     return (uint32_t)std::max<uint64_t>(1, std::max(std::min<uint64_t>(grid, nbu),
                                                     std::min<uint64_t>(grid, wblocks)));
@@ -207,7 +210,7 @@ static int admit(dfpr_server *srv, int64_t r, Slot &sl, double now_ms)
         uint32_t sbase = 0;
         rc = df_begin(g, ge.p, nd, bds, bdd, ni, bis, bid, nullptr, 0, &sbase);
         if (rc) break;
-        if (hipMemcpyAsync(srv->sched_pin, g->sched_off, (kBins + 1) * sizeof(uint32_t),
+        if (hipMemcpyAsync(srv->sched_pin, g->sched_off, (kSchedBins + 1) * sizeof(uint32_t),
                            hipMemcpyDeviceToHost, srv->astream) != hipSuccess ||
             hipStreamSynchronize(srv->astream) != hipSuccess) {
             rc = set_error(DFPR_E_DEVICE, "admission failed on the device");
@@ -525,7 +528,7 @@ int dfpr_server_create(int32_t max_slots, int64_t hbm_budget_bytes, dfpr_server 
     if (e == hipSuccess) e = hipStreamCreateWithFlags(&s->astream, hipStreamNonBlocking);
     if (e == hipSuccess) e = hipMalloc(&s->ctl_dev, kMaxSlots * sizeof(Ctl));
     if (e == hipSuccess) e = hipHostMalloc(&s->ctl_pin, kMaxSlots * sizeof(Ctl));
-    if (e == hipSuccess) e = hipHostMalloc(&s->sched_pin, (kBins + 1) * sizeof(uint32_t));
+    if (e == hipSuccess) e = hipHostMalloc(&s->sched_pin, (kSchedBins + 1) * sizeof(uint32_t));
     if (e != hipSuccess) {
         dfpr_server_free(s);
         return hip_fail(e, "server set-up");
