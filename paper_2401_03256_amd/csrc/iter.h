@@ -7,13 +7,15 @@
 
 namespace dfpr {
 
+// Index loads in flight per lane and round of a gather (each lane still
+// adds its entries in index order, so the value does not change the sums).
+// Measured on R-MAT scale 22: 8 beats 4, 6, 10, 12 and 16.
 #ifndef DFPR_UNROLL
-#define DFPR_UNROLL 4
+#define DFPR_UNROLL 8
 #endif
 // Minimum waves per SIMD the iteration kernels are compiled for (the second
-// launch bound).  Five fit with a few spills of the expansion path; the
-// compiler alone picks four.  Measured on R-MAT scale 22 and the 4096^2
-// grid, five is faster on both.
+// launch bound).  The kernels now fit 6-7 waves without spills; asking for
+// eight is slower on R-MAT scale 22.
 #ifndef DFPR_ITER_WAVES_PER_SIMD
 #define DFPR_ITER_WAVES_PER_SIMD 5
 #endif
