@@ -17,7 +17,11 @@ constexpr int kWavesPerBlock = kBlock / kWave;
 constexpr int kBins = 7;               // in-degree classes of the pull
 constexpr int kMaxGrid = 8192;         // upper bound on iteration-kernel grids
 constexpr uint64_t kSentinel = ~0ull;  // batch key of an entry that changes nothing
-constexpr int kCounters = 4;           // rows, in-edges, expanded rows, their out-edges
+constexpr int kCounters = 4;
+// Slots the workgroups of an iteration fold their partial results into:
+// ~32 workgroups share a slot at the full grid, so the per-iteration fold
+// reads 256 slots instead of one partial per workgroup.
+constexpr int kFoldSlots = 256;           // rows, in-edges, expanded rows, their out-edges
 constexpr int kLoopChunk = 64;         // most iteration launches between two host looks
 
 // In-degree classes.  A row of class b < 6 is reduced by a group of
@@ -94,9 +98,12 @@ struct Csr {
 };
 
 struct IterBufs {
-    double *dr_part = nullptr;                // per-workgroup L-inf partials
-    double *rmax_part = nullptr;              // per-workgroup largest rank
-    unsigned long long *cnt_part = nullptr;   // per-workgroup counters (kCounters each)
+    // kFoldSlots slots each; workgroup w of an iteration folds its results
+    // into slot w mod kFoldSlots with atomics, the per-iteration fold reads
+    // and clears every slot
+    double *dr_part = nullptr;                // L-inf of Delta r (atomic max on the bits)
+    double *rmax_part = nullptr;              // largest rank (atomic max on the bits)
+    unsigned long long *cnt_part = nullptr;   // counters (kCounters per slot)
 };
 
 // Host-side profile of the iteration kernel (see dfpr_profile in dfpr.h).

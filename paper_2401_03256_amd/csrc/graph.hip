@@ -360,11 +360,16 @@ int dfpr_load_graph(int32_t n, int64_t m, const int32_t *src, const int32_t *dst
         if (!rc) rc = al((void **)&g->sched_off, (kSchedBins + 1) * 4);
         if (!rc) rc = al((void **)&g->sched_tmp, ((size_t)n / 4096 + 1) * kSchedBins * 4);
         if (!rc) rc = al((void **)&g->ctl, sizeof(Ctl));
-        if (!rc) rc = al((void **)&g->it.dr_part, kMaxGrid * 8);
-        if (!rc) rc = al((void **)&g->it.rmax_part, kMaxGrid * 8);
+        if (!rc) rc = al((void **)&g->it.dr_part, kFoldSlots * 8);
+        if (!rc) rc = al((void **)&g->it.rmax_part, kFoldSlots * 8);
         if (!rc) rc = al((void **)&g->C32[0], (size_t)n * 4);
         if (!rc) rc = al((void **)&g->C32[1], (size_t)n * 4);
-        if (!rc) rc = al((void **)&g->it.cnt_part, (size_t)kMaxGrid * kCounters * 8);
+        if (!rc) rc = al((void **)&g->it.cnt_part, (size_t)kFoldSlots * kCounters * 8);
+        // the fold slots start cleared; every fold clears them again
+        if (!rc && (hipMemset(g->it.dr_part, 0, kFoldSlots * 8) != hipSuccess ||
+                    hipMemset(g->it.rmax_part, 0, kFoldSlots * 8) != hipSuccess ||
+                    hipMemset(g->it.cnt_part, 0, (size_t)kFoldSlots * kCounters * 8) != hipSuccess))
+            rc = set_error(DFPR_E_DEVICE, "hipMemset of the fold slots failed");
         if (!rc) rc = al((void **)&g->scratch_sum, 4096 * 8);
         if (!rc) rc = al((void **)&g->Rx, nd);
         if (!rc) rc = al((void **)&g->ext2int, (size_t)n * 4);

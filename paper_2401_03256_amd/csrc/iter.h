@@ -450,15 +450,18 @@ struct IterShared {
     unsigned long long wc[kWavesPerBlock][kCounters];
 };
 
-// Threads of the per-iteration fold: with kFold partials in flight per
-// thread, one round covers the 8192 workgroups of a full-size iteration.
-constexpr int kFinalThreads = 1024;
+// Threads of the per-iteration fold.  Its time is mostly the dependent
+// loads of the control block, not the fold: 1024 threads (one round of
+// loads for a full grid) were no faster on R-MAT scale 22 and cost ~3 us
+// per iteration more on small frontiers.
+#ifndef DFPR_FINAL_THREADS
+#define DFPR_FINAL_THREADS 256
+#endif
+constexpr int kFinalThreads = DFPR_FINAL_THREADS;
 constexpr int kFinalWaves = kFinalThreads / kWave;
 
 // Shared memory of the per-iteration fold.
 struct FinalShared {
-    Plan plan;
-    uint32_t active;
     int copy;
     double wdr[kFinalWaves], wrm[kFinalWaves];
     unsigned long long wc[kFinalWaves][kCounters];
@@ -516,24 +519,28 @@ __device__ inline void iter_body(const IterArgs &a, uint32_t blk, uint32_t G, It
     for (int j = 0; j < kCounters; j++) c[j] = acc.c[j];
     block_fold(dr, rm, c, sh.wdr, sh.wrm, sh.wc);
     if (threadIdx.x == 0) {
-        a.dr_part[blk] = dr;
-        a.rmax_part[blk] = rm;
+        // non-negative doubles order like their bit patterns
+        const uint32_t slot = blk % kFoldSlots;
+        atomicMax(reinterpret_cast<unsigned long long *>(a.dr_part) + slot,
+                  (unsigned long long)__double_as_longlong(dr));
+        atomicMax(reinterpret_cast<unsigned long long *>(a.rmax_part) + slot,
+                  (unsigned long long)__double_as_longlong(rm));
 #pragma unroll
-        for (int j = 0; j < kCounters; j++) a.cnt_part[blk * kCounters + j] = c[j];
+        for (int j = 0; j < kCounters; j++)
+            if (c[j]) atomicAdd(&a.cnt_part[slot * kCounters + j], c[j]);
     }
 }
 
-// After each iteration (one workgroup): fold the partials of the
-// iteration's active workgroups, decide convergence or the cap, and prepare
-// the next iteration.  The launch boundary orders it after k_iter.
+// After each iteration (one workgroup): fold the slots the iteration's
+// workgroups left, decide convergence or the cap, and prepare the next
+// iteration.  The launch boundary orders it after k_iter.
 // In the FP32 phase of the precision form, reaching tol or the FP32
 // resolution of the ranks ends the phase instead of the call.
 // `active` is the number of workgroups that wrote partials for this graph.
 // The control block goes to the host mirror when `last` (the last launch
 // the host queued before it next waits) or when this step ends the call or
 // the phase: later launches then return at once.
-__device__ inline void final_body(const IterArgs &a, uint32_t active, bool df, bool f32,
-                                  FinalShared &sh, bool last)
+__device__ inline void final_body(const IterArgs &a, bool df, bool f32, FinalShared &sh, bool last)
 {
     Ctl *ctl = a.ctl;
     if (ctl->done || (f32 && ctl->phase_end)) return;
@@ -541,27 +548,16 @@ __device__ inline void final_body(const IterArgs &a, uint32_t active, bool df, b
     const bool sparse = df && !ctl->dense;
     double dr = 0.0, rm = 0.0;
     unsigned long long c[kCounters] = {0, 0, 0, 0};
-    // kFold partials per thread and round, all loads issued before use
-    constexpr int kFold = 8;
-    for (uint32_t i0 = threadIdx.x; i0 < active; i0 += kFinalThreads * kFold) {
-        double pd[kFold], pr[kFold];
-        unsigned long long pc[kFold][kCounters];
+    // each thread reads its slots and clears them for the next iteration
+    for (uint32_t i = threadIdx.x; i < (uint32_t)kFoldSlots; i += kFinalThreads) {
+        dr = fmax(dr, a.dr_part[i]);
+        rm = fmax(rm, a.rmax_part[i]);
 #pragma unroll
-        for (int u = 0; u < kFold; u++) {
-            const uint32_t i = i0 + u * kFinalThreads;
-            const bool in = i < active;
-            pd[u] = in ? a.dr_part[i] : 0.0;
-            pr[u] = in ? a.rmax_part[i] : 0.0;
+        for (int j = 0; j < kCounters; j++) c[j] += a.cnt_part[i * kCounters + j];
+        a.dr_part[i] = 0.0;
+        a.rmax_part[i] = 0.0;
 #pragma unroll
-            for (int j = 0; j < kCounters; j++) pc[u][j] = in ? a.cnt_part[i * kCounters + j] : 0ull;
-        }
-#pragma unroll
-        for (int u = 0; u < kFold; u++) {
-            dr = fmax(dr, pd[u]);
-            rm = fmax(rm, pr[u]);
-#pragma unroll
-            for (int j = 0; j < kCounters; j++) c[j] += pc[u][j];
-        }
+        for (int j = 0; j < kCounters; j++) a.cnt_part[i * kCounters + j] = 0ull;
     }
     block_fold<kFinalWaves>(dr, rm, c, sh.wdr, sh.wrm, sh.wc);
     if (threadIdx.x == 0) {
@@ -613,14 +609,6 @@ __device__ inline void final_body(const IterArgs &a, uint32_t active, bool df, b
 }
 
 
-// Workgroups that hold partials of the iteration just run (single graph).
-__device__ inline uint32_t single_graph_active(const IterArgs &a, bool df, uint32_t grid,
-                                               Plan &plan)
-{
-    const bool sparse = df && !a.ctl->dense;
-    make_plan(a, a.ctl, sparse, df, a.it & 1, plan);
-    return active_blocks(plan, grid);
-}
 
 }  // namespace dfpr
 

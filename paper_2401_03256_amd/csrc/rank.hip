@@ -61,18 +61,13 @@ __global__ __launch_bounds__(kBlock, DFPR_ITER_WAVES_PER_SIMD) void k_iter(IterA
     iter_body<DF, F32>(a, blockIdx.x, gridDim.x, sh);
 }
 
-// After each iteration (one workgroup): fold the partials of the
-// iteration's active workgroups, decide convergence or the cap, and prepare
-// the next iteration.  The launch boundary orders it after k_iter.
-__global__ __launch_bounds__(kFinalThreads) void k_final(IterArgs a, uint32_t grid, int df, int f32,
-                                                        int last)
+// After each iteration (one workgroup): fold the slots the iteration's
+// workgroups left, decide convergence or the cap, and prepare the next
+// iteration.  The launch boundary orders it after k_iter.
+__global__ __launch_bounds__(kFinalThreads) void k_final(IterArgs a, int df, int f32, int last)
 {
     __shared__ FinalShared sh;
-    const Ctl *ctl = a.ctl;
-    if (ctl->done || (f32 && ctl->phase_end)) return;
-    if (threadIdx.x == 0) sh.active = single_graph_active(a, df != 0, grid, sh.plan);
-    __syncthreads();
-    final_body(a, sh.active, df != 0, f32 != 0, sh, last != 0);
+    final_body(a, df != 0, f32 != 0, sh, last != 0);
 }
 
 // ---------------------------------------------------------------------------
@@ -842,7 +837,7 @@ static int run_loop(dfpr_graph *g, const dfpr_params &p, bool df, bool f32, uint
             else if (f32) k_iter<true, true><<<gsz, kBlock, 0, g->stream>>>(a);
             else k_iter<true, false><<<gsz, kBlock, 0, g->stream>>>(a);
             if (g->prof.enabled) DFPR_HIP(hipEventRecord(g->evk[2 * j + 1], g->stream));
-            k_final<<<1, kFinalThreads, 0, g->stream>>>(a, gsz, df ? 1 : 0, f32 ? 1 : 0,
+            k_final<<<1, kFinalThreads, 0, g->stream>>>(a, df ? 1 : 0, f32 ? 1 : 0,
                                                          j == k - 1 ? 1 : 0);
         }
         DFPR_HIP(hipGetLastError());

@@ -73,10 +73,7 @@ __global__ __launch_bounds__(kFinalThreads) void k_final_multi(MultiArgs m)
     const int s = blockIdx.x;
     const IterArgs &a = m.s[s];
     const bool f32 = (m.f32_mask >> s) & 1u;
-    if (a.ctl->done || (f32 && a.ctl->phase_end)) return;
-    if (threadIdx.x == 0) sh.active = single_graph_active(a, true, m.off[s + 1] - m.off[s], sh.plan);
-    __syncthreads();
-    final_body(a, sh.active, true, f32, sh, false);
+    final_body(a, true, f32, sh, false);
 }
 
 // Copy the control blocks of the slots into one array for one host copy.
