@@ -240,13 +240,15 @@ int dfpr_export_csr(const dfpr_graph *g, int out_orientation, int64_t *offsets,
 
 /* Profile of the iteration kernel (the pull, Delta r, L-inf and expansion
  * of one iteration), summed over every call made while profiling is on.
- * ms is measured with HIP events recorded on the graph's stream around each
- * chunk of back-to-back iteration launches, so it includes the short gaps
- * between those launches.  bytes is the algorithmic traffic of those
+ * ms is measured with HIP events recorded on the graph's stream right
+ * before and after each iteration-kernel launch (timing-only events, with
+ * no system-scope fence).  bytes is the algorithmic traffic of those
  * launches: per processed row 40 bytes (list entry, row start and length,
- * R[v], |out(v)|, the two written values) plus 12 per in-edge (index and
- * gathered FP64 contribution); per expanding row 8 bytes plus 5 per
- * out-edge (index and mark); per newly marked vertex 8 bytes. */
+ * R[v], |out(v)|, the two written values; 36 with an FP32 contribution)
+ * plus 8 in Dynamic Frontier (its mark and expansion stamp); per in-edge
+ * 12 bytes (index and gathered FP64 contribution; 8 in FP32); per
+ * expanding row 8 bytes (out-row start and length) plus 8 per out-edge it
+ * scans (index and the target's mark). */
 typedef struct {
     int64_t launches;        /* iteration-kernel launches                  */
     double ms;               /* their device time                          */
@@ -255,7 +257,9 @@ typedef struct {
     int64_t edges;           /* in-edges gathered                          */
     int64_t expanded_rows;   /* rows whose change exceeded frontier_tol     */
     int64_t expanded_edges;  /* out-edges those rows scanned               */
-    int64_t marked;          /* vertices newly marked by expansion          */
+    int64_t marked;          /* vertices newly marked by expansion in sparse
+                                iterations (dense ones mark with plain stores
+                                and do not count)                           */
 } dfpr_profile;
 
 /* Zero the profile and switch profiling on (enable != 0) or off. */

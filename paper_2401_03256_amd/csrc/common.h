@@ -174,7 +174,7 @@ struct dfpr_graph {
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     hipEvent_t evk[2 * dfpr::kLoopChunk] = {};   // around each iteration launch (profiling)
     dfpr::Profile prof;
-    int64_t prof_base[4] = {0, 0, 0, 0};   // counters already added to prof
+    int64_t prof_base[5] = {0, 0, 0, 0, 0};   // counters already added to prof
     int32_t refine_sweeps = 0;        // FP64 iterations after the FP32 phase
     int busy = 0;
     int grid = 1024;                  // iteration-kernel workgroups

@@ -880,10 +880,12 @@ static int run_loop(dfpr_graph *g, const dfpr_params &p, bool df, bool f32, uint
         const int64_t de = (int64_t)c.edges - g->prof_base[1];
         const int64_t dxv = (int64_t)c.xverts - g->prof_base[2];
         const int64_t dxe = (int64_t)c.xedges - g->prof_base[3];
+        const int64_t dmk = (int64_t)c.marked - g->prof_base[4];
         g->prof.rows += dv;
         g->prof.edges += de;
         g->prof.exp_rows += dxv;
         g->prof.exp_edges += dxe;
+        g->prof.marked += dmk;
         // per processed row: schedule entry 4 B, row start and length 8 B,
         // R[v] 8 B, |out(v)| 4 B, R'[v] and C'[v] written 16 B (12 B with an
         // FP32 contribution) (+ its mark 4 B and expansion stamp 4 B in
@@ -898,6 +900,7 @@ static int run_loop(dfpr_graph *g, const dfpr_params &p, bool df, bool f32, uint
         g->prof_base[1] = (int64_t)c.edges;
         g->prof_base[2] = (int64_t)c.xverts;
         g->prof_base[3] = (int64_t)c.xedges;
+        g->prof_base[4] = (int64_t)c.marked;
     }
     return DFPR_OK;
 }
