@@ -54,9 +54,9 @@ struct IterArgs {
     const uint32_t *sched_off;  // kSchedBins + 1 offsets
     Ctl *ctl;
     Ctl *mirror;                // host-visible copy of the control block, or NULL
-    double *dr_part;
-    double *rmax_part;          // per-workgroup largest new rank
-    unsigned long long *cnt_part;   // kCounters per workgroup
+    double *dr_part;            // kFoldSlots slots of the L-inf of Delta r
+    double *rmax_part;          //   ... of the largest new rank
+    unsigned long long *cnt_part;   // kCounters per slot
     double base_rank;           // (1 - alpha) / n
     double alpha, tol, ftol;
     uint32_t sbase;             // stamp base of the call
@@ -468,7 +468,8 @@ struct FinalShared {
 };
 
 // One workgroup's share of an iteration of one graph: workgroup blk of the
-// G workgroups given to the graph.  Its partials go to slot blk.
+// G workgroups given to the graph.  Its results are folded into slot
+// blk mod kFoldSlots.
 template <bool DF, bool F32>
 __device__ inline void iter_body(const IterArgs &a, uint32_t blk, uint32_t G, IterShared &sh)
 {
@@ -536,7 +537,6 @@ __device__ inline void iter_body(const IterArgs &a, uint32_t blk, uint32_t G, It
 // iteration.  The launch boundary orders it after k_iter.
 // In the FP32 phase of the precision form, reaching tol or the FP32
 // resolution of the ranks ends the phase instead of the call.
-// `active` is the number of workgroups that wrote partials for this graph.
 // The control block goes to the host mirror when `last` (the last launch
 // the host queued before it next waits) or when this step ends the call or
 // the phase: later launches then return at once.

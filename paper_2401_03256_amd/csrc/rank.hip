@@ -6,15 +6,16 @@
 //   - computes Delta r = |r - R[v]| and the L-inf maximum;
 //   - (Dynamic Frontier) marks the out-neighbours of every row whose rank
 //     moved by more than frontier_tol;
-// followed by a one-workgroup launch of k_final that folds the
-// per-workgroup partials and decides convergence (Delta R <= tol) or the
-// iteration cap.
+// followed by a one-workgroup launch of k_final that folds the slots the
+// workgroups folded their results into and decides convergence
+// (Delta R <= tol) or the iteration cap.
 // The host enqueues iterations in chunks and reads the stop flag between
 // chunks; launches issued after the stop flag is set return at once.
 //
 // Work layout.  Rows are split by in-degree into classes; a class-b row is
 // reduced by group_of(b) lanes of one wave (1, 2, 4, 8, 32 or 64 lanes) or,
-// above 1024 in-edges, by a whole workgroup.  Each lane loads kUnroll
+// above 1024 in-edges, by a whole workgroup.  Rows whose only in-entry is
+// the self-loop have a schedule bin of their own (sched_bin_of).  Each lane loads kUnroll
 // indices and then kUnroll contributions per round, so that many loads are
 // in flight per wave.  Each lane sums its strided share of a row in order
 // and the group folds the partial sums with a fixed butterfly, so the sum
