@@ -274,6 +274,39 @@ def test_dynamic_frontier_config0(dfpr):
     assert abs(st.vertices_processed - sto.vertices_processed) <= 0.02 * sto.vertices_processed
 
 
+def test_self_loop_only_rows_in_dense_mode(dfpr):
+    # Rows whose only in-entry is the self-loop have a schedule bin of their
+    # own on the full schedule.  Vertex 0 reaches 5000 vertices, so every
+    # batch from it runs in dense mode.  Vertices 5001..5998 have no in-edge
+    # but their self-loop; 4000 has one from 0 only.  The batches make 4000
+    # and 5500 cross between one and two in-entries both ways (the schedule
+    # must follow) and use self-loop-only vertices as sources and deletion
+    # targets (they must be processed although no other row points at them).
+    n = 6000
+    src = np.concatenate([np.zeros(5000, np.int32), np.arange(5001, 5999, dtype=np.int32)])
+    dst = np.concatenate([np.arange(1, 5001, dtype=np.int32), np.arange(1, 999, dtype=np.int32)])
+    g, o = _pair(dfpr, n, src, dst)
+    p = dfpr.params(tol=1e-10, frontier_tol=1e-13)
+    g.static(p)
+    Ro, _ = o.static()
+    batches = [_batch([(0, 4000)], [(0, 5500), (5600, 10)]),
+               _batch([(0, 5500)], [(5601, 20), (0, 4000)])]
+    for k, b in enumerate(batches):
+        _say(f"self-loop rows batch {k}")
+        assert g.apply_batch(b) == o.apply_batch(b)
+        R, st = g.dynamic_frontier(b, p=p)
+        Ro, sto, f0, f1 = o.dynamic_frontier(b, Ro, frontier_tol=1e-13, return_flags=True)
+        assert st.converged and sto.converged
+        assert st.affected_initial == sto.affected_initial == int(f0.sum())
+        assert np.max(np.abs(R - Ro)) < TOL_RANK
+        Rref, _ = o.reference()
+        assert np.max(np.abs(R - Rref)) < TOL_RANK
+        fg = g.affected()
+        for v in (4000, 5500, 5600, 5601):
+            assert fg[v] == f1[v], v
+        assert fg[4000] and fg[5500] and fg[5600 + k]
+
+
 def test_dynamic_frontier_sequence_rmat(dfpr):
     n, src, dst = synth.rmat(13, 16, seed=4)
     g, o = _pair(dfpr, n, src, dst)
