@@ -55,6 +55,8 @@ struct Ctl {
     uint32_t snap[2][kBins];    // entries iteration i processes: snap[i & 1]
     uint32_t done;              // iteration loop finished (or aborted)
     uint32_t dense;             // iterations walk the full schedule
+    uint32_t force_dense;       // set during a sparse iteration: walk the full
+                                // schedule from the next iteration on
     uint32_t phase_end;         // the FP32 phase of the precision form is over
     int32_t phase_iters;        // iterations of the current FP32 phase
     double prev_linf;           // Delta R of the previous iteration

@@ -177,6 +177,16 @@ __device__ inline void mark_out_row(const IterArgs &a, int32_t w, uint32_t lane0
     }
 }
 
+// On the class lists, a row with more out-edges than this marks them with
+// plain stores, like the full schedule does, and moves the call to the full
+// schedule from the next iteration on: its out-row alone would fill a good
+// part of the lists, and one workgroup appending them entry by entry (an
+// atomic per out-edge) stalls the whole iteration.
+__device__ inline bool heavy_in_sparse(const IterArgs &a, uint32_t oc)
+{
+    return oc > a.sparse_limit / 8;
+}
+
 // Expansion of the rows of a wave whose lanes have `deg` > 0 out-edges
 // starting at `ob` (`incl` = inclusive prefix sum of `deg` over the wave,
 // `total` its last value): every lane takes one out-edge per round, so
@@ -316,8 +326,13 @@ __device__ inline void wave_unit(const IterArgs &a, const int32_t *list, uint32_
         while (q) {
             const int l = __ffsll((long long)q) - 1;
             const int32_t w = __shfl(v, l);
-            if (sparse) mark_out_row<true>(a, w, lane, kWave, sv);
-            else mark_out_row<false>(a, w, lane, kWave, sv);
+            const uint32_t wc = __shfl(oc, l);
+            if (sparse && !heavy_in_sparse(a, wc)) {
+                mark_out_row<true>(a, w, lane, kWave, sv);
+            } else {
+                if (sparse && lane == 0) a.ctl->force_dense = 1;
+                mark_out_row<false>(a, w, lane, kWave, sv);
+            }
             q &= q - 1;
         }
     }
@@ -346,8 +361,12 @@ __device__ inline void block_row(const IterArgs &a, int32_t v, bool check, bool 
     __syncthreads();
     if (DF && *flag) {
         const uint32_t sv = a.sbase + (uint32_t)a.it + 1;
-        if (sparse) mark_out_row<true>(a, v, threadIdx.x, kBlock, sv);
-        else mark_out_row<false>(a, v, threadIdx.x, kBlock, sv);
+        if (sparse && !heavy_in_sparse(a, a.out_cnt[v])) {
+            mark_out_row<true>(a, v, threadIdx.x, kBlock, sv);
+        } else {
+            if (sparse && threadIdx.x == 0) a.ctl->force_dense = 1;
+            mark_out_row<false>(a, v, threadIdx.x, kBlock, sv);
+        }
     }
     __syncthreads();
 }
@@ -576,7 +595,7 @@ __device__ inline void final_body(const IterArgs &a, bool df, bool f32, FinalSha
                 ctl->snap[par ^ 1][b] = l;
             }
             ctl->marked += after - before;
-            if (after > a.sparse_limit) ctl->dense = 1;
+            if (after > a.sparse_limit || ctl->force_dense) ctl->dense = 1;
         }
         if (f32) {
             // FP32 contributions carry a relative rounding error of 2^-24;

@@ -85,6 +85,7 @@ __global__ void k_reset(Ctl *ctl)
         }
         ctl->done = 0;
         ctl->dense = 0;
+        ctl->force_dense = 0;
         ctl->phase_end = 0;
         ctl->phase_iters = 0;
         ctl->prev_linf = 0.0;
