@@ -273,8 +273,9 @@ int dfpr_profile_read(const dfpr_graph *g, dfpr_profile *out);
  * (graph, batch) that arrive over time, by continuous batching: a request is
  * admitted into one of max_slots slots when a slot is free, its graph has no
  * update in flight (one writer per graph, Section 3.2) and the HBM budget
- * covers the resident graphs plus the scratch of the requests in flight
- * (96 bytes per batch entry).  Admission applies the batch (as
+ * covers the resident graphs (graph store, ranks, marks, schedule and the
+ * applier's copies of long rows, estimated when the graph is added) plus
+ * the scratch of the requests in flight (96 bytes per batch entry).  Admission applies the batch (as
  * dfpr_apply_batch) and runs the initial marking; then every step runs one
  * Dynamic Frontier iteration of every admitted request in one coalesced
  * launch.  Steps run in chunks between two looks by the host (kept to about

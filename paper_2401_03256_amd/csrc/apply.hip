@@ -833,6 +833,13 @@ static int ensure_apply_bufs(dfpr_graph *g, uint64_t B)
     return DFPR_OK;
 }
 
+// Bytes of the row slabs the applier keeps for a graph's current largest row.
+int64_t apply_slab_bytes(const dfpr_graph *g)
+{
+    const uint64_t stride = std::max(g->csr[0].max_cap, g->csr[1].max_cap);
+    return (int64_t)(stride * kBigGrid * 2 * 4);
+}
+
 static int ensure_slab(dfpr_graph *g)
 {
     const uint64_t stride = std::max(g->csr[0].max_cap, g->csr[1].max_cap);

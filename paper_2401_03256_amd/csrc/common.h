@@ -211,6 +211,7 @@ int ranks_to_caller(const dfpr_graph *g, const double *Rint, double *out, int ou
 int ranks_from_caller(const dfpr_graph *g, const double *in, int in_dev, double *Rint);
 
 // device helpers (rank.hip)
+int64_t apply_slab_bytes(const dfpr_graph *g);
 int launch_fill_u32(dfpr_graph *g, uint32_t *p, uint64_t len, uint32_t value);
 
 }  // namespace dfpr

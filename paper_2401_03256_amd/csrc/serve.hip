@@ -145,7 +145,7 @@ static int64_t graph_bytes(const dfpr_graph *g)
     int64_t b = 0;
     for (int o = 0; o < 2; o++) b += (int64_t)g->csr[o].slots * 4 + 3 * n * 4;
     b += 5 * n * 8 + 2 * n * 4 + 2 * n * 4 + (int64_t)kBins * n * 4 + n * 4 + 2 * n * 4;
-    return b;
+    return b + apply_slab_bytes(g);   // the applier's row copies of long rows
 }
 
 static double pct(std::vector<double> v, double q)
