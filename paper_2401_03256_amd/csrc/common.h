@@ -174,7 +174,9 @@ struct dfpr_graph {
     hipStream_t stream = nullptr;
     hipStream_t own_stream = nullptr;
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
-    hipEvent_t evk[2 * dfpr::kLoopChunk] = {};   // around each iteration launch (profiling)
+    hipEvent_t evk[4 * dfpr::kLoopChunk] = {};   // around each iteration launch (profiling),
+                                                 // per chunk slot
+    hipEvent_t evc[2] = {};                      // completion of the chunk in each slot
     dfpr::Profile prof;
     int64_t prof_base[5] = {0, 0, 0, 0, 0};   // counters already added to prof
     int32_t refine_sweeps = 0;        // FP64 iterations after the FP32 phase

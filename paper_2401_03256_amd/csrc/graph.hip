@@ -318,6 +318,8 @@ void dfpr_free_graph(dfpr_graph *g)
     if (g->ev1) (void)hipEventDestroy(g->ev1);
     for (hipEvent_t e : g->evk)
         if (e) (void)hipEventDestroy(e);
+    for (hipEvent_t e : g->evc)
+        if (e) (void)hipEventDestroy(e);
     if (g->own_stream) (void)hipStreamDestroy(g->own_stream);
     delete g;
 }
@@ -382,7 +384,9 @@ int dfpr_load_graph(int32_t n, int64_t m, const int32_t *src, const int32_t *dst
             rc = set_error(DFPR_E_DEVICE, "map upload failed");
     }
     if (!rc) {
-        hipError_t e = hipHostMalloc((void **)&g->ctl_host, sizeof(Ctl), hipHostMallocCoherent);
+        // two mirrors: the chunk in flight in each slot of the iteration loop
+        hipError_t e =
+            hipHostMalloc((void **)&g->ctl_host, 2 * sizeof(Ctl), hipHostMallocCoherent);
         if (e != hipSuccess) rc = hip_fail(e, "hipHostMalloc");
     }
     if (!rc) {
@@ -393,6 +397,9 @@ int dfpr_load_graph(int32_t n, int64_t m, const int32_t *src, const int32_t *dst
         // system-scope fence (with it, each record stalls the queue ~6 us)
         for (hipEvent_t &ev : g->evk)
             if (e == hipSuccess) e = hipEventCreateWithFlags(&ev, hipEventDisableSystemFence);
+        // waited on before the host reads a chunk's mirror: keep the fence
+        for (hipEvent_t &ev : g->evc)
+            if (e == hipSuccess) e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
         if (e != hipSuccess) rc = hip_fail(e, "stream/event");
         g->stream = g->own_stream;
     }

@@ -791,9 +791,10 @@ static int take_base(dfpr_graph *g, int32_t max_iters, uint32_t *base)
 // `base`; iteration i reads buffer base ^ ((i - it0) & 1), or, in the
 // asynchronous form (FP64 only), reads and writes buffer `base` in place.
 // *res_buf receives the buffer holding the result.  Iterations are enqueued in
-// chunks; between chunks the host reads the control block once and sizes
-// the next chunk from the observed geometric decay of Delta R, so few
-// launches run after convergence.
+// chunks, up to two at a time; when a chunk completes the host reads the
+// control block it left and sizes the next chunk from the observed
+// geometric decay of Delta R, less what is still queued, so few launches
+// run after convergence and the device does not wait for the host.
 // Workgroups for the next chunk of a call still on the class lists: what
 // the current lists need, times four and plus 64 for the frontier to grow
 // within the chunk, at least one per CU.  Any grid gives the same result
@@ -816,15 +817,30 @@ static int run_loop(dfpr_graph *g, const dfpr_params &p, bool df, bool f32, uint
 {
     IterArgs a = iter_args(g, p, sbase);
     const bool async = p.mode == DFPR_ASYNC && !f32;
-    int it = it0, chunk = 4;
+    // Up to two chunks are in flight: while the host waits for the older
+    // one and reads the control block it left in its own mirror, the newer
+    // one keeps the device busy.  Chunk c uses mirror, completion event and
+    // profiling events of slot c & 1.
+    Ctl *const mirror[2] = {g->ctl_host, g->ctl_host + 1};
+    struct Chunk {
+        int k, slot;
+    };
+    Chunk q[2];
+    int nq = 0, next_it = it0, nchunks = 0, chunk = 4, fin = 0;
+    // iterations to keep queued beyond the last state read; until a state
+    // is known, two chunks of four
+    int target = 8, cap = 4;
+    bool stop = false;
     uint32_t gsz = (uint32_t)g->grid;
     double prev_dr = -1.0;
     int prev_it = it0;
     *res_buf = base;
-    while (it < p.max_iters) {
-        const int k = std::min(chunk, p.max_iters - it);
+    auto launch = [&](int k) -> int {
+        const int slot = nchunks & 1;
+        a.mirror = mirror[slot];
+        hipEvent_t *ev = g->evk + slot * 2 * kLoopChunk;
         for (int j = 0; j < k; j++) {
-            const int i = it + j;
+            const int i = next_it + j;
             const int src = async ? base : base ^ ((i - it0) & 1);
             const int dst = async ? base : src ^ 1;
             a.Rc = g->R[src];
@@ -834,43 +850,73 @@ static int run_loop(dfpr_graph *g, const dfpr_params &p, bool df, bool f32, uint
             a.C32c = g->C32[src];
             a.C32n = g->C32[src ^ 1];
             a.it = i;
-            if (g->prof.enabled) DFPR_HIP(hipEventRecord(g->evk[2 * j], g->stream));
+            if (g->prof.enabled) DFPR_HIP(hipEventRecord(ev[2 * j], g->stream));
             if (!df) k_iter<false, false><<<gsz, kBlock, 0, g->stream>>>(a);
             else if (f32) k_iter<true, true><<<gsz, kBlock, 0, g->stream>>>(a);
             else k_iter<true, false><<<gsz, kBlock, 0, g->stream>>>(a);
-            if (g->prof.enabled) DFPR_HIP(hipEventRecord(g->evk[2 * j + 1], g->stream));
+            if (g->prof.enabled) DFPR_HIP(hipEventRecord(ev[2 * j + 1], g->stream));
             k_final<<<1, kFinalThreads, 0, g->stream>>>(a, df ? 1 : 0, f32 ? 1 : 0,
                                                          j == k - 1 ? 1 : 0);
         }
         DFPR_HIP(hipGetLastError());
-        // k_snap, the chunk's last k_final and a k_final that ended the
-        // call or the phase leave the control block in the host mirror
-        DFPR_HIP(hipStreamSynchronize(g->stream));
+        DFPR_HIP(hipEventRecord(g->evc[slot], g->stream));
+        q[nq++] = Chunk{k, slot};
+        next_it += k;
+        nchunks++;
+        return DFPR_OK;
+    };
+    while (true) {
+        int queued = 0;
+        for (int t = 0; t < nq; t++) queued += q[t].k;
+        while (!stop && nq < 2 && queued < target && next_it < p.max_iters) {
+            const int k = std::min(std::min(target - queued, cap), p.max_iters - next_it);
+            const int rc = launch(k);
+            if (rc) return rc;
+            queued += k;
+        }
+        if (nq == 0) break;
+        const Chunk c = q[0];
+        q[0] = q[1];
+        nq--;
+        // the chunk's last k_final, or the one that ended the call or the
+        // phase, left the control block in the chunk's mirror
+        DFPR_HIP(hipEventSynchronize(g->evc[c.slot]));
         if (g->prof.enabled) {
             // the iteration kernel alone, launch by launch
-            for (int j = 0; j < k; j++) {
+            const hipEvent_t *ev = g->evk + c.slot * 2 * kLoopChunk;
+            for (int j = 0; j < c.k; j++) {
                 float ms = 0.f;
-                DFPR_HIP(hipEventElapsedTime(&ms, g->evk[2 * j], g->evk[2 * j + 1]));
+                DFPR_HIP(hipEventElapsedTime(&ms, ev[2 * j], ev[2 * j + 1]));
                 g->prof.ms += ms;
             }
-            g->prof.launches += k;
+            g->prof.launches += c.k;
         }
-        if (g->ctl_host->done || (f32 && g->ctl_host->phase_end)) break;
-        it += k;
-        gsz = df && !g->ctl_host->dense ? sparse_grid(g, *g->ctl_host) : (uint32_t)g->grid;
-        const double dr = g->ctl_host->final_linf;
-        const int its = g->ctl_host->iterations;
-        int next = std::min(chunk * 2, 32);
+        if (stop) continue;             // later chunks return at once
+        const Ctl &st = *mirror[c.slot];
+        if (st.done || (f32 && st.phase_end)) {
+            stop = true;
+            fin = c.slot;
+            continue;
+        }
+        // iterations still needed after this state, from the observed
+        // geometric decay of Delta R
+        gsz = df && !st.dense ? sparse_grid(g, st) : (uint32_t)g->grid;
+        const double dr = st.final_linf;
+        const int its = st.iterations;
+        int need = std::min(chunk * 2, 32);
         if (!f32 && prev_dr > 0.0 && dr > 0.0 && dr < prev_dr && its > prev_it && p.tol > 0.0) {
             const double rate = std::pow(dr / prev_dr, 1.0 / (its - prev_it));
-            const double need = std::ceil(std::log(p.tol / dr) / std::log(rate));
-            if (std::isfinite(need))
-                next = (int)std::min<double>(kLoopChunk, std::max(1.0, need));
+            const double left = std::ceil(std::log(p.tol / dr) / std::log(rate));
+            if (std::isfinite(left)) need = (int)std::min<double>(kLoopChunk, std::max(1.0, left));
         }
         prev_dr = dr;
         prev_it = its;
-        chunk = next;
+        chunk = need;
+        cap = kLoopChunk;
+        // at least one more iteration if nothing is queued: the call is not over
+        target = std::max(need, nq > 0 ? 0 : 1);
     }
+    if (fin == 1) *mirror[0] = *mirror[1];   // the final state goes to the main mirror
     if (p.max_iters <= it0) {
         DFPR_HIP(hipMemcpyAsync(g->ctl_host, g->ctl, sizeof(Ctl), hipMemcpyDeviceToHost, g->stream));
         DFPR_HIP(hipStreamSynchronize(g->stream));
