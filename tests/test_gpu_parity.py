@@ -307,6 +307,35 @@ def test_self_loop_only_rows_in_dense_mode(dfpr):
         assert fg[4000] and fg[5500] and fg[5600 + k]
 
 
+@pytest.mark.parametrize("cap", [1, 2, 3, 5, 8, 9, 13])
+def test_iteration_cap_matches_oracle(dfpr, cap):
+    # the host queues iterations in chunks ahead of the device's stop flag;
+    # whatever the cap, exactly that many iterations run and the ranks are
+    # the oracle's after as many iterations (Static, Naive-dynamic and
+    # Dynamic Frontier, all stopped before convergence)
+    _say(f"iteration cap {cap}")
+    n = 2000
+    src, dst = synth.gnm(n, 16000, seed=3)
+    g, o = _pair(dfpr, n, src, dst)
+    p = dfpr.params(max_iters=cap)
+    R, st = g.static(p)
+    Ro, sto = o.static(max_iters=cap)
+    assert st.iterations == sto.iterations == cap and not st.converged
+    assert np.max(np.abs(R - Ro)) < TOL_RANK
+    R0, _ = o.static()
+    b = synth.random_batch(src, dst, n, 40, 160, seed=4)
+    g.apply_batch(b)
+    o.apply_batch(b)
+    Rn, stn = g.naive_dynamic(prev=R0, p=p)
+    Rno, stno = o.naive_dynamic(R0, max_iters=cap)
+    assert stn.iterations == stno.iterations == cap
+    assert np.max(np.abs(Rn - Rno)) < TOL_RANK
+    Rd, std = g.dynamic_frontier(b, prev=R0, p=p)
+    Rdo, stdo = o.dynamic_frontier(b, R0, max_iters=cap)
+    assert std.iterations == stdo.iterations == cap
+    assert np.max(np.abs(Rd - Rdo)) < TOL_RANK
+
+
 def test_dynamic_frontier_sequence_rmat(dfpr):
     n, src, dst = synth.rmat(13, 16, seed=4)
     g, o = _pair(dfpr, n, src, dst)
