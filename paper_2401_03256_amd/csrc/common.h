@@ -64,6 +64,7 @@ struct Ctl {
     int32_t iterations;
     int32_t converged;
     double final_linf;
+    double final_rmax;          // largest rank of the last iteration
     unsigned long long edges;   // in-edges gathered, all iterations
     unsigned long long verts;   // rank updates, all iterations
     unsigned long long xverts;  // rows that expanded (Delta r > frontier_tol)

@@ -586,6 +586,7 @@ __device__ inline void final_body(const IterArgs &a, bool df, bool f32, FinalSha
         ctl->xedges += c[3];
         ctl->iterations = a.it + 1;
         ctl->final_linf = dr;
+        ctl->final_rmax = rm;
         if (sparse) {
             unsigned long long before = 0, after = 0;
             for (int b = 0; b < kBins; b++) {

@@ -93,6 +93,7 @@ __global__ void k_reset(Ctl *ctl)
         ctl->iterations = 0;
         ctl->converged = 0;
         ctl->final_linf = 0.0;
+        ctl->final_rmax = 0.0;
         ctl->edges = ctl->verts = 0;
         ctl->xverts = ctl->xedges = ctl->marked = 0;
         ctl->affected0 = ctl->affected = 0;
@@ -904,9 +905,12 @@ static int run_loop(dfpr_graph *g, const dfpr_params &p, bool df, bool f32, uint
         const double dr = st.final_linf;
         const int its = st.iterations;
         int need = std::min(chunk * 2, 32);
-        if (!f32 && prev_dr > 0.0 && dr > 0.0 && dr < prev_dr && its > prev_it && p.tol > 0.0) {
+        // the FP32 phase ends at the larger of tol and its resolution
+        // floor (see final_body); the FP64 loop at tol
+        const double goal = f32 ? std::max(p.tol, st.final_rmax * 0x1p-22) : p.tol;
+        if (prev_dr > 0.0 && dr > 0.0 && dr < prev_dr && its > prev_it && goal > 0.0) {
             const double rate = std::pow(dr / prev_dr, 1.0 / (its - prev_it));
-            const double left = std::ceil(std::log(p.tol / dr) / std::log(rate));
+            const double left = std::ceil(std::log(goal / dr) / std::log(rate));
             if (std::isfinite(left)) need = (int)std::min<double>(kLoopChunk, std::max(1.0, left));
         }
         prev_dr = dr;
