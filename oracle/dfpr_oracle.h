@@ -20,6 +20,12 @@
  * Vertex loops run under OpenMP with a dynamic schedule of 2048 as in
  * Section 5.1.2; every result is independent of the thread count.
  *
+ * Ranks, marks and CSRs are pinned by the tests (closed forms, dense
+ * solves, the worked example of Section 4.1.2, set arithmetic).  The
+ * iteration counts and work counters in oracle_stats are parity unpinned:
+ * the paper prints none for any input, and a rank change near the frontier
+ * tolerance can flip with the summation order.
+ *
  * All functions return 0 on success and a negative code on bad input:
  *   -1 bad argument, -2 vertex id out of range, -3 out of memory.
  */
