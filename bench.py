@@ -106,8 +106,8 @@ def main():
     ap.add_argument("--serve-slots", type=int, default=8)
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU only: this build runs the whole update on a "
-              "single MI355X (see DESIGN.md for how it would shard); use --gpus 1",
+        print("bench.py measures one GPU only: the library runs the whole update on a "
+              "single MI355X; use --gpus 1",
               file=sys.stderr)
         sys.exit(2)
     if int(os.environ.get("WORLD_SIZE", "1")) > 1:

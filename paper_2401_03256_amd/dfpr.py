@@ -132,7 +132,7 @@ def lib():
     if _lib is not None:
         return _lib
     if not os.path.exists(LIB_PATH):
-        raise RuntimeError(f"{LIB_PATH} is not built; run __graft_entry__.build()")
+        raise RuntimeError(f"{LIB_PATH} is not built; run python paper_2401_03256_amd/build.py")
     try:
         import torch  # noqa: F401
     except ImportError:
