@@ -51,3 +51,16 @@ def test_library_is_built_for_gfx950():
         pytest.skip("libdfpr.so not built")
     data = open(LIB, "rb").read()
     assert b"gfx950" in data
+
+
+def test_bench_refuses_more_than_one_gpu():
+    # the benchmark measures one GPU; asking for more ends at argument
+    # checking, before any device is touched
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    r = subprocess.run([sys.executable, os.path.join(root, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr
+    assert r.stdout == ""
