@@ -228,7 +228,9 @@ int dfpr_get_affected(const dfpr_graph *g, uint8_t *flags_out);
 /* Copy the resident ranks out (host or device pointer, n doubles). */
 int dfpr_get_ranks(const dfpr_graph *g, double *ranks, int on_device);
 
-/* Replace the resident ranks (host or device pointer, n doubles). */
+/* Replace the resident ranks (host or device pointer, n doubles, in the
+ * caller's vertex numbering); NULL restores the uniform start 1/n.
+ * DFPR_E_BUSY while another call uses the graph. */
 int dfpr_set_ranks(dfpr_graph *g, const double *ranks, int on_device);
 
 /* Compacted CSR of G (host arrays): out_orientation 1 gives rows = sources,

@@ -468,6 +468,8 @@ int dfpr_export_csr(const dfpr_graph *g, int out_orientation, int64_t *offsets, 
         offsets[v] = pos;
         if (pos + cnt[r] > g->m)
             return set_error(DFPR_E_DEVICE, "device CSR holds more entries than m");
+        if ((uint64_t)beg[r] + cnt[r] > (uint64_t)c.slots)
+            return set_error(DFPR_E_DEVICE, "device CSR row runs past its slots");
         for (uint32_t k = 0; k < cnt[r]; k++) idx[pos + k] = g->int2ext_h[slots[beg[r] + k]];
         std::sort(idx + pos, idx + pos + cnt[r]);
         pos += cnt[r];

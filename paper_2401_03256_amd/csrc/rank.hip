@@ -1299,6 +1299,8 @@ extern "C" {
 int dfpr_set_ranks(dfpr_graph *g, const double *ranks, int on_device)
 {
     if (!g) return set_error(DFPR_E_ARG, "graph is NULL");
+    BusyGuard guard(g);
+    if (!guard.ok) return set_error(DFPR_E_BUSY, "graph in use");
     const int32_t n = g->n;
     hipStream_t s = g->stream;
     if (ranks) {
