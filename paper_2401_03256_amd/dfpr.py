@@ -208,11 +208,25 @@ def params(alpha=None, tol=None, frontier_tol=None, max_iters=None, precision=No
     return p
 
 
-def _dev_ptr(t):
+def _batch_arrays(batch):
+    """Deletion and insertion pairs as int32 arrays; each side's two arrays
+    must have the same length (the library reads that many of each)."""
+    ds, dd, is_, id_ = (_i32(batch.del_src), _i32(batch.del_dst), _i32(batch.ins_src),
+                        _i32(batch.ins_dst))
+    if ds.ndim != 1 or ds.shape != dd.shape or is_.ndim != 1 or is_.shape != id_.shape:
+        raise ValueError("a batch needs 1-D source and target arrays of equal length")
+    return ds, dd, is_, id_
+
+
+def _dev_ptr(t, dtype=None, numel=None):
     if t is None:
         return None
     if not t.is_cuda or not t.is_contiguous():
         raise ValueError("device arguments must be contiguous tensors on the GPU")
+    if dtype is not None and t.dtype != dtype:
+        raise ValueError(f"device argument of dtype {t.dtype}, expected {dtype}")
+    if numel is not None and t.numel() != numel:
+        raise ValueError(f"device argument of {t.numel()} elements, expected {numel}")
     return _P(t.data_ptr())
 
 
@@ -258,8 +272,7 @@ class Graph:
 
     # -- graph updates ----------------------------------------------------
     def apply_batch(self, batch):
-        ds, dd, is_, id_ = (_i32(batch.del_src), _i32(batch.del_dst), _i32(batch.ins_src),
-                            _i32(batch.ins_dst))
+        ds, dd, is_, id_ = _batch_arrays(batch)
         applied = np.zeros(2, np.int64)
         _check(lib().dfpr_apply_batch(self._h, ds.size, _hp(ds), _hp(dd), is_.size, _hp(is_),
                                       _hp(id_), _hp(applied)))
@@ -267,10 +280,12 @@ class Graph:
 
     def apply_batch_device(self, ds, dd, is_, id_):
         """Torch int32 tensors on the GPU."""
+        import torch
+        nd, ni = ds.numel(), is_.numel()
         applied = np.zeros(2, np.int64)
-        _check(lib().dfpr_apply_batch_device(self._h, ds.numel(), _dev_ptr(ds), _dev_ptr(dd),
-                                             is_.numel(), _dev_ptr(is_), _dev_ptr(id_),
-                                             _hp(applied)))
+        _check(lib().dfpr_apply_batch_device(
+            self._h, nd, _dev_ptr(ds, torch.int32), _dev_ptr(dd, torch.int32, nd), ni,
+            _dev_ptr(is_, torch.int32), _dev_ptr(id_, torch.int32, ni), _hp(applied)))
         return int(applied[0]), int(applied[1])
 
     # -- rank engines -----------------------------------------------------
@@ -283,16 +298,15 @@ class Graph:
 
     def naive_dynamic(self, prev=None, p: Params | None = None, out=True):
         st = _Stats()
-        prev = None if prev is None else np.ascontiguousarray(prev, np.float64)
+        prev = self._ranks_arg(prev)
         R = np.empty(self.n, np.float64) if out else None
         _check(lib().dfpr_pagerank_naive_dynamic(self._h, ctypes.byref(p) if p else None,
                                                  _hp(prev), _hp(R), ctypes.byref(st)))
         return R, _stats(st)
 
     def dynamic_frontier(self, batch, prev=None, p: Params | None = None, out=True):
-        ds, dd, is_, id_ = (_i32(batch.del_src), _i32(batch.del_dst), _i32(batch.ins_src),
-                            _i32(batch.ins_dst))
-        prev = None if prev is None else np.ascontiguousarray(prev, np.float64)
+        ds, dd, is_, id_ = _batch_arrays(batch)
+        prev = self._ranks_arg(prev)
         R = np.empty(self.n, np.float64) if out else None
         st = _Stats()
         _check(lib().dfpr_pagerank_dynamic_frontier(
@@ -303,19 +317,21 @@ class Graph:
     def dynamic_frontier_device(self, ds, dd, is_, id_, prev=None, out=None,
                                 p: Params | None = None):
         """Batch as torch int32 GPU tensors; prev/out optional float64 GPU tensors."""
+        import torch
+        nd, ni = ds.numel(), is_.numel()
         st = _Stats()
         _check(lib().dfpr_pagerank_dynamic_frontier_device(
-            self._h, ctypes.byref(p) if p else None, ds.numel(), _dev_ptr(ds), _dev_ptr(dd),
-            is_.numel(), _dev_ptr(is_), _dev_ptr(id_), _dev_ptr(prev), _dev_ptr(out),
-            ctypes.byref(st)))
+            self._h, ctypes.byref(p) if p else None, nd, _dev_ptr(ds, torch.int32),
+            _dev_ptr(dd, torch.int32, nd), ni, _dev_ptr(is_, torch.int32),
+            _dev_ptr(id_, torch.int32, ni), _dev_ptr(prev, torch.float64, self.n),
+            _dev_ptr(out, torch.float64, self.n), ctypes.byref(st)))
         return _stats(st)
 
     # -- inspection ---------------------------------------------------------
     def dynamic_traversal(self, batch, prev=None, p: Params | None = None, out=True):
         """Dynamic Traversal PageRank (comparator) after apply_batch(batch)."""
-        ds, dd, is_, id_ = (_i32(batch.del_src), _i32(batch.del_dst), _i32(batch.ins_src),
-                            _i32(batch.ins_dst))
-        prev = None if prev is None else np.ascontiguousarray(prev, np.float64)
+        ds, dd, is_, id_ = _batch_arrays(batch)
+        prev = self._ranks_arg(prev)
         R = np.empty(self.n, np.float64) if out else None
         st = _Stats()
         _check(lib().dfpr_pagerank_dynamic_traversal(
@@ -324,16 +340,14 @@ class Graph:
         return R, _stats(st)
 
     def mark_reachable(self, batch):
-        ds, dd, is_, id_ = (_i32(batch.del_src), _i32(batch.del_dst), _i32(batch.ins_src),
-                            _i32(batch.ins_dst))
+        ds, dd, is_, id_ = _batch_arrays(batch)
         flags = np.zeros(self.n, np.uint8)
         _check(lib().dfpr_mark_reachable(self._h, ds.size, _hp(ds), _hp(dd), is_.size, _hp(is_),
                                          _hp(id_), _hp(flags)))
         return flags
 
     def mark_affected(self, batch):
-        ds, dd, is_, id_ = (_i32(batch.del_src), _i32(batch.del_dst), _i32(batch.ins_src),
-                            _i32(batch.ins_dst))
+        ds, dd, is_, id_ = _batch_arrays(batch)
         flags = np.zeros(self.n, np.uint8)
         _check(lib().dfpr_mark_affected(self._h, ds.size, _hp(ds), _hp(dd), is_.size, _hp(is_),
                                         _hp(id_), _hp(flags)))
@@ -350,11 +364,21 @@ class Graph:
         return R
 
     def ranks_device(self, out):
-        _check(lib().dfpr_get_ranks(self._h, _dev_ptr(out), 1))
+        import torch
+        _check(lib().dfpr_get_ranks(self._h, _dev_ptr(out, torch.float64, self.n), 1))
         return out
 
+    def _ranks_arg(self, R):
+        """A host rank vector as n contiguous doubles (the library reads n)."""
+        if R is None:
+            return None
+        R = np.ascontiguousarray(R, np.float64)
+        if R.shape != (self.n,):
+            raise ValueError(f"rank vector of shape {R.shape}, expected ({self.n},)")
+        return R
+
     def set_ranks(self, R=None):
-        R = None if R is None else np.ascontiguousarray(R, np.float64)
+        R = self._ranks_arg(R)
         _check(lib().dfpr_set_ranks(self._h, _hp(R), 0))
 
     def profile_reset(self, enable=True):
@@ -401,8 +425,7 @@ class Server:
         return int(gid.value)
 
     def submit(self, gid, arrival_ms, batch) -> int:
-        ds, dd, is_, id_ = (_i32(batch.del_src), _i32(batch.del_dst), _i32(batch.ins_src),
-                            _i32(batch.ins_dst))
+        ds, dd, is_, id_ = _batch_arrays(batch)
         rid = _I64()
         _check(lib().dfpr_server_submit(self._h, int(gid), float(arrival_ms), ds.size, _hp(ds),
                                         _hp(dd), is_.size, _hp(is_), _hp(id_), ctypes.byref(rid)))

@@ -64,3 +64,18 @@ def test_bench_refuses_more_than_one_gpu():
     assert r.returncode == 2
     assert "one GPU" in r.stderr
     assert r.stdout == ""
+
+
+def test_binding_rejects_ragged_batches():
+    # the library reads n_del (n_ins) entries from both arrays of a side, so
+    # the binding refuses arrays of different lengths before any call
+    import numpy as np
+    from paper_2401_03256_amd import dfpr, synth
+    z = np.zeros(0, np.int32)
+    ok = synth.Batch(np.array([1, 2], np.int32), np.array([3, 4], np.int32), z, z)
+    assert [a.size for a in dfpr._batch_arrays(ok)] == [2, 2, 0, 0]
+    for bad in (synth.Batch(np.array([1, 2], np.int32), np.array([3], np.int32), z, z),
+                synth.Batch(z, z, np.array([5], np.int32), z),
+                synth.Batch(z, z, np.zeros((1, 1), np.int32), np.zeros((1, 1), np.int32))):
+        with pytest.raises(ValueError):
+            dfpr._batch_arrays(bad)

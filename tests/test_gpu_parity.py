@@ -726,3 +726,26 @@ def test_frontier_tolerance_and_batch_mix(dfpr, ftol, mix):
     assert abs(st.iterations - sto.iterations) <= 1
     # marks near tau_f may differ with summation order, only by a few rows
     assert abs(st.affected_final - int(f1.sum())) <= max(5, int(f1.sum()) // 100)
+
+
+# ---------------------------------------------------------------------------
+# resident ranks
+# ---------------------------------------------------------------------------
+
+def test_resident_ranks_round_trip_and_uniform_reset(dfpr):
+    _say("set_ranks / get_ranks round trip, uniform reset")
+    n, src, dst = synth.rmat(11, 8, seed=51)
+    g = dfpr.Graph(n, src, dst)
+    R = np.random.default_rng(52).random(n)
+    R /= R.sum()
+    g.set_ranks(R)
+    assert np.array_equal(g.ranks(), R)
+    # NULL restores the uniform start, so Naive-dynamic from the resident
+    # ranks repeats the Static computation exactly
+    g.set_ranks()
+    assert np.array_equal(g.ranks(), np.full(n, 1.0 / n))
+    Rn, sn = g.naive_dynamic()
+    Rs, ss = g.static()
+    assert sn.iterations == ss.iterations and np.array_equal(Rn, Rs)
+    with pytest.raises(ValueError):
+        g.set_ranks(np.zeros(n - 1))
