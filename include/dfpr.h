@@ -337,7 +337,8 @@ int dfpr_server_submit(dfpr_server *s, int32_t graph_id, double arrival_ms,
  * than its arrival time, and return when all are done.  A request whose
  * batch holds an id outside [0, n) fails (status DFPR_E_RANGE) without
  * changing its graph.  DFPR_E_BUSY if a graph is in use by another call;
- * device errors end the run with DFPR_E_DEVICE. */
+ * device errors end the run with DFPR_E_DEVICE: the requests then in flight
+ * fail with that status and the ranks of their graphs are undefined. */
 int dfpr_server_run(dfpr_server *s, dfpr_server_stats *st);
 
 /* Outcome of one request after dfpr_server_run. */

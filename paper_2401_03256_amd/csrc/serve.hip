@@ -479,6 +479,17 @@ out:
     if (rc) {
         (void)hipStreamSynchronize(srv->stream);
         (void)hipStreamSynchronize(srv->astream);
+        // requests in flight end with the run's error; later runs do not
+        // take them up again
+        for (Slot &s : slots) {
+            if (s.req < 0) continue;
+            Request &q = srv->reqs[s.req];
+            q.state = 2;
+            q.res.status = rc;
+            q.res.done_ms = ms_since(t0);
+            srv->graphs[q.gid].busy = 0;
+            s = Slot();
+        }
     }
     for (size_t i = 0; i < srv->graphs.size(); i++) srv->graphs[i].g->stream = saved[i];
     if (rc) return rc;
