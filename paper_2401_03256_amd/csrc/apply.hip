@@ -952,11 +952,16 @@ static int relayout(dfpr_graph *g, int o, uint32_t novf, const uint64_t *sorted_
     hipStream_t s = g->stream;
     const int32_t n = g->n;
     Csr &c = g->csr[o];
-    uint64_t *caps = nullptr, *sums = nullptr;
+    // temporaries freed on every return (hipFree waits for the device)
+    struct Tmp {
+        uint64_t *p = nullptr;
+        ~Tmp() { (void)hipFree(p); }
+    } caps_buf, sums_buf;
     const uint64_t len = (uint64_t)n + 1;
     const uint32_t nb = (uint32_t)((len + kScanTile - 1) / kScanTile);
-    DFPR_HIP(hipMalloc(&caps, len * 8));
-    DFPR_HIP(hipMalloc(&sums, (uint64_t)nb * 8));
+    DFPR_HIP(hipMalloc(&caps_buf.p, len * 8));
+    DFPR_HIP(hipMalloc(&sums_buf.p, (uint64_t)nb * 8));
+    uint64_t *const caps = caps_buf.p, *const sums = sums_buf.p;
     k_caps<<<grid_for(len), kBlock, 0, s>>>(n, c.cap, caps);
     k_ovf_caps<<<grid_for(novf), kBlock, 0, s>>>(novf, g->ap.ovf_list[o], g->ap.ovf_need[o],
                                                  sorted_keys, caps, c.cap);
@@ -970,11 +975,7 @@ static int relayout(dfpr_graph *g, int o, uint32_t novf, const uint64_t *sorted_
     DFPR_HIP(hipMemcpyAsync(&packed, caps + n, 8, hipMemcpyDeviceToHost, s));
     DFPR_HIP(hipStreamSynchronize(s));
     const uint64_t slots = packed + std::max<uint64_t>(packed / 16, 1 << 16);
-    if (slots > 0xFFFFFFFFull) {
-        (void)hipFree(caps);
-        (void)hipFree(sums);
-        return set_error(DFPR_E_LIMIT, "graph needs more than 2^32-1 edge slots");
-    }
+    if (slots > 0xFFFFFFFFull) return set_error(DFPR_E_LIMIT, "graph needs more than 2^32-1 edge slots");
     int32_t *nidx = nullptr;
     DFPR_HIP(hipMalloc(&nidx, slots * 4));
     k_move_rows<<<4096, kBlock, 0, s>>>(n, c.beg, c.cnt, c.idx, caps, nidx);
@@ -983,8 +984,6 @@ static int relayout(dfpr_graph *g, int o, uint32_t novf, const uint64_t *sorted_
     DFPR_HIP(hipMemcpyAsync(&g->ctl->top[o], &top, 8, hipMemcpyHostToDevice, s));
     DFPR_HIP(hipStreamSynchronize(s));
     (void)hipFree(c.idx);
-    (void)hipFree(caps);
-    (void)hipFree(sums);
     c.idx = nidx;
     c.slots = slots;
     for (int32_t d : need) {
