@@ -184,7 +184,10 @@ int dfpr_pagerank_dynamic_frontier(dfpr_graph *g, const dfpr_params *p,
                                    dfpr_stats *st);
 
 /* As dfpr_pagerank_dynamic_frontier with the batch arrays, prev and
- * ranks_out in device memory (prev and ranks_out nullable as above). */
+ * ranks_out in device memory (prev and ranks_out nullable as above).  The
+ * ids are checked on the device: an id outside [0, n) ends the call with
+ * DFPR_E_RANGE before any iteration, the resident ranks then being prev if
+ * given, else unchanged. */
 int dfpr_pagerank_dynamic_frontier_device(dfpr_graph *g, const dfpr_params *p,
                                           int64_t n_del, const int32_t *del_src,
                                           const int32_t *del_dst, int64_t n_ins,
