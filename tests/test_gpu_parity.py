@@ -749,3 +749,21 @@ def test_resident_ranks_round_trip_and_uniform_reset(dfpr):
     assert sn.iterations == ss.iterations and np.array_equal(Rn, Rs)
     with pytest.raises(ValueError):
         g.set_ranks(np.zeros(n - 1))
+
+
+def test_device_call_rejects_out_of_range_ids(dfpr):
+    # ids in device arrays are checked by the device: the call ends with
+    # DFPR_E_RANGE before any iteration and the resident ranks stay
+    import torch
+    _say("device Dynamic Frontier with an id outside [0, n)")
+    n, src, dst = synth.rmat(10, 8, seed=61)
+    g = dfpr.Graph(n, src, dst)
+    R0, _ = g.static()
+    bad = [torch.tensor(x, dtype=torch.int32, device="cuda")
+           for x in ([], [], [0, 5], [1, n])]
+    with pytest.raises(dfpr.DfprError) as e:
+        g.dynamic_frontier_device(*bad)
+    assert e.value.code == dfpr.DFPR_E_RANGE
+    assert np.array_equal(g.ranks(), R0)
+    with pytest.raises(ValueError):
+        g.dynamic_frontier_device(*bad[:3], bad[3][:1])
