@@ -1,11 +1,13 @@
 """Parity at full size, in the launch configuration the bench times.
 
-R-MAT scale 22 (4,194,304 vertices, about 6.9e7 edges with self-loops)
-and the 4096 x 4096 grid with 5% diagonal shortcuts (16,777,216 vertices):
-the HIP library against the oracle on the same seeded inputs.  CSRs and
-initial markings bit-exact; ranks within 1e-9 L-inf, each side starting
-from its own previous ranks.  The oracle runs on the host cores, so these
-cases take tens of seconds each.
+R-MAT scale 22 (4,194,304 vertices, about 6.9e7 edges with self-loops),
+R-MAT scale 24 (16,777,216 vertices, about 2.8e8 edges, the precision
+form's workload) and the 4096 x 4096 grid with 5% diagonal shortcuts
+(16,777,216 vertices): the HIP library against the oracle on the same
+seeded inputs.  CSRs and initial markings bit-exact; FP64 ranks within
+1e-9 L-inf, each side starting from its own previous ranks.  The oracle
+runs on the host cores, so these cases take tens of seconds to a few
+minutes each.
 """
 import sys
 
@@ -81,6 +83,49 @@ def test_rmat22_static_and_dynamic_frontier(dfpr):
     Rt, sto = o.dynamic_traversal(b, Ro)
     assert st.converged and st.affected_final == sto.affected_final
     assert np.max(np.abs(R - Rt)) < TOL_RANK
+
+
+def test_rmat24_fp64_and_fp32_form(dfpr):
+    # one batch of 1e-4 |E|: FP64 Dynamic Frontier and the FP32 storage
+    # form (FP32 phase + FP64 refinement) from the same previous ranks, both
+    # within 1e-9 of the oracle; the FP32 phase alone within 1e-6 of as many
+    # FP64 iterations of the oracle
+    n, src, dst = synth.rmat(24, 16, seed=1)
+    _say(f"rmat24: generated, {src.size} edges")
+    g = dfpr.Graph(n, src, dst)
+    o = oracle.OracleGraph(n, src, dst)
+    m = o.m
+    b = synth.batch_sequence(src, dst, n, [synth.batch_counts(1e-4, m)], seed=2)[0]
+    del src, dst
+    p64 = dfpr.params(frontier_tol=FTOL)
+    p32 = dfpr.params(frontier_tol=FTOL, precision=dfpr.FP32_KAHAN)
+    R0, st = g.static(p64)
+    Ro, sto = o.static()
+    _say(f"rmat24: static {st.iterations} it (oracle {sto.iterations})")
+    assert np.max(np.abs(R0 - Ro)) < TOL_RANK
+    _say(f"rmat24: batch of {b.size} edges")
+    assert g.apply_batch(b) == o.apply_batch(b)
+    assert np.array_equal(g.mark_affected(b), o.mark_initial(b))
+    R32, s32 = g.dynamic_frontier(b, p=p32)
+    k32 = s32.iterations - s32.refine_sweeps
+    g.set_ranks(R0)
+    R32p, s32p = g.dynamic_frontier(
+        b, p=dfpr.params(frontier_tol=FTOL, precision=dfpr.FP32_KAHAN, max_iters=k32))
+    g.set_ranks(R0)
+    R64, s64 = g.dynamic_frontier(b, p=p64)
+    _say(f"rmat24: FP64 {s64.iterations} it, FP32 form {s32.iterations} it "
+         f"({s32.refine_sweeps} refinement sweeps); oracle")
+    Rd, sd = o.dynamic_frontier(b, Ro, frontier_tol=FTOL)
+    Rk, _ = o.dynamic_frontier(b, Ro, frontier_tol=FTOL, max_iters=k32)
+    assert s64.converged and s32.converged and sd.converged
+    assert abs(s64.iterations - sd.iterations) <= 1
+    assert s64.affected_initial == sd.affected_initial
+    assert np.max(np.abs(R64 - Rd)) < TOL_RANK
+    assert np.max(np.abs(R32 - Rd)) < TOL_RANK
+    assert s32p.iterations == k32 and s32p.refine_sweeps == 0
+    assert np.max(np.abs(R32p - Rk)) < 1e-6
+    _say("rmat24: CSRs")
+    _same_csr(g, o)
 
 
 def test_grid4096_uniform_and_localised(dfpr):
