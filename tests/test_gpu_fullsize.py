@@ -2,9 +2,10 @@
 
 R-MAT scale 22 (4,194,304 vertices, about 6.9e7 edges with self-loops),
 R-MAT scale 24 (16,777,216 vertices, about 2.8e8 edges, the precision
-form's workload) and the 4096 x 4096 grid with 5% diagonal shortcuts
-(16,777,216 vertices): the HIP library against the oracle on the same
-seeded inputs.  CSRs and initial markings bit-exact; FP64 ranks within
+form's workload), the 4096 x 4096 grid with 5% diagonal shortcuts
+(16,777,216 vertices) and the serving form's twelve resident R-MAT graphs
+(scales 16 to 22): the HIP library against the oracle on the same seeded
+inputs.  CSRs and initial markings bit-exact; FP64 ranks within
 1e-9 L-inf, each side starting from its own previous ranks.  The oracle
 runs on the host cores, so these cases take tens of seconds to a few
 minutes each.
@@ -137,3 +138,75 @@ def test_grid4096_uniform_and_localised(dfpr):
     uni = synth.batch_sequence(src, dst, n, [(nd, ni)], seed=2)
     loc = [synth.localized_batch(src, dst, side, nd, ni, seed=10)]
     _run_sequence(dfpr, g, o, uni + loc, "grid4096")
+
+
+def test_serving_twelve_graphs_alone_and_in_the_mix(dfpr):
+    # the serving workload's graphs (R-MAT scales 16, 18, 20, 22, three
+    # seeds each, FP32 storage on the second seed of every scale) and 24
+    # requests of log-uniform size in [1e-7, 1e-3] |E| for uniformly chosen
+    # graphs, all arriving at once: every served result equals the plain
+    # calls one at a time, bitwise (FP64 and FP32 graphs); the graphs of
+    # scales 16 and 18 are replayed by the oracle, within 1e-9
+    rng = synth.rng_for(71)
+    work = []
+    for sc in (16, 18, 20, 22):
+        for k in range(3):
+            n, s_, d_ = synth.rmat(sc, 16, seed=100 + 10 * sc + k)
+            work.append([sc, n, s_, d_, dfpr.FP32_KAHAN if k == 1 else dfpr.FP64, []])
+    nreq = 24
+    gids = rng.integers(0, len(work), size=nreq)
+    fracs = np.exp(np.log(1e-7) + rng.random(nreq) * (np.log(1e-3) - np.log(1e-7)))
+    for gi, w in enumerate(work):
+        _, n, s_, d_, _, bl = w
+        ks = [k for k in range(nreq) if gids[k] == gi]
+        counts = [synth.batch_counts(fracs[k], s_.size + n) for k in ks]
+        bl.extend(zip(ks, synth.batch_sequence(s_, d_, n, counts, seed=300 + gi)))
+    _say(f"serving: 12 graphs generated, requests per graph {np.bincount(gids, minlength=12).tolist()}")
+    p0 = dfpr.params(frontier_tol=FTOL)
+    pg = [dfpr.params(frontier_tol=FTOL, precision=w[4]) for w in work]
+    # one at a time through the plain calls
+    alone_R, alone_it = [], {}
+    for w, p in zip(work, pg):
+        g = dfpr.Graph(w[1], w[2], w[3])
+        g.static(p0, out=False)
+        for k, b in w[5]:
+            g.apply_batch(b)
+            _, st = g.dynamic_frontier(b, p=p, out=False)
+            alone_it[k] = st.iterations
+        alone_R.append(g.ranks())
+        g.close()
+    _say("serving: one at a time done")
+    # the same requests through the server
+    srv = dfpr.Server(max_slots=8, hbm_budget_bytes=200 << 30)
+    graphs = []
+    for w, p in zip(work, pg):
+        g = dfpr.Graph(w[1], w[2], w[3])
+        g.static(p0, out=False)
+        graphs.append((g, srv.add_graph(g, p)))
+    rid = {}
+    for k in range(nreq):
+        gi = int(gids[k])
+        b = dict(work[gi][5])[k]
+        rid[k] = srv.submit(graphs[gi][1], 0.0, b)
+    st = srv.run()
+    _say(f"serving: served, max active {st['max_active']}, steps {st['steps']}")
+    assert st["completed"] == nreq and st["failed"] == 0 and st["max_active"] > 1
+    for k in range(nreq):
+        r = srv.result(rid[k])
+        assert r["status"] == 0 and r["converged"] and r["iterations"] == alone_it[k]
+    for gi, (g, _) in enumerate(graphs):
+        assert np.array_equal(g.ranks(), alone_R[gi]), work[gi][0]
+    # the oracle replays the small graphs
+    for gi, w in enumerate(work):
+        if w[0] > 18:
+            continue
+        o = oracle.OracleGraph(w[1], w[2], w[3])
+        Ro, _ = o.static()
+        for k, b in w[5]:
+            o.apply_batch(b)
+            Ro, sto = o.dynamic_frontier(b, Ro, frontier_tol=FTOL)
+            assert sto.converged
+        assert np.max(np.abs(alone_R[gi] - Ro)) < TOL_RANK, f"graph {gi}"
+    srv.close()
+    for g, _ in graphs:
+        g.close()
