@@ -183,7 +183,7 @@ def main():
         edges += st.edges_processed
         f = fracs[i % len(fracs)]
         per.setdefault(f, []).append((dt * 1e3, st.iterations, st.affected_final,
-                                      st.edges_processed))
+                                      st.edges_processed, st.ms_apply, st.ms_mark, st.ms_iter))
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     prof = g.profile()
@@ -280,7 +280,13 @@ def main():
                    "frontier_tol": args.frontier_tol, "parallelism": "single GPU"},
         "latency_ms": {"p50": round(pct(lat, 50), 3), "p99": round(pct(lat, 99), 3),
                        "by_frac_p50": {str(f): round(pct([x[0] for x in v], 50), 3)
-                                       for f, v in sorted(per.items())}},
+                                       for f, v in sorted(per.items())},
+                       # device time per step by phase (HIP events): batch
+                       # applier, set-up and initial marking, iterations
+                       "device_split_mean_by_frac": {
+                           str(f): {k: round(float(np.mean([x[j] for x in v])), 3)
+                                    for k, j in (("apply", 4), ("mark", 5), ("iterate", 6))}
+                           for f, v in sorted(per.items())}},
         "roofline": roofline,
         "cpu_baseline": cpu,
         "comparators": comparators,

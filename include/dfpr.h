@@ -102,6 +102,17 @@ typedef struct {
     int64_t affected_final;     /* vertices marked when the loop ended         */
     int64_t vertices_processed; /* rank updates, summed over iterations        */
     int64_t edges_processed;    /* in-edges gathered, summed over iterations   */
+    double ms_mark;             /* part of ms_device before the first
+                                   iteration: batch staging, starting ranks,
+                                   class schedule, and the initial marking
+                                   (Dynamic Frontier) or the reachability
+                                   search (Dynamic Traversal)                 */
+    double ms_iter;             /* the rest of ms_device: iterations (FP32
+                                   phase, renormalisation, refinement) and the
+                                   closing pass over the marks                 */
+    double ms_apply;            /* device time of the last dfpr_apply_batch or
+                                   dfpr_apply_batch_device on this graph (0 if
+                                   none, or if it was empty); not in ms_device */
 } dfpr_stats;
 
 /* Defaults of Section 5.1.2 and Section 4.3. */

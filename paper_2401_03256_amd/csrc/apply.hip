@@ -1006,12 +1006,14 @@ int apply_batch_impl(dfpr_graph *g, int64_t n_del, const int32_t *ds, const int3
         if (rc) return rc;
     }
     if (applied) applied[0] = applied[1] = 0;
+    g->last_apply_ms = 0.f;
     const uint32_t B = (uint32_t)(n_del + n_ins);
     if (B == 0) return DFPR_OK;
     int rc = ensure_apply_bufs(g, B);
     if (!rc) rc = ensure_slab(g);
     if (rc) return rc;
     hipStream_t s = g->stream;
+    DFPR_HIP(hipEventRecord(g->ev_a0, s));
     rc = stage_batch(g, n_del, ds, dd, n_ins, is, id, on_device, &ds, &dd, &is, &id);
     if (rc) return rc;
     ApplyArgs a = apply_args(g);
@@ -1048,6 +1050,7 @@ int apply_batch_impl(dfpr_graph *g, int64_t n_del, const int32_t *ds, const int3
     k_apply_rows<true><<<dim3(kBigGrid, 2), kBlock, 0, s>>>(a, B, -1);
     k_apply_fold<<<1, kFoldThreads, 0, s>>>(a.part, tiny_grid, small_grid, a.ctl);
     DFPR_HIP(hipGetLastError());
+    DFPR_HIP(hipEventRecord(g->ev_a1, s));
     DFPR_HIP(hipMemcpyAsync(g->ctl_host, g->ctl, sizeof(Ctl), hipMemcpyDeviceToHost, s));
     DFPR_HIP(hipStreamSynchronize(s));
     if (g->ctl_host->err) return set_error(DFPR_E_RANGE, "vertex id outside [0, n) in the batch");
@@ -1070,6 +1073,7 @@ int apply_batch_impl(dfpr_graph *g, int64_t n_del, const int32_t *ds, const int3
         DFPR_HIP(hipMemcpyAsync(&g->ctl->nbig[o], &g->ctl->novf[o], 4, hipMemcpyDeviceToDevice, s));
         k_apply_rows<true><<<dim3(kBigGrid, 1), kBlock, 0, s>>>(b, B, o);
         DFPR_HIP(hipGetLastError());
+        DFPR_HIP(hipEventRecord(g->ev_a1, s));
         DFPR_HIP(hipMemcpyAsync(g->ctl_host, g->ctl, sizeof(Ctl), hipMemcpyDeviceToHost, s));
         DFPR_HIP(hipStreamSynchronize(s));
         if (g->ctl_host->novf[o] != novf)
@@ -1080,6 +1084,11 @@ int apply_batch_impl(dfpr_graph *g, int64_t n_del, const int32_t *ds, const int3
     const int64_t eff_del = (int64_t)g->ctl_host->applied[0];
     const int64_t eff_ins = (int64_t)g->ctl_host->applied[1];
     g->m += eff_ins - eff_del;
+    {
+        float ms = 0.f;
+        DFPR_HIP(hipEventElapsedTime(&ms, g->ev_a0, g->ev_a1));
+        g->last_apply_ms = ms;
+    }
     if (applied) {
         applied[0] = eff_del;
         applied[1] = eff_ins;

@@ -174,7 +174,10 @@ struct dfpr_graph {
     double *scratch_sum = nullptr;    // FP64 reduction scratch
     hipStream_t stream = nullptr;
     hipStream_t own_stream = nullptr;
-    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;     // a call's device time
+    hipEvent_t ev_mid = nullptr;                 // its first iteration's start
+    hipEvent_t ev_a0 = nullptr, ev_a1 = nullptr; // the last batch application
+    float last_apply_ms = 0.f;
     hipEvent_t evk[4 * dfpr::kLoopChunk] = {};   // around each iteration launch (profiling),
                                                  // per chunk slot
     hipEvent_t evc[2] = {};                      // completion of the chunk in each slot

@@ -314,8 +314,8 @@ void dfpr_free_graph(dfpr_graph *g)
     (void)hipFree(g->ap.part);
     (void)hipFree(g->ap.slab);
     (void)hipFree(g->ap.batch_dev);
-    if (g->ev0) (void)hipEventDestroy(g->ev0);
-    if (g->ev1) (void)hipEventDestroy(g->ev1);
+    for (hipEvent_t e : {g->ev0, g->ev1, g->ev_mid, g->ev_a0, g->ev_a1})
+        if (e) (void)hipEventDestroy(e);
     for (hipEvent_t e : g->evk)
         if (e) (void)hipEventDestroy(e);
     for (hipEvent_t e : g->evc)
@@ -393,6 +393,9 @@ int dfpr_load_graph(int32_t n, int64_t m, const int32_t *src, const int32_t *dst
         hipError_t e = hipStreamCreateWithFlags(&g->own_stream, hipStreamNonBlocking);
         if (e == hipSuccess) e = hipEventCreate(&g->ev0);
         if (e == hipSuccess) e = hipEventCreate(&g->ev1);
+        // phase marks, read after the call's stream synchronisation
+        for (hipEvent_t *ev : {&g->ev_mid, &g->ev_a0, &g->ev_a1})
+            if (e == hipSuccess) e = hipEventCreateWithFlags(ev, hipEventDisableSystemFence);
         // per-launch timing only, read after a stream synchronisation: no
         // system-scope fence (with it, each record stalls the queue ~6 us)
         for (hipEvent_t &ev : g->evk)

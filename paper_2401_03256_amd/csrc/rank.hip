@@ -966,9 +966,14 @@ static void fill_stats(dfpr_graph *g, dfpr_stats *st, bool df)
     st->refine_sweeps = g->refine_sweeps;
     st->reserved = 0;
     st->final_linf = c.final_linf;
-    float ms = 0.f;
+    float ms = 0.f, ms0 = 0.f, ms1 = 0.f;
     (void)hipEventElapsedTime(&ms, g->ev0, g->ev1);
+    (void)hipEventElapsedTime(&ms0, g->ev0, g->ev_mid);
+    (void)hipEventElapsedTime(&ms1, g->ev_mid, g->ev1);
     st->ms_device = ms;
+    st->ms_mark = ms0;
+    st->ms_iter = ms1;
+    st->ms_apply = g->last_apply_ms;
     st->affected_initial = df ? (int64_t)c.affected0 : g->n;
     st->affected_final = df ? (int64_t)c.affected : g->n;
     st->vertices_processed = (int64_t)c.verts;
@@ -1006,6 +1011,7 @@ static int full_sweeps(dfpr_graph *g, const dfpr_params *pp, const double *prev,
     int res = cur;
     g->refine_sweeps = 0;
     std::memset(g->prof_base, 0, sizeof(g->prof_base));
+    DFPR_HIP(hipEventRecord(g->ev_mid, s));
     rc = run_loop(g, p, false, false, 0, 0, cur, &res);
     if (rc) return rc;
     k_copy2<<<blocks_for(n), kBlock, 0, s>>>(n, g->R[res], g->R[res ^ 1], g->C[res],
@@ -1124,6 +1130,7 @@ static int df_impl(dfpr_graph *g, const dfpr_params *pp, int64_t nd, const int32
     uint32_t sbase = 0;
     rc = df_begin(g, p, nd, bds, bdd, ni, bis, bid, prev, on_device, &sbase);
     if (rc) return rc;
+    DFPR_HIP(hipEventRecord(g->ev_mid, s));
     int res = cur;
     if (p.precision == DFPR_FP32_KAHAN) {
         // FP32 phase on FP32 copies of the contributions
@@ -1272,6 +1279,7 @@ static int dt_impl(dfpr_graph *g, const dfpr_params *pp, int64_t nd, const int32
     DFPR_HIP(hipGetLastError());
     g->refine_sweeps = 0;
     std::memset(g->prof_base, 0, sizeof(g->prof_base));
+    DFPR_HIP(hipEventRecord(g->ev_mid, s));
     int res = cur;
     rc = run_loop(g, p, true, false, sbase, 0, cur, &res);
     if (rc) return rc;

@@ -60,7 +60,9 @@ class _Stats(ctypes.Structure):
                 ("refine_sweeps", ctypes.c_int32), ("reserved", ctypes.c_int32),
                 ("final_linf", ctypes.c_double), ("ms_device", ctypes.c_double),
                 ("affected_initial", ctypes.c_int64), ("affected_final", ctypes.c_int64),
-                ("vertices_processed", ctypes.c_int64), ("edges_processed", ctypes.c_int64)]
+                ("vertices_processed", ctypes.c_int64), ("edges_processed", ctypes.c_int64),
+                ("ms_mark", ctypes.c_double), ("ms_iter", ctypes.c_double),
+                ("ms_apply", ctypes.c_double)]
 
 
 class Profile(ctypes.Structure):
@@ -112,11 +114,15 @@ class Stats:
     affected_final: int
     vertices_processed: int
     edges_processed: int
+    ms_mark: float
+    ms_iter: float
+    ms_apply: float
 
 
 def _stats(s):
     return Stats(s.iterations, bool(s.converged), s.refine_sweeps, s.final_linf, s.ms_device,
-                 s.affected_initial, s.affected_final, s.vertices_processed, s.edges_processed)
+                 s.affected_initial, s.affected_final, s.vertices_processed, s.edges_processed,
+                 s.ms_mark, s.ms_iter, s.ms_apply)
 
 
 _lib = None

@@ -767,3 +767,21 @@ def test_device_call_rejects_out_of_range_ids(dfpr):
     assert np.array_equal(g.ranks(), R0)
     with pytest.raises(ValueError):
         g.dynamic_frontier_device(*bad[:3], bad[3][:1])
+
+
+def test_stats_split_device_time_by_phase(dfpr):
+    _say("per-phase device times in the statistics")
+    n, src, dst = synth.rmat(12, 16, seed=81)
+    g = dfpr.Graph(n, src, dst)
+    _, st = g.static()
+    assert st.ms_apply == 0.0 and st.ms_mark >= 0.0 and st.ms_iter > 0.0
+    b = synth.random_batch(src, dst, n, 20, 80, seed=82)
+    g.apply_batch(b)
+    for call in (lambda: g.dynamic_frontier(b), lambda: g.dynamic_traversal(b),
+                 lambda: g.dynamic_frontier(b, p=dfpr.params(precision=dfpr.FP32_KAHAN))):
+        _, st = call()
+        assert st.ms_apply > 0.0 and st.ms_mark > 0.0 and st.ms_iter > 0.0
+        assert abs(st.ms_mark + st.ms_iter - st.ms_device) <= 0.01 + 1e-3 * st.ms_device
+    g.apply_batch(synth.Batch.empty())
+    _, st = g.naive_dynamic()
+    assert st.ms_apply == 0.0
