@@ -401,6 +401,26 @@ class Graph:
         _check(lib().dfpr_export_csr(self._h, 1 if out else 0, _hp(off), _hp(idx)))
         return off, idx[: self.m]
 
+    # -- checkpoint ---------------------------------------------------------
+    def save(self, path):
+        """Checkpoint: the current graph (out-CSR, self-loops included) and
+        the resident ranks, the only state carried from one snapshot to the
+        next (Algorithm 1 takes R^{t-1}), in one .npz file."""
+        off, idx = self.csr(out=True)
+        np.savez(path, n=np.int64(self.n), out_offsets=off, out_idx=idx, ranks=self.ranks())
+
+    @classmethod
+    def load(cls, path):
+        """A graph and its ranks from save(); the file holds plain arrays
+        and is read without unpickling."""
+        with np.load(path, allow_pickle=False) as z:
+            n = int(z["n"])
+            off = z["out_offsets"]
+            src = np.repeat(np.arange(n, dtype=np.int32), np.diff(off))
+            g = cls(n, src, z["out_idx"])
+            g.set_ranks(z["ranks"])
+        return g
+
 
 class Server:
     """Serving form: resident graphs, update requests served by continuous

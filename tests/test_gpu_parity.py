@@ -785,3 +785,38 @@ def test_stats_split_device_time_by_phase(dfpr):
     g.apply_batch(synth.Batch.empty())
     _, st = g.naive_dynamic()
     assert st.ms_apply == 0.0
+
+
+def test_checkpoint_and_resume(dfpr, tmp_path):
+    # a graph saved after some batches and loaded again continues the same
+    # sequence: the same CSR after every batch, ranks within the parity
+    # tolerance of the uninterrupted run (the reloaded graph renumbers its
+    # vertices, so sums may round differently and a call may stop one
+    # iteration apart)
+    _say("checkpoint and resume")
+    n, src, dst = synth.rmat(12, 16, seed=91)
+    counts = [synth.batch_counts(f, src.size + n) for f in (1e-4, 1e-3, 1e-4, 1e-3)]
+    seq = synth.batch_sequence(src, dst, n, counts, seed=92)
+    g = dfpr.Graph(n, src, dst)
+    g.static()
+    for b in seq[:2]:
+        g.apply_batch(b)
+        g.dynamic_frontier(b)
+    path = tmp_path / "ckpt.npz"
+    g.save(path)
+    h = dfpr.Graph.load(path)
+    assert np.array_equal(h.ranks(), g.ranks())
+    _same_csr_pair(g, h)
+    for b in seq[2:]:
+        assert g.apply_batch(b) == h.apply_batch(b)
+        Rg, sg = g.dynamic_frontier(b)
+        Rh, sh = h.dynamic_frontier(b)
+        assert sg.converged and sh.converged and abs(sg.iterations - sh.iterations) <= 1
+        assert np.max(np.abs(Rg - Rh)) < TOL_RANK
+    _same_csr_pair(g, h)
+
+
+def _same_csr_pair(a, b):
+    for out in (True, False):
+        x, y = a.csr(out), b.csr(out)
+        assert np.array_equal(x[0], y[0]) and np.array_equal(x[1], y[1])
