@@ -820,3 +820,42 @@ def _same_csr_pair(a, b):
     for out in (True, False):
         x, y = a.csr(out), b.csr(out)
         assert np.array_equal(x[0], y[0]) and np.array_equal(x[1], y[1])
+
+
+@pytest.mark.parametrize("n", [1, 2, 65])
+def test_degenerate_graphs_every_method(dfpr, n):
+    # one vertex (its self-loop only), two vertices and one edge, and a
+    # complete digraph whose rows are one entry longer than a wave: every
+    # method against the oracle's reference, and the closed form where
+    # there is one (uniform ranks on a vertex-transitive graph)
+    _say(f"degenerate graph n={n}")
+    if n == 1:
+        src = dst = np.zeros(0, np.int32)
+        b = _batch([(0, 0)], [])                 # deleting a self-loop changes nothing
+    elif n == 2:
+        src, dst = np.array([0], np.int32), np.array([1], np.int32)
+        b = _batch([(0, 1)], [(1, 0)])
+    else:
+        u, v = np.meshgrid(np.arange(n), np.arange(n), indexing="ij")
+        keep = u != v
+        src, dst = u[keep].astype(np.int32), v[keep].astype(np.int32)
+        b = _batch([(0, 1)], [])
+    g, o = _pair(dfpr, n, src, dst)
+    R0, st = g.static()
+    Ro, _ = o.static()
+    assert st.converged and np.max(np.abs(R0 - Ro)) < TOL_RANK
+    if n != 2:
+        assert np.max(np.abs(R0 - 1.0 / n)) < 1e-15
+    assert g.apply_batch(b) == o.apply_batch(b)
+    _same_csr(g, o)
+    Rref, _ = o.reference()
+    runs = [("DF", lambda: g.dynamic_frontier(b, p=dfpr.params(frontier_tol=1e-13))),
+            ("FP32 form", lambda: g.dynamic_frontier(
+                b, p=dfpr.params(frontier_tol=1e-13, precision=dfpr.FP32_KAHAN))),
+            ("DT", lambda: g.dynamic_traversal(b)),
+            ("naive", lambda: g.naive_dynamic())]
+    for name, call in runs:
+        g.set_ranks(R0)
+        R, s_ = call()
+        assert s_.converged, name
+        assert np.max(np.abs(R - Rref)) < TOL_RANK, name
