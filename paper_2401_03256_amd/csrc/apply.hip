@@ -34,7 +34,10 @@ namespace dfpr {
 constexpr int kTile = 2048;    // keys sorted per workgroup in LDS
 constexpr int kOpsLds = 1024;  // batch entries of one row per round
 constexpr int kRowLds = 4096;  // rows up to this capacity are copied to LDS
-constexpr int kBigGrid = 64;   // workgroups (and slabs) for larger rows
+#ifndef DFPR_BIG_GRID
+#define DFPR_BIG_GRID 256
+#endif
+constexpr int kBigGrid = DFPR_BIG_GRID;   // workgroups (and slabs) per orientation for larger rows
 // Workgroups of the three row kernels.  Each workgroup of the out-row pass
 // leaves its applied counts in its own pair of slots of ApplyBufs::part,
 // folded once afterwards: tens of thousands of atomics on one address
