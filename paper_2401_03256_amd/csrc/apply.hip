@@ -1054,7 +1054,7 @@ int apply_batch_impl(dfpr_graph *g, int64_t n_del, const int32_t *ds, const int3
     k_apply_fold<<<1, kFoldThreads, 0, s>>>(a.part, tiny_grid, small_grid, a.ctl);
     DFPR_HIP(hipGetLastError());
     DFPR_HIP(hipEventRecord(g->ev_a1, s));
-    DFPR_HIP(hipMemcpyAsync(g->ctl_host, g->ctl, sizeof(Ctl), hipMemcpyDeviceToHost, s));
+    DFPR_CHECK_RC(ctl_to_host(g));
     DFPR_HIP(hipStreamSynchronize(s));
     if (g->ctl_host->err) return set_error(DFPR_E_RANGE, "vertex id outside [0, n) in the batch");
     for (int o = 0; o < 2; o++)
@@ -1077,7 +1077,7 @@ int apply_batch_impl(dfpr_graph *g, int64_t n_del, const int32_t *ds, const int3
         k_apply_rows<true><<<dim3(kBigGrid, 1), kBlock, 0, s>>>(b, B, o);
         DFPR_HIP(hipGetLastError());
         DFPR_HIP(hipEventRecord(g->ev_a1, s));
-        DFPR_HIP(hipMemcpyAsync(g->ctl_host, g->ctl, sizeof(Ctl), hipMemcpyDeviceToHost, s));
+        DFPR_CHECK_RC(ctl_to_host(g));
         DFPR_HIP(hipStreamSynchronize(s));
         if (g->ctl_host->novf[o] != novf)
             return set_error(DFPR_E_DEVICE, "row still overflows after re-layout");

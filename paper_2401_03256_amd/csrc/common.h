@@ -200,6 +200,13 @@ int hip_fail(hipError_t e, const char *what);
         if (e_ != hipSuccess) return dfpr::hip_fail(e_, #call); \
     } while (0)
 
+// Return a library status other than DFPR_OK to the caller.
+#define DFPR_CHECK_RC(call)             \
+    do {                                \
+        const int rc_ = (call);         \
+        if (rc_ != 0) return rc_;       \
+    } while (0)
+
 // batch applier (apply.hip)
 int apply_batch_impl(dfpr_graph *g, int64_t n_del, const int32_t *ds, const int32_t *dd,
                      int64_t n_ins, const int32_t *is, const int32_t *id, int on_device,
@@ -219,5 +226,8 @@ int ranks_from_caller(const dfpr_graph *g, const double *in, int in_dev, double 
 // device helpers (rank.hip)
 int64_t apply_slab_bytes(const dfpr_graph *g);
 int launch_fill_u32(dfpr_graph *g, uint32_t *p, uint64_t len, uint32_t value);
+// Enqueue the copy of the control block to its host copy (g->ctl_host) on
+// the graph's stream; the host reads it after synchronising the stream.
+int ctl_to_host(dfpr_graph *g);
 
 }  // namespace dfpr

@@ -690,6 +690,25 @@ static void launch_initial_marking(dfpr_graph *g, const IterArgs &a, int64_t nd,
 }
 
 
+// The control block to its host copy (coherent pinned memory) by one wave.
+// A copy-engine transfer of these few hundred bytes occupies the queue for
+// ~20 us; a one-wave kernel takes a few.
+__global__ __launch_bounds__(kWave) void k_ctl_to_host(const Ctl *ctl, Ctl *host)
+{
+    static_assert(sizeof(Ctl) % 4 == 0, "the control block is copied in 4-byte words");
+    constexpr int words = (int)(sizeof(Ctl) / 4);
+    const uint32_t *src = reinterpret_cast<const uint32_t *>(ctl);
+    uint32_t *dst = reinterpret_cast<uint32_t *>(host);
+    for (int i = threadIdx.x; i < words; i += kWave) dst[i] = src[i];
+}
+
+int ctl_to_host(dfpr_graph *g)
+{
+    k_ctl_to_host<<<1, kWave, 0, g->stream>>>(g->ctl, g->ctl_host);
+    DFPR_HIP(hipGetLastError());
+    return DFPR_OK;
+}
+
 int launch_fill_u32(dfpr_graph *g, uint32_t *p, uint64_t len, uint32_t value)
 {
     k_fill_u32<<<std::min<int>(blocks_for((int64_t)len), 4096), kBlock, 0, g->stream>>>(p, len,
@@ -922,7 +941,7 @@ static int run_loop(dfpr_graph *g, const dfpr_params &p, bool df, bool f32, uint
     }
     if (fin == 1) *mirror[0] = *mirror[1];   // the final state goes to the main mirror
     if (p.max_iters <= it0) {
-        DFPR_HIP(hipMemcpyAsync(g->ctl_host, g->ctl, sizeof(Ctl), hipMemcpyDeviceToHost, g->stream));
+        DFPR_CHECK_RC(ctl_to_host(g));
         DFPR_HIP(hipStreamSynchronize(g->stream));
     }
     const Ctl &c = *g->ctl_host;
@@ -1160,7 +1179,7 @@ static int df_impl(dfpr_graph *g, const dfpr_params *pp, int64_t nd, const int32
         rc = ranks_to_caller(g, g->R[res], ranks_out, on_device);
         if (rc) return rc;
     }
-    DFPR_HIP(hipMemcpyAsync(g->ctl_host, g->ctl, sizeof(Ctl), hipMemcpyDeviceToHost, s));
+    DFPR_CHECK_RC(ctl_to_host(g));
     DFPR_HIP(hipStreamSynchronize(s));
     fill_stats(g, st, true);
     return DFPR_OK;
@@ -1217,7 +1236,7 @@ static int traverse(dfpr_graph *g, const IterArgs &a, int64_t nd, const int32_t 
         for (int j = 0; j < chunk; j++, L++)
             k_bfs_level<<<grid, kBlock, 0, s>>>(a, bfs_queues(g, L), append ? 1 : 0);
         DFPR_HIP(hipGetLastError());
-        DFPR_HIP(hipMemcpyAsync(g->ctl_host, g->ctl, sizeof(Ctl), hipMemcpyDeviceToHost, s));
+        DFPR_CHECK_RC(ctl_to_host(g));
         DFPR_HIP(hipStreamSynchronize(s));
         const Ctl &c = *g->ctl_host;
         const uint32_t next = c.qn[L % 3], nexth = c.qhn[L % 3];
@@ -1292,7 +1311,7 @@ static int dt_impl(dfpr_graph *g, const dfpr_params *pp, int64_t nd, const int32
         rc = ranks_to_caller(g, g->R[res], ranks_out, on_device);
         if (rc) return rc;
     }
-    DFPR_HIP(hipMemcpyAsync(g->ctl_host, g->ctl, sizeof(Ctl), hipMemcpyDeviceToHost, s));
+    DFPR_CHECK_RC(ctl_to_host(g));
     DFPR_HIP(hipStreamSynchronize(s));
     fill_stats(g, st, true);
     return DFPR_OK;
