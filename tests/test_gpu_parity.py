@@ -859,3 +859,32 @@ def test_degenerate_graphs_every_method(dfpr, n):
         R, s_ = call()
         assert s_.converged, name
         assert np.max(np.abs(R - Rref)) < TOL_RANK, name
+
+
+def test_mega_row_star(dfpr):
+    # a centre with 10^6 in-edges and 10^6 out-edges (bidirectional star):
+    # the whole-workgroup row path over thousands of rounds, against the
+    # closed form; then a batch at the centre, whose expansion scans its
+    # million-entry out-row, against the oracle
+    _say("star with 10^6 leaves")
+    k = 1_000_000
+    n = k + 1
+    leaves = np.arange(1, k + 1, dtype=np.int32)
+    src = np.concatenate([np.zeros(k, np.int32), leaves])
+    dst = np.concatenate([leaves, np.zeros(k, np.int32)])
+    g, o = _pair(dfpr, n, src, dst)
+    R, st = g.static(dfpr.params(tol=1e-15))
+    D = 2 * (k + 1) + 0.85 * (k - 1)
+    assert st.converged
+    # the centre's sum of 10^6 terms carries rounding up to k u sum|x|
+    # (recursive summation, Higham 4.2), sum|x| <= 1
+    assert abs(R[0] - (k + 1) / n * (2 + 0.85 * (k - 1)) / D) < k * 2.0 ** -53
+    assert np.max(np.abs(R[1:] - (k + 1) / n * 2 / D)) < 1e-14
+    Ro, _ = o.static()
+    g.set_ranks(Ro)
+    b = _batch([(0, 7)], [(5, 9)])
+    assert g.apply_batch(b) == o.apply_batch(b) == (1, 1)
+    Rd, sd = g.dynamic_frontier(b, p=dfpr.params(frontier_tol=1e-13))
+    Rdo, sdo = o.dynamic_frontier(b, Ro, frontier_tol=1e-13)
+    assert sd.converged and abs(sd.iterations - sdo.iterations) <= 1
+    assert np.max(np.abs(Rd - Rdo)) < TOL_RANK
