@@ -32,6 +32,7 @@
 
 #include "common.h"
 #include "iter.h"
+#include "serve_policy.h"
 
 namespace dfpr {
 
@@ -344,15 +345,20 @@ static int run(dfpr_server *srv, dfpr_server_stats *st)
         int admitted = 0;
         {
             double now = ms_since(t0);
-            for (size_t k = next; k < order.size(); k++) {
-                Request &q = srv->reqs[order[k]];
-                if (q.state != 0) continue;
-                if (q.arrival_ms > now) break;
+            auto view = [&](int64_t r) {
+                const Request &q = srv->reqs[r];
+                return PendingView{q.arrival_ms, q.state, q.gid, q.charge};
+            };
+            auto busy = [&](int32_t gid) { return srv->graphs[gid].busy != 0; };
+            for (size_t from = next;;) {
                 auto free_slot = std::find_if(slots.begin(), slots.end(),
                                               [](const Slot &s) { return s.req < 0; });
-                if (free_slot == slots.end()) break;
-                if (srv->graphs[q.gid].busy) continue;
-                if (srv->resident + in_flight + q.charge > srv->budget) break;
+                const int64_t pos = next_admission(order, from, now, free_slot != slots.end(), view,
+                                                   busy, srv->resident + in_flight, srv->budget);
+                if (pos < 0) break;
+                from = (size_t)pos + 1;
+                const size_t k = (size_t)pos;
+                Request &q = srv->reqs[order[k]];
                 srv->graphs[q.gid].busy = 1;
                 in_flight += q.charge;
                 peak = std::max(peak, srv->resident + in_flight);
