@@ -31,7 +31,11 @@
 
 namespace dfpr {
 
-constexpr int kTile = 2048;    // keys sorted per workgroup in LDS
+#ifndef DFPR_SORT_TILE
+#define DFPR_SORT_TILE 512
+#endif
+constexpr int kTile = DFPR_SORT_TILE;   // keys sorted per tile in LDS (a multiple of kBlock)
+static_assert(kTile % kBlock == 0, "a tile is ranked by whole workgroups");
 constexpr int kOpsLds = 1024;  // batch entries of one row per round
 constexpr int kRowLds = 4096;  // rows up to this capacity are copied to LDS
 #ifndef DFPR_BIG_GRID
