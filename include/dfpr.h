@@ -236,7 +236,9 @@ int dfpr_mark_affected(dfpr_graph *g,
                        int64_t n_ins, const int32_t *ins_src, const int32_t *ins_dst,
                        uint8_t *flags_out);
 
-/* Marks held when the last Dynamic Frontier call ended (host, n bytes). */
+/* Marks held when the last Dynamic Frontier or Dynamic Traversal call on
+ * this graph ended: flags_out[v] = 1 (host, n bytes, caller's numbering)
+ * for every vertex that call processed; all 0 before the first such call. */
 int dfpr_get_affected(const dfpr_graph *g, uint8_t *flags_out);
 
 /* Copy the resident ranks out (host or device pointer, n doubles). */
