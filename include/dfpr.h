@@ -238,7 +238,8 @@ int dfpr_mark_affected(dfpr_graph *g,
 
 /* Marks held when the last Dynamic Frontier or Dynamic Traversal call on
  * this graph ended: flags_out[v] = 1 (host, n bytes, caller's numbering)
- * for every vertex that call processed; all 0 before the first such call. */
+ * for every vertex it marked affected, those marked in its last iteration
+ * included; all 0 before the first such call. */
 int dfpr_get_affected(const dfpr_graph *g, uint8_t *flags_out);
 
 /* Copy the resident ranks out (host or device pointer, n doubles). */

@@ -158,7 +158,7 @@ struct dfpr_graph {
     uint32_t *xstamp = nullptr;       // call in which a vertex expanded
     uint32_t next_base = 1;           // stamp base of the next call
     uint32_t last_base = 0;           // stamp base and iterations of the last
-    int32_t last_iters = -1;          //   Dynamic Frontier call
+    int32_t last_iters = -1;          //   Dynamic Frontier or Traversal call
     int32_t *bins = nullptr;          // kBins appended lists of n entries (sparse mode)
     int32_t *bfs_q = nullptr;         // traversal: 3 light + 3 heavy level queues, n each
     int32_t *sched = nullptr;         // all vertices by schedule bin, sorted (dense mode)
