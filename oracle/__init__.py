@@ -22,14 +22,15 @@ _lib = None
 
 
 def build(force: bool = True) -> str:
-    """Compile ``liboracle.so`` with gcc (plain -O2, OpenMP)."""
+    """Compile ``liboracle.so`` with gcc (-O3, OpenMP; no contraction of a
+    multiply and an add into one rounding)."""
     import subprocess
 
     if not force and os.path.exists(LIB_PATH):
         return LIB_PATH
     src = os.path.join(_HERE, "dfpr_oracle.c")
     tmp = LIB_PATH + ".tmp"
-    subprocess.check_call(["gcc", "-O2", "-std=c11", "-fopenmp", "-fPIC", "-shared",
+    subprocess.check_call(["gcc", "-O3", "-ffp-contract=off", "-std=c11", "-fopenmp", "-fPIC", "-shared",
                            "-o", tmp, src, "-lm"])
     os.replace(tmp, LIB_PATH)
     return LIB_PATH
@@ -84,13 +85,15 @@ def lib():
         L.oracle_pagerank_static.argtypes = [_P, _D, _D, _I32, _P, _P]
         L.oracle_pagerank_naive_dynamic.argtypes = [_P, _D, _D, _I32, _P, _P, _P]
         L.oracle_pagerank_dynamic_frontier.argtypes = [
-            _P, _D, _D, _D, _I32, _I64, _P, _P, _I64, _P, _P, _P, _P, _P, _P, _P]
+            _P, _D, _D, _D, _I32, _I64, _P, _P, _I64, _P, _P, _P, _P, _P, _P, _P, _P]
         L.oracle_mark_initial_csr.argtypes = [_I32, _P, _P, _I64, _P, _P, _I64, _P, _P, _P]
         L.oracle_expand_csr.argtypes = [_I32, _P, _P, _P, _P, _D, _P]
         L.oracle_mark_reachable_csr.argtypes = [_I32, _P, _P, _I64, _P, _P, _I64, _P, _P, _P]
         L.oracle_pagerank_dynamic_traversal.argtypes = [
             _P, _D, _D, _I32, _I64, _P, _P, _I64, _P, _P, _P, _P, _P, _P]
         L.oracle_num_threads.argtypes = []
+        L.oracle_set_num_threads.argtypes = [ctypes.c_int]
+        L.oracle_set_num_threads.restype = None
         _lib = L
     return _lib
 
@@ -115,6 +118,12 @@ MAX_ITERS = 500     # Section 5.1.2
 
 def num_threads() -> int:
     return int(lib().oracle_num_threads())
+
+
+def set_num_threads(k: int) -> None:
+    """Threads of the oracle's parallel loops from now on (results do not
+    depend on it)."""
+    lib().oracle_set_num_threads(int(k))
 
 
 class OracleGraph:
@@ -179,21 +188,28 @@ class OracleGraph:
         return R, _stats(st)
 
     def dynamic_frontier(self, batch, prev, alpha=ALPHA, tol=TOL, frontier_tol=TOL / 1e5,
-                         max_iters=MAX_ITERS, return_flags=False):
+                         max_iters=MAX_ITERS, return_flags=False, return_changes=False):
+        """Dynamic Frontier on the current graph.  return_flags adds the
+        initial and final marks; return_changes adds, per vertex, the
+        largest rank change over the sweeps that processed it."""
         prev = np.ascontiguousarray(prev, np.float64)
         ds, dd = _i32(batch.del_src), _i32(batch.del_dst)
         is_, id_ = _i32(batch.ins_src), _i32(batch.ins_dst)
         R = np.zeros(self.n, np.float64)
         f0 = np.zeros(self.n, np.uint8)
         f1 = np.zeros(self.n, np.uint8)
+        ch = np.zeros(self.n, np.float64) if return_changes else None
         st = _Stats()
         _check(lib().oracle_pagerank_dynamic_frontier(
             self._h, alpha, tol, frontier_tol, max_iters, ds.size, _ptr(ds), _ptr(dd),
             is_.size, _ptr(is_), _ptr(id_), _ptr(prev), _ptr(R), ctypes.byref(st),
-            _ptr(f0), _ptr(f1)), "dynamic_frontier")
+            _ptr(f0), _ptr(f1), _ptr(ch)), "dynamic_frontier")
+        out = (R, _stats(st))
         if return_flags:
-            return R, _stats(st), f0, f1
-        return R, _stats(st)
+            out += (f0, f1)
+        if return_changes:
+            out += (ch,)
+        return out
 
     def mark_initial(self, batch):
         off, idx = self.csr(out=True)

@@ -41,6 +41,15 @@ int oracle_num_threads(void)
 #endif
 }
 
+void oracle_set_num_threads(int k)
+{
+#ifdef _OPENMP
+    if (k > 0) omp_set_num_threads(k);
+#else
+    (void)k;
+#endif
+}
+
 static int cmp_u64(const void *a, const void *b)
 {
     uint64_t x = *(const uint64_t *)a, y = *(const uint64_t *)b;
@@ -196,51 +205,78 @@ int oracle_apply_batch(oracle_graph *g,
     return rebuild_csr(g);
 }
 
-/* Eq. 1 for one vertex, in the order of Algorithm 1's rank loop:
- * r = (1 - alpha)/|V|, then r += alpha * R[u] / |out(u)| for u in in(v). */
-static double rank_of(const oracle_graph *g, const double *R, int32_t v,
-                      double alpha)
+/* Eq. 1 at vertex v, as printed: alpha times the sum over the
+ * in-neighbours u of R[u] / |out(u)|, plus (1 - alpha)/|V|.  The sum runs
+ * over the in-row in ascending id order. */
+static double eq1(const oracle_graph *g, const double *R, int32_t v, double alpha)
 {
-    double r = (1.0 - alpha) / (double)g->n;
+    double sum = 0.0;
     for (int64_t k = g->in_off[v]; k < g->in_off[v + 1]; k++) {
-        int32_t u = g->in_idx[k];
-        double outdeg = (double)(g->out_off[u + 1] - g->out_off[u]);
-        r += alpha * R[u] / outdeg;
+        const int32_t u = g->in_idx[k];
+        sum += R[u] / (double)(g->out_off[u + 1] - g->out_off[u]);
     }
-    return r;
+    return alpha * sum + (1.0 - alpha) / (double)g->n;
+}
+
+/* Work done by one sweep. */
+typedef struct {
+    double linf;       /* largest |new - old| over the vertices swept */
+    int64_t verts;     /* vertices swept                              */
+    int64_t edges;     /* their in-edges                              */
+} sweep_result;
+
+/* One synchronous sweep (Section 4.2): new ranks of the vertices picked by
+ * `pick` (every vertex when it is NULL) are computed from `cur` with Eq. 1
+ * and written to `out`; `cur` is not written.  `change` (nullable)
+ * receives |new - old| of each picked vertex and 0 elsewhere. */
+static sweep_result sweep(const oracle_graph *g, const uint8_t *pick, const double *cur,
+                          double *out, double *change, double alpha)
+{
+    sweep_result res = {0.0, 0, 0};
+    double linf = 0.0;
+    int64_t verts = 0, edges = 0;
+#pragma omp parallel for schedule(dynamic, 2048) reduction(max : linf) reduction(+ : verts, edges)
+    for (int32_t v = 0; v < g->n; v++) {
+        if (pick && !pick[v]) {
+            if (change) change[v] = 0.0;
+            continue;
+        }
+        const double r = eq1(g, cur, v, alpha);
+        const double d = fabs(r - cur[v]);
+        out[v] = r;
+        if (change) change[v] = d;
+        linf = d > linf ? d : linf;
+        verts += 1;
+        edges += g->in_off[v + 1] - g->in_off[v];
+    }
+    res.linf = linf;
+    res.verts = verts;
+    res.edges = edges;
+    return res;
 }
 
 /* Power iteration over all vertices from the start vector R (n entries,
- * overwritten with the result); synchronous: reads R, writes a second
- * vector, then swaps (Section 4.2). */
+ * overwritten with the result): sweeps alternate between two vectors until
+ * the L-inf change is at most tol (Section 3.1). */
 static int power_iterate(const oracle_graph *g, double alpha, double tol,
                          int32_t max_iters, double *R, oracle_stats *st)
 {
     int32_t n = g->n;
-    double *Rn = malloc((size_t)n * sizeof(double));
-    if (!Rn) return -3;
-    double *cur = R, *nxt = Rn;
+    double *other = malloc((size_t)n * sizeof(double));
+    if (!other) return -3;
+    double *cur = R, *nxt = other;
     oracle_stats s = {0};
-    for (int32_t it = 0; it < max_iters; it++) {
-        double dR = 0.0;
-        int64_t edges = 0;
-#pragma omp parallel for schedule(dynamic, 2048) reduction(max : dR) reduction(+ : edges)
-        for (int32_t v = 0; v < n; v++) {
-            double r = rank_of(g, cur, v, alpha);
-            double d = fabs(r - cur[v]);
-            nxt[v] = r;
-            if (d > dR) dR = d;
-            edges += g->in_off[v + 1] - g->in_off[v];
-        }
+    while (s.iterations < max_iters) {
+        const sweep_result w = sweep(g, NULL, cur, nxt, NULL, alpha);
         double *t = cur; cur = nxt; nxt = t;
-        s.iterations = it + 1;
-        s.final_linf = dR;
-        s.vertices_processed += n;
-        s.edges_processed += edges;
-        if (dR <= tol) { s.converged = 1; break; }
+        s.iterations += 1;
+        s.final_linf = w.linf;
+        s.vertices_processed += w.verts;
+        s.edges_processed += w.edges;
+        if (w.linf <= tol) { s.converged = 1; break; }
     }
     if (cur != R) memcpy(R, cur, (size_t)n * sizeof(double));
-    free(Rn);
+    free(other);
     s.affected_initial = s.affected_final = n;
     if (st) *st = s;
     return 0;
@@ -272,7 +308,8 @@ int oracle_pagerank_naive_dynamic(const oracle_graph *g, double alpha,
  * deleted or inserted edge (u, v), the out-neighbours of u in G^{t-1} and
  * in G^t are affected.  G^{t-1}.out(u) differs from G^t.out(u) only by the
  * batch edges leaving u (Section 3.2), so the union is G^t.out(u) plus the
- * v of each deletion. */
+ * v of each deletion.  The set of batch sources is collected first, then
+ * each source's out-row is marked once, then the deletion targets. */
 int oracle_mark_initial_csr(int32_t n, const int64_t *out_off,
                             const int32_t *out_idx,
                             int64_t n_del, const int32_t *del_src, const int32_t *del_dst,
@@ -283,12 +320,17 @@ int oracle_mark_initial_csr(int32_t n, const int64_t *out_off,
     if ((n_del && (!del_src || !del_dst)) || (n_ins && (!ins_src || !ins_dst))) return -1;
     if (!ids_ok(n, n_del, del_src, del_dst) || !ids_ok(n, n_ins, ins_src, ins_dst))
         return -2;
+    uint8_t *is_source = calloc((size_t)n, 1);
+    if (!is_source) return -3;
+    for (int64_t i = 0; i < n_del; i++) is_source[del_src[i]] = 1;
+    for (int64_t i = 0; i < n_ins; i++) is_source[ins_src[i]] = 1;
     memset(flags, 0, (size_t)n);
-    for (int64_t i = 0; i < n_del + n_ins; i++) {
-        int32_t u = i < n_del ? del_src[i] : ins_src[i - n_del];
+    for (int32_t u = 0; u < n; u++) {
+        if (!is_source[u]) continue;
         for (int64_t k = out_off[u]; k < out_off[u + 1]; k++) flags[out_idx[k]] = 1;
-        if (i < n_del) flags[del_dst[i]] = 1;
     }
+    for (int64_t i = 0; i < n_del; i++) flags[del_dst[i]] = 1;
+    free(is_source);
     return 0;
 }
 
@@ -314,82 +356,69 @@ int oracle_expand_csr(int32_t n, const int64_t *out_off, const int32_t *out_idx,
     return 0;
 }
 
-/* Algorithm 1 in the synchronous form of Section 4.2:
- *   R <- R^{t-1}; mark initial affected;
- *   repeat up to max_iters times:
- *     Delta R <- 0
- *     for each affected v: r from Eq. 1 over G^t.in(v);
- *        dr = |r - R[v]|; R'[v] = r; Delta R = max(Delta R, dr);
- *        if dr > frontier_tol: mark G^t.out(v)
- *     stop if Delta R <= tol.
- * R' starts equal to R and only affected rows are written, so after the
- * swap the unaffected rows hold their unchanged ranks.  Marks made during
- * an iteration are processed from the next iteration on; marks are never
- * cleared within one update. */
+/* Dynamic Frontier (Section 4.1, Algorithm 1) in the synchronous form of
+ * Section 4.2.  The ranks start at the previous snapshot's and the marks at
+ * the initial marking.  Each iteration sweeps the marked vertices with
+ * Eq. 1 from the current vector into the other one; a swept vertex whose
+ * rank moved by more than frontier_tol marks its out-neighbours in G^t for
+ * the next iteration (marks only grow within one update); the loop ends
+ * once the largest move of the sweep is at most tol, or after max_iters
+ * sweeps.  Between sweeps the two vectors agree on every vertex not swept,
+ * so a sweep need only write the vertices it processes. */
 int oracle_pagerank_dynamic_frontier(
     const oracle_graph *g, double alpha, double tol, double frontier_tol,
     int32_t max_iters,
     int64_t n_del, const int32_t *del_src, const int32_t *del_dst,
     int64_t n_ins, const int32_t *ins_src, const int32_t *ins_dst,
     const double *prev, double *ranks_out, oracle_stats *st,
-    uint8_t *affected_initial, uint8_t *affected_final)
+    uint8_t *affected_initial, uint8_t *affected_final, double *largest_change)
 {
     if (!g || !prev || !ranks_out || max_iters < 0) return -1;
     int32_t n = g->n;
-    uint8_t *aff = malloc((size_t)n);
-    uint8_t *nxt = malloc((size_t)n);
-    double *R = malloc((size_t)n * sizeof(double));
-    double *Rn = malloc((size_t)n * sizeof(double));
-    double *dr = malloc((size_t)n * sizeof(double));
-    if (!aff || !nxt || !R || !Rn || !dr) {
-        free(aff); free(nxt); free(R); free(Rn); free(dr);
+    uint8_t *marks = malloc((size_t)n);
+    uint8_t *grown = malloc((size_t)n);
+    double *A = malloc((size_t)n * sizeof(double));
+    double *B = malloc((size_t)n * sizeof(double));
+    double *change = malloc((size_t)n * sizeof(double));
+    if (!marks || !grown || !A || !B || !change) {
+        free(marks); free(grown); free(A); free(B); free(change);
         return -3;
     }
     int rc = oracle_mark_initial_csr(n, g->out_off, g->out_idx, n_del, del_src,
-                                     del_dst, n_ins, ins_src, ins_dst, aff);
-    if (rc) { free(aff); free(nxt); free(R); free(Rn); free(dr); return rc; }
-    memcpy(R, prev, (size_t)n * sizeof(double));
-    memcpy(Rn, prev, (size_t)n * sizeof(double));
+                                     del_dst, n_ins, ins_src, ins_dst, marks);
+    if (rc) { free(marks); free(grown); free(A); free(B); free(change); return rc; }
+    memcpy(A, prev, (size_t)n * sizeof(double));
+    memcpy(B, prev, (size_t)n * sizeof(double));
     oracle_stats s = {0};
-    for (int32_t v = 0; v < n; v++) s.affected_initial += aff[v];
-    if (affected_initial) memcpy(affected_initial, aff, (size_t)n);
+    for (int32_t v = 0; v < n; v++) s.affected_initial += marks[v];
+    if (affected_initial) memcpy(affected_initial, marks, (size_t)n);
+    if (largest_change) memset(largest_change, 0, (size_t)n * sizeof(double));
 
-    double *cur = R, *out = Rn;
-    for (int32_t it = 0; it < max_iters; it++) {
-        double dR = 0.0;
-        int64_t edges = 0, verts = 0;
-#pragma omp parallel for schedule(dynamic, 2048) reduction(max : dR) reduction(+ : edges, verts)
-        for (int32_t v = 0; v < n; v++) {
-            dr[v] = 0.0;
-            if (!aff[v]) continue;
-            double r = rank_of(g, cur, v, alpha);
-            double d = fabs(r - cur[v]);
-            out[v] = r;
-            dr[v] = d;
-            if (d > dR) dR = d;
-            verts += 1;
-            edges += g->in_off[v + 1] - g->in_off[v];
-        }
-        /* incremental marking into a separate vector */
-        oracle_expand_csr(n, g->out_off, g->out_idx, aff, dr, frontier_tol, nxt);
-        double *t = cur; cur = out; out = t;
-        /* the buffer just read becomes the next output: bring its affected
-         * rows up to date so that every unaffected row matches */
+    double *cur = A, *nxt = B;
+    while (s.iterations < max_iters) {
+        const sweep_result w = sweep(g, marks, cur, nxt, change, alpha);
+        oracle_expand_csr(n, g->out_off, g->out_idx, marks, change, frontier_tol, grown);
+        if (largest_change)
+            for (int32_t v = 0; v < n; v++)
+                if (change[v] > largest_change[v]) largest_change[v] = change[v];
+        /* the vector just read becomes the next output: copy in the swept
+         * vertices so that the two agree again everywhere */
 #pragma omp parallel for schedule(static)
         for (int32_t v = 0; v < n; v++)
-            if (aff[v]) out[v] = cur[v];
-        uint8_t *tf = aff; aff = nxt; nxt = tf;
-        s.iterations = it + 1;
-        s.final_linf = dR;
-        s.vertices_processed += verts;
-        s.edges_processed += edges;
-        if (dR <= tol) { s.converged = 1; break; }
+            if (marks[v]) cur[v] = nxt[v];
+        double *t = cur; cur = nxt; nxt = t;
+        uint8_t *tm = marks; marks = grown; grown = tm;
+        s.iterations += 1;
+        s.final_linf = w.linf;
+        s.vertices_processed += w.verts;
+        s.edges_processed += w.edges;
+        if (w.linf <= tol) { s.converged = 1; break; }
     }
     memcpy(ranks_out, cur, (size_t)n * sizeof(double));
-    for (int32_t v = 0; v < n; v++) s.affected_final += aff[v];
-    if (affected_final) memcpy(affected_final, aff, (size_t)n);
+    for (int32_t v = 0; v < n; v++) s.affected_final += marks[v];
+    if (affected_final) memcpy(affected_final, marks, (size_t)n);
     if (st) *st = s;
-    free(aff); free(nxt); free(R); free(Rn); free(dr);
+    free(marks); free(grown); free(A); free(B); free(change);
     return 0;
 }
 
@@ -474,26 +503,17 @@ int oracle_pagerank_dynamic_traversal(
     for (int32_t v = 0; v < n; v++) s.affected_initial += aff[v];
     s.affected_final = s.affected_initial;
     if (affected) memcpy(affected, aff, (size_t)n);
-    double *cur = R, *out = Rn;
-    for (int32_t it = 0; it < max_iters; it++) {
-        double dR = 0.0;
-        int64_t edges = 0, verts = 0;
-#pragma omp parallel for schedule(dynamic, 2048) reduction(max : dR) reduction(+ : edges, verts)
-        for (int32_t v = 0; v < n; v++) {
-            if (!aff[v]) continue;
-            double r = rank_of(g, cur, v, alpha);
-            double d = fabs(r - cur[v]);
-            out[v] = r;
-            if (d > dR) dR = d;
-            verts += 1;
-            edges += g->in_off[v + 1] - g->in_off[v];
-        }
-        double *t = cur; cur = out; out = t;
-        s.iterations = it + 1;
-        s.final_linf = dR;
-        s.vertices_processed += verts;
-        s.edges_processed += edges;
-        if (dR <= tol) { s.converged = 1; break; }
+    /* the marked set never changes, so the swept vertices are the same
+     * every time and the two vectors agree on the others throughout */
+    double *cur = R, *nxt = Rn;
+    while (s.iterations < max_iters) {
+        const sweep_result w = sweep(g, aff, cur, nxt, NULL, alpha);
+        double *t = cur; cur = nxt; nxt = t;
+        s.iterations += 1;
+        s.final_linf = w.linf;
+        s.vertices_processed += w.verts;
+        s.edges_processed += w.edges;
+        if (w.linf <= tol) { s.converged = 1; break; }
     }
     memcpy(ranks_out, cur, (size_t)n * sizeof(double));
     if (st) *st = s;

@@ -87,14 +87,17 @@ int oracle_pagerank_naive_dynamic(const oracle_graph *g, double alpha,
 /* Dynamic Frontier PageRank on the updated graph G^t, given the batch that
  * produced it and the previous ranks.  affected_initial / affected_final
  * (nullable, n bytes) receive the marks after the initial marking and at
- * the end. */
+ * the end.  largest_change (nullable, n doubles) receives, per vertex, the
+ * largest |change of rank| over the sweeps that processed it (0 if none):
+ * the quantity compared with frontier_tol, so that a caller can tell which
+ * marks hinge on a comparison within rounding of the tolerance. */
 int oracle_pagerank_dynamic_frontier(
     const oracle_graph *g, double alpha, double tol, double frontier_tol,
     int32_t max_iters,
     int64_t n_del, const int32_t *del_src, const int32_t *del_dst,
     int64_t n_ins, const int32_t *ins_src, const int32_t *ins_dst,
     const double *prev, double *ranks_out, oracle_stats *st,
-    uint8_t *affected_initial, uint8_t *affected_final);
+    uint8_t *affected_initial, uint8_t *affected_final, double *largest_change);
 
 /* Initial marking on an arbitrary out-CSR (it need not hold self-loops):
  * flags[w] = 1 for every w in out(u) of each batch edge (u, v), and
@@ -131,8 +134,10 @@ int oracle_pagerank_dynamic_traversal(
     int64_t n_ins, const int32_t *ins_src, const int32_t *ins_dst,
     const double *prev, double *ranks_out, oracle_stats *st, uint8_t *affected);
 
-/* Number of OpenMP threads the oracle's parallel loops use. */
+/* Number of OpenMP threads the oracle's parallel loops use, and a way to
+ * change it (k > 0) for timing at a given thread count. */
 int oracle_num_threads(void);
+void oracle_set_num_threads(int k);
 
 #ifdef __cplusplus
 }

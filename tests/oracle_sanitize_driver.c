@@ -106,7 +106,8 @@ static int run(int32_t n, int64_t m)
 
     CHECK(oracle_mark_initial_csr(n, off, idx, nd, ds, dd, ni, is, id, f0) == 0);
     CHECK(oracle_pagerank_dynamic_frontier(g, alpha, tol, ftol, 500, nd, ds, dd, ni, is, id,
-                                           R0, R1, &st, f1, f2) == 0 && st.converged);
+                                           R0, R1, &st, f1, f2, dr) == 0 && st.converged);
+    for (int32_t v = 0; v < n; v++) CHECK(dr[v] >= 0.0 && (f2[v] || dr[v] == 0.0));
     for (int32_t v = 0; v < n; v++) CHECK(f1[v] == f0[v] && (!f1[v] || f2[v]));
     CHECK(oracle_pagerank_static(g, alpha, tol, 500, Rs, &st) == 0 && st.converged);
     CHECK(linf(R1, Rs, n) < 1e-8);
@@ -125,7 +126,7 @@ static int run(int32_t n, int64_t m)
 
     /* an empty batch: the previous ranks come back after one iteration */
     CHECK(oracle_pagerank_dynamic_frontier(g, alpha, tol, ftol, 500, 0, NULL, NULL, 0, NULL,
-                                           NULL, Rs, R1, &st, NULL, NULL) == 0);
+                                           NULL, Rs, R1, &st, NULL, NULL, NULL) == 0);
     CHECK(st.iterations == 1 && st.converged && linf(R1, Rs, n) == 0.0);
 
     oracle_free_graph(g);

@@ -259,6 +259,30 @@ def test_zero_frontier_tolerance_marks_reachable_set():
     assert st_.affected_final > st_.affected_initial
 
 
+@pytest.mark.parametrize("ftol", [1e-13, 1e-11, 0.0])
+def test_final_marks_follow_from_largest_changes(ftol):
+    # Section 4.1.1: the final marks are the initial marks plus the
+    # out-neighbours of every vertex whose rank moved by more than the
+    # frontier tolerance in some sweep that processed it; vertices never
+    # processed report no change.  Recomputed here with plain set
+    # arithmetic on the edge list.
+    n = 600
+    src, dst = synth.gnm(n, 2400, seed=17)
+    g = OracleGraph(n, src, dst)
+    R0, _ = g.static()
+    b = synth.random_batch(src, dst, n, 2, 6, seed=18)
+    g.apply_batch(b)
+    _, st_, f0, f1, ch = g.dynamic_frontier(b, R0, frontier_tol=ftol, return_flags=True,
+                                            return_changes=True)
+    assert np.all(ch >= 0.0) and np.all(ch[f1 == 0] == 0.0)
+    off, idx = g.csr(out=True)
+    expect = set(np.flatnonzero(f0).tolist())
+    for v in np.flatnonzero(ch > ftol):
+        expect |= set(idx[off[v]:off[v + 1]].tolist())
+    assert set(np.flatnonzero(f1).tolist()) == expect
+    assert st_.affected_final == len(expect)
+
+
 def test_empty_batch_returns_previous_ranks_in_one_iteration():
     n = 500
     src, dst = synth.gnm(n, 3000, seed=11)
