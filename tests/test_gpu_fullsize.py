@@ -17,6 +17,7 @@ import pytest
 
 import oracle
 from paper_2401_03256_amd import synth
+from markcheck import check_final_marks
 
 pytestmark = [pytest.mark.gpu, pytest.mark.timeout(900)]
 
@@ -57,11 +58,14 @@ def _run_sequence(dfpr, g, o, batches, tag):
         assert g.apply_batch(b) == o.apply_batch(b)
         assert np.array_equal(g.mark_affected(b), o.mark_initial(b))
         R, st = g.dynamic_frontier(b, p=p)
-        Ro, sto = o.dynamic_frontier(b, Ro, frontier_tol=FTOL)
+        Ro, sto, _, f1, ch = o.dynamic_frontier(b, Ro, frontier_tol=FTOL, return_flags=True,
+                                                return_changes=True)
         assert st.converged and sto.converged
         assert abs(st.iterations - sto.iterations) <= 1
         assert np.max(np.abs(R - Ro)) < TOL_RANK, f"batch {i}"
         assert abs(st.affected_initial - sto.affected_initial) == 0
+        check_final_marks(g.affected(), f1, ch, *o.csr(out=False), FTOL, f"{tag} batch {i}",
+                          st.iterations == sto.iterations)
     _same_csr(g, o)
     return Ro
 
@@ -86,17 +90,38 @@ def test_rmat22_static_and_dynamic_frontier(dfpr):
     assert np.max(np.abs(R - Rt)) < TOL_RANK
 
 
+# FP32 phase of the precision form against as many FP64 iterations of the
+# oracle.  A stored FP32 contribution carries a relative rounding error of
+# at most u = 2^-24 and the Kahan row sum adds at most 2u (Kahan 1965;
+# Higham, Accuracy and Stability of Numerical Algorithms, 4.3), all terms
+# being positive.  One iteration thus moves a rank by at most 3u of itself
+# on top of the relative error of its inputs, and k iterations (plus the
+# initial rounding of the contributions) by at most (3k + 1) u of the rank.
+# In L1 the iteration contracts by alpha, so the L1 error stays below
+# (3 + 1) u / (1 - alpha).  A vertex may also be processed on one side only
+# when a rank change lies within rounding of the frontier tolerance; the
+# change such a vertex misses is of the order of that tolerance, allowed for
+# by an absolute term of 10 tau_f per vertex.
+U32 = 2.0 ** -24
+
+
+def _fp32_phase_bounds(k, alpha=0.85):
+    return (3 * k + 1) * U32, 4 * U32 / (1 - alpha)
+
+
 def test_rmat24_fp64_and_fp32_form(dfpr):
-    # one batch of 1e-4 |E|: FP64 Dynamic Frontier and the FP32 storage
-    # form (FP32 phase + FP64 refinement) from the same previous ranks, both
-    # within 1e-9 of the oracle; the FP32 phase alone within 1e-6 of as many
-    # FP64 iterations of the oracle
+    # batches of 1e-6 and 1e-4 |E|, each side from its own previous ranks:
+    # FP64 Dynamic Frontier and the FP32 storage form (FP32 phase + FP64
+    # refinement) from the same previous ranks, both within 1e-9 of the
+    # oracle; the FP32 phase alone against as many FP64 iterations of the
+    # oracle, within the rounding bounds above and the 1e-6 gate
     n, src, dst = synth.rmat(24, 16, seed=1)
     _say(f"rmat24: generated, {src.size} edges")
     g = dfpr.Graph(n, src, dst)
     o = oracle.OracleGraph(n, src, dst)
     m = o.m
-    b = synth.batch_sequence(src, dst, n, [synth.batch_counts(1e-4, m)], seed=2)[0]
+    batches = synth.batch_sequence(src, dst, n, [synth.batch_counts(f, m) for f in (1e-6, 1e-4)],
+                                   seed=2)
     del src, dst
     p64 = dfpr.params(frontier_tol=FTOL)
     p32 = dfpr.params(frontier_tol=FTOL, precision=dfpr.FP32_KAHAN)
@@ -104,27 +129,40 @@ def test_rmat24_fp64_and_fp32_form(dfpr):
     Ro, sto = o.static()
     _say(f"rmat24: static {st.iterations} it (oracle {sto.iterations})")
     assert np.max(np.abs(R0 - Ro)) < TOL_RANK
-    _say(f"rmat24: batch of {b.size} edges")
-    assert g.apply_batch(b) == o.apply_batch(b)
-    assert np.array_equal(g.mark_affected(b), o.mark_initial(b))
-    R32, s32 = g.dynamic_frontier(b, p=p32)
-    k32 = s32.iterations - s32.refine_sweeps
-    g.set_ranks(R0)
-    R32p, s32p = g.dynamic_frontier(
-        b, p=dfpr.params(frontier_tol=FTOL, precision=dfpr.FP32_KAHAN, max_iters=k32))
-    g.set_ranks(R0)
-    R64, s64 = g.dynamic_frontier(b, p=p64)
-    _say(f"rmat24: FP64 {s64.iterations} it, FP32 form {s32.iterations} it "
-         f"({s32.refine_sweeps} refinement sweeps); oracle")
-    Rd, sd = o.dynamic_frontier(b, Ro, frontier_tol=FTOL)
-    Rk, _ = o.dynamic_frontier(b, Ro, frontier_tol=FTOL, max_iters=k32)
-    assert s64.converged and s32.converged and sd.converged
-    assert abs(s64.iterations - sd.iterations) <= 1
-    assert s64.affected_initial == sd.affected_initial
-    assert np.max(np.abs(R64 - Rd)) < TOL_RANK
-    assert np.max(np.abs(R32 - Rd)) < TOL_RANK
-    assert s32p.iterations == k32 and s32p.refine_sweeps == 0
-    assert np.max(np.abs(R32p - Rk)) < 1e-6
+    for b in batches:
+        _say(f"rmat24: batch of {b.size} edges")
+        assert g.apply_batch(b) == o.apply_batch(b)
+        assert np.array_equal(g.mark_affected(b), o.mark_initial(b))
+        R32, s32 = g.dynamic_frontier(b, p=p32)
+        k32 = s32.iterations - s32.refine_sweeps
+        g.set_ranks(R0)
+        R32p, s32p = g.dynamic_frontier(
+            b, p=dfpr.params(frontier_tol=FTOL, precision=dfpr.FP32_KAHAN, max_iters=k32))
+        g.set_ranks(R0)
+        R64, s64 = g.dynamic_frontier(b, p=p64)
+        _say(f"rmat24: FP64 {s64.iterations} it, FP32 form {s32.iterations} it "
+             f"({s32.refine_sweeps} refinement sweeps); oracle")
+        Rd, sd = o.dynamic_frontier(b, Ro, frontier_tol=FTOL)
+        Rk, _ = o.dynamic_frontier(b, Ro, frontier_tol=FTOL, max_iters=k32)
+        assert s64.converged and s32.converged and sd.converged
+        assert abs(s64.iterations - sd.iterations) <= 1
+        assert s64.affected_initial == sd.affected_initial
+        err = {"fp64": R64 - Rd, "fp32 form": R32 - Rd, "fp32 phase": R32p - Rk}
+        for k_, e in err.items():
+            _say(f"rmat24 {b.size}: {k_} vs oracle: Linf {np.max(np.abs(e)):.3e}, "
+                 f"L1 {np.sum(np.abs(e)):.3e}")
+        assert np.max(np.abs(R64 - Rd)) < TOL_RANK
+        assert np.max(np.abs(R32 - Rd)) < TOL_RANK
+        assert s32p.iterations == k32 and s32p.refine_sweeps == 0
+        rel_bound, l1_bound = _fp32_phase_bounds(k32)
+        e = np.abs(R32p - Rk)
+        rel = e / Rk
+        _say(f"rmat24 {b.size}: fp32 phase ({k32} it) max rel {np.max(rel):.3e} "
+             f"(bound {rel_bound:.3e}), L1 {np.sum(e):.3e} (bound {l1_bound:.3e})")
+        assert np.max(e) < 1e-6
+        assert np.all(e <= rel_bound * Rk + 10 * FTOL)
+        assert np.sum(e) <= l1_bound
+        R0, Ro = R64, Rd
     _say("rmat24: CSRs")
     _same_csr(g, o)
 
