@@ -100,14 +100,17 @@ def gnm(n: int, m: int, seed: int):
 
 
 def rmat(scale: int, edge_factor: int = 16, a: float = 0.57, b: float = 0.19,
-         c: float = 0.19, seed: int = 1):
+         c: float = 0.19, seed: int = 1, permute: bool = False):
     """R-MAT graph with ``2**scale`` vertices and ``edge_factor * 2**scale``
     generated edges; self-loops are dropped and duplicates removed.
 
     At every one of the ``scale`` levels an edge picks the quadrant
     (src bit, dst bit) = (0,0), (0,1), (1,0), (1,1) with probabilities
-    a, b, c, d = 1 - a - b - c.  Vertex ids are not permuted, so high-degree
-    vertices sit at ids with many zero bits.
+    a, b, c, d = 1 - a - b - c.  By default vertex ids are not permuted, so
+    high-degree vertices sit at ids with many zero bits and ids that share
+    their bits share neighbourhoods.  ``permute`` relabels the vertices by a
+    seeded uniform permutation (the Graph500 convention), which removes that
+    id structure; the edge set is otherwise the same.
     """
     n = 1 << scale
     m_raw = edge_factor * n
@@ -126,6 +129,11 @@ def rmat(scale: int, edge_factor: int = 16, a: float = 0.57, b: float = 0.19,
     keys = (u[keep].astype(np.int64) << 32) | v[keep].astype(np.int64)
     del u, v, keep
     keys = np.unique(keys)
+    if permute:
+        # new label of each vertex, from a stream of its own
+        perm = rng_for(seed + (1 << 40)).permutation(n).astype(np.int64)
+        keys = (perm[keys >> 32] << 32) | perm[keys & 0xFFFFFFFF]
+        keys.sort()
     src = (keys >> 32).astype(np.int32)
     dst = (keys & 0xFFFFFFFF).astype(np.int32)
     return n, src, dst

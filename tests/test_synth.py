@@ -79,3 +79,19 @@ def test_localized_batch_stays_in_window():
     k = set(_keys(s, d, n).tolist())
     assert all(x in k for x in _keys(b.del_src, b.del_dst, n).tolist())
     assert not any(x in k for x in _keys(b.ins_src, b.ins_dst, n).tolist())
+
+
+def test_rmat_permuted_is_a_relabelling():
+    # the permuted graph is the same edge set under a bijection of the
+    # vertex ids: equal sizes and degree multisets, ids moved, still a
+    # sorted set without self-loops, and seeded
+    n, s, d = synth.rmat(11, 8, seed=5)
+    n2, s2, d2 = synth.rmat(11, 8, seed=5, permute=True)
+    assert n == n2 and s.size == s2.size
+    assert np.array_equal(np.sort(np.bincount(s, minlength=n)), np.sort(np.bincount(s2, minlength=n)))
+    assert np.array_equal(np.sort(np.bincount(d, minlength=n)), np.sort(np.bincount(d2, minlength=n)))
+    assert not np.array_equal(s, s2)
+    keys = s2.astype(np.int64) * n + d2
+    assert np.all(np.diff(keys) > 0) and np.all(s2 != d2)
+    n3, s3, d3 = synth.rmat(11, 8, seed=5, permute=True)
+    assert np.array_equal(s2, s3) and np.array_equal(d2, d3)
