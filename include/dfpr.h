@@ -66,6 +66,13 @@ extern "C" {
 #define DFPR_SYNC 0         /* separate input and output rank vectors          */
 #define DFPR_ASYNC 1        /* one rank vector updated in place                 */
 
+/* dfpr_params.frontier_tol: choose it per call (see dfpr_params) */
+#define DFPR_FTOL_ADAPTIVE (-1.0)
+
+/* iteration drivers (dfpr_params.loop) */
+#define DFPR_LOOP_LAUNCHES 0 /* one launch pair per iteration                   */
+#define DFPR_LOOP_DEVICE 1   /* small frontiers iterate inside one launch       */
+
 typedef struct dfpr_graph dfpr_graph;
 
 typedef struct {
@@ -74,7 +81,15 @@ typedef struct {
                               default 1e-10 (Section 5.1.2)                     */
     double frontier_tol;   /* frontier tolerance tau_f; a vertex whose rank
                               changes by MORE than this marks its out-
-                              neighbours; default tol/1e5 (Section 4.3)         */
+                              neighbours; default tol/1e5 (Section 4.3).  A
+                              negative value (DFPR_FTOL_ADAPTIVE) lets each
+                              Dynamic Frontier call choose tol/10^k, k = 1..5,
+                              from the mean out-degree g of the vertices its
+                              initial marking marked: k = 1 for g <= 8, 2 for
+                              g <= 16, 3 for g <= 32, 4 for g <= 64, else 5
+                              (Section 5.2.4: the suitable tau_f depends on
+                              the batch; the choice is reported in
+                              dfpr_stats.frontier_tol_used)                   */
     int32_t max_iters;     /* iteration cap; default 500 (Section 5.1.2)       */
     int32_t precision;     /* DFPR_FP64 (default) or DFPR_FP32_KAHAN           */
     int32_t mode;          /* DFPR_SYNC (default): every iteration reads the
@@ -86,7 +101,15 @@ typedef struct {
                               are not bitwise reproducible; it applies to the
                               FP64 iterations (not to the FP32 phase) and is
                               ignored by the serving calls.                    */
-    int32_t reserved;      /* 0                                                */
+    int32_t loop;          /* DFPR_LOOP_LAUNCHES (default): every iteration
+                              is its own launch pair (pull, then fold);
+                              DFPR_LOOP_DEVICE: while a Dynamic Frontier
+                              call's frontier is small, its iterations run
+                              inside one cooperative launch (Algorithm 1's
+                              loop on the device, a grid barrier between the
+                              pull and the fold).  Results are bitwise the
+                              same either way; on MI355X the launch pairs are
+                              as fast or faster at every frontier measured. */
 } dfpr_params;
 
 typedef struct {
@@ -95,7 +118,8 @@ typedef struct {
     int32_t converged;          /* 1 if the L-inf change reached <= tol;
                                    reaching max_iters is not an error         */
     int32_t refine_sweeps;      /* FP64 iterations after the FP32 phase       */
-    int32_t reserved;
+    int32_t loop_iterations;    /* iterations run inside the small-frontier
+                                   loop (see dfpr_params.loop)                */
     double final_linf;          /* L-inf change of the last iteration          */
     double ms_device;           /* device time of the call (HIP events)        */
     int64_t affected_initial;   /* vertices marked by the initial marking      */
@@ -113,6 +137,9 @@ typedef struct {
     double ms_apply;            /* device time of the last dfpr_apply_batch or
                                    dfpr_apply_batch_device on this graph (0 if
                                    none, or if it was empty); not in ms_device */
+    double frontier_tol_used;   /* frontier tolerance of a Dynamic Frontier
+                                   call (the adaptive choice, if asked for);
+                                   0 for the other methods                    */
 } dfpr_stats;
 
 /* Defaults of Section 5.1.2 and Section 4.3. */
@@ -239,7 +266,8 @@ int dfpr_mark_affected(dfpr_graph *g,
 /* Marks held when the last Dynamic Frontier or Dynamic Traversal call on
  * this graph ended: flags_out[v] = 1 (host, n bytes, caller's numbering)
  * for every vertex it marked affected, those marked in its last iteration
- * included; all 0 before the first such call. */
+ * included; all 0 before the first such call.  dfpr_mark_affected and
+ * dfpr_mark_reachable keep their marks apart and leave these unchanged. */
 int dfpr_get_affected(const dfpr_graph *g, uint8_t *flags_out);
 
 /* Copy the resident ranks out (host or device pointer, n doubles). */

@@ -86,6 +86,12 @@ struct Ctl {
     unsigned long long top[2];  //   first free slot of each index array
     unsigned long long applied[2];  // effective deletions, insertions
     uint32_t cls_moved;         //   an in-row changed its schedule bin
+    unsigned long long reach0;  // out-edges of the vertices the initial marking marked
+    double ftol_used;           // frontier tolerance of the call (the adaptive rule's
+                                // choice when the parameter asks for it)
+    uint32_t bar[2];            // arrivals at the grid barriers of the small-frontier
+                                // loop, one counter per loop phase of a call
+    uint32_t loop_fail;         // a grid barrier of that loop timed out
 };
 
 // One orientation of the graph: row r holds cnt[r] sorted ids in
@@ -156,6 +162,8 @@ struct dfpr_graph {
     int cur = 0;                      // buffer holding the resident ranks
     uint32_t *stamp = nullptr;        // iteration a vertex was marked (see rank.hip)
     uint32_t *xstamp = nullptr;       // call in which a vertex expanded
+    uint32_t *mstamp = nullptr;       // stamps of the marking-only calls (their own,
+    uint32_t *mxstamp = nullptr;      //   so those calls keep the last update's marks)
     uint32_t next_base = 1;           // stamp base of the next call
     uint32_t last_base = 0;           // stamp base and iterations of the last
     int32_t last_iters = -1;          //   Dynamic Frontier or Traversal call
@@ -184,8 +192,10 @@ struct dfpr_graph {
     dfpr::Profile prof;
     int64_t prof_base[5] = {0, 0, 0, 0, 0};   // counters already added to prof
     int32_t refine_sweeps = 0;        // FP64 iterations after the FP32 phase
+    int32_t loop_iters = 0;           // iterations the small-frontier loop ran
     int busy = 0;
     int grid = 1024;                  // iteration-kernel workgroups
+    int coop = 0;                     // the device takes cooperative launches
     uint32_t sparse_limit = 0;        // frontier size that switches to the schedule
 };
 

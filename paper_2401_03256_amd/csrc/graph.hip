@@ -272,7 +272,7 @@ void dfpr_params_default(dfpr_params *p)
     p->max_iters = 500;
     p->precision = DFPR_FP64;
     p->mode = DFPR_SYNC;
-    p->reserved = 0;
+    p->loop = DFPR_LOOP_LAUNCHES;
 }
 
 void dfpr_free_graph(dfpr_graph *g)
@@ -288,6 +288,8 @@ void dfpr_free_graph(dfpr_graph *g)
     }
     (void)hipFree(g->stamp);
     (void)hipFree(g->xstamp);
+    (void)hipFree(g->mstamp);
+    (void)hipFree(g->mxstamp);
     (void)hipFree(g->bins);
     (void)hipFree(g->bfs_q);
     (void)hipFree(g->sched);
@@ -410,6 +412,9 @@ int dfpr_load_graph(int32_t n, int64_t m, const int32_t *src, const int32_t *dst
         hipDeviceProp_t prop;
         if (hipGetDeviceProperties(&prop, 0) == hipSuccess && prop.multiProcessorCount > 0)
             g->grid = std::min(kMaxGrid, prop.multiProcessorCount * kGridPerCU);
+        int coop = 0;
+        if (hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, 0) == hipSuccess)
+            g->coop = coop ? 1 : 0;
     }
     if (!rc) {
         Ctl c0;

@@ -59,7 +59,12 @@ template <bool DF, bool F32>
 __global__ __launch_bounds__(kBlock, DFPR_ITER_WAVES_PER_SIMD) void k_iter(IterArgs a)
 {
     __shared__ IterShared sh;
+#if DFPR_HUB
+    __shared__ double hub[kHubRows];
+    iter_body<DF, F32>(a, blockIdx.x, gridDim.x, sh, hub);
+#else
     iter_body<DF, F32>(a, blockIdx.x, gridDim.x, sh);
+#endif
 }
 
 // After each iteration (one workgroup): fold the slots the iteration's
@@ -69,6 +74,123 @@ __global__ __launch_bounds__(kFinalThreads) void k_final(IterArgs a, int df, int
 {
     __shared__ FinalShared sh;
     final_body(a, df != 0, f32 != 0, sh, last != 0);
+}
+
+// ---------------------------------------------------------------------------
+// small-frontier loop
+// ---------------------------------------------------------------------------
+// While the class lists hold few rows, an iteration's two launches and their
+// kernel boundaries cost more than its rows.  k_loop runs the iterations of
+// Algorithm 1's loop inside one cooperative launch of a few workgroups
+// instead: the rows of an iteration are spread over the workgroups exactly as
+// in k_iter, a grid barrier separates the pull from the fold (workgroup 0
+// runs final_body), and a second barrier publishes the new control block.
+// The launch hands back to the host loop when the call or the FP32 phase
+// ends, when an iteration has more rows than `limit` or the call moves to
+// the full schedule, or after kLoopChunk iterations.  Every row is summed
+// as in k_iter, so the ranks do not depend on which loop ran an iteration.
+#ifndef DFPR_LOOP_GRID
+#define DFPR_LOOP_GRID 64
+#endif
+#ifndef DFPR_LOOP_ROWS
+#define DFPR_LOOP_ROWS 16384
+#endif
+constexpr int kLoopGrid = DFPR_LOOP_GRID;        // workgroups of the small-frontier loop
+constexpr uint32_t kLoopRows = DFPR_LOOP_ROWS;   // most rows of an iteration it runs
+constexpr uint32_t kSpinLimit = 1u << 22;        // polls of a grid barrier before it gives up
+
+struct LoopArgs {
+    double *R[2], *C[2];
+    float *C32[2];
+    int32_t base;       // buffer that iteration it0 reads
+    int32_t it0;        // first iteration of the phase (buffer parity)
+    int32_t it_start;   // first iteration of this launch
+    uint32_t limit;     // rows of an iteration above which the launch hands over
+    int32_t bar;        // barrier counter of the control block
+};
+
+// All workgroups of the launch meet here.  The counter only grows: the
+// k-th barrier of a launch waits for k * gridDim.x arrivals.  Releases and
+// acquires are at agent scope, so the rows, marks and lists one workgroup
+// wrote are visible to all after it.  Returns false if the others did not
+// arrive within kSpinLimit polls (every workgroup then leaves the loop).
+__device__ inline bool grid_barrier(uint32_t *count, uint32_t target, int *s_ok)
+{
+    __syncthreads();
+    if (gridDim.x == 1) return true;   // one workgroup: its barrier orders everything
+    if (threadIdx.x == 0) {
+        __hip_atomic_fetch_add(count, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        uint32_t spins = 0;
+        int ok = 1;
+        while (__hip_atomic_load(count, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
+            __builtin_amdgcn_s_sleep(1);
+            if (++spins == kSpinLimit) {
+                ok = 0;
+                break;
+            }
+        }
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        *s_ok = ok;
+    }
+    __syncthreads();
+    return *s_ok != 0;
+}
+
+template <bool F32>
+__global__ __launch_bounds__(kBlock) void k_loop(IterArgs a, LoopArgs L)
+{
+    __shared__ IterShared sh;
+    __shared__ FinalShared fsh;
+    __shared__ int s_go, s_ok;
+    Ctl *ctl = a.ctl;
+    uint32_t *bar = &ctl->bar[L.bar];
+    const uint32_t G = gridDim.x;
+    uint32_t passed = 0;
+    bool failed = false;
+    for (int k = 0; k < kLoopChunk; k++) {
+        const int i = L.it_start + k;
+        if (threadIdx.x == 0) {
+            // every workgroup reads the same state: it was written before
+            // the last barrier (or by an earlier launch)
+            uint32_t rows = 0;
+            for (int b = 0; b < kBins; b++) rows += ctl->snap[i & 1][b];
+            s_go = !(ctl->done || (F32 && ctl->phase_end) || ctl->dense || ctl->loop_fail) &&
+                   rows <= L.limit && i < a.max_iters;
+        }
+        __syncthreads();
+        if (!s_go) break;
+        const int src = L.base ^ ((i - L.it0) & 1);
+        IterArgs ai = a;
+        ai.it = i;
+        ai.Rc = L.R[src];
+        ai.Cc = L.C[src];
+        ai.Rn = L.R[src ^ 1];
+        ai.Cn = L.C[src ^ 1];
+        ai.C32c = L.C32[src];
+        ai.C32n = L.C32[src ^ 1];
+        iter_body<true, F32>(ai, blockIdx.x, G, sh);
+        if (!grid_barrier(bar, ++passed * G, &s_ok)) {
+            failed = true;
+            break;
+        }
+        if (blockIdx.x == 0) final_body(ai, true, F32, fsh, false);
+        if (!grid_barrier(bar, ++passed * G, &s_ok)) {
+            failed = true;
+            break;
+        }
+    }
+    if (failed && threadIdx.x == 0) {
+        __hip_atomic_store(&ctl->loop_fail, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_store(&ctl->done, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    if (blockIdx.x == 0) {
+        // the state for the host (workgroup 0 wrote the last fold itself)
+        __syncthreads();
+        constexpr int words = (int)(sizeof(Ctl) / 4);
+        const volatile uint32_t *src = reinterpret_cast<const volatile uint32_t *>(ctl);
+        uint32_t *dst = reinterpret_cast<uint32_t *>(a.mirror);
+        for (int w = threadIdx.x; w < words; w += kBlock) dst[w] = src[w];
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -101,14 +223,42 @@ __global__ void k_reset(Ctl *ctl)
         ctl->mk_light = ctl->mk_heavy = 0;
         ctl->reach = 0;
         for (int k = 0; k < 3; k++) ctl->qn[k] = ctl->qhn[k] = 0;
+        ctl->bar[0] = ctl->bar[1] = 0;
+        ctl->loop_fail = 0;
+        ctl->reach0 = 0;
+        ctl->ftol_used = 0.0;
     }
 }
 
 // Freeze the lists built by the marking as iteration 0's snapshot and pick
 // the walk of the first iteration.
-__global__ void k_snap(Ctl *ctl, int32_t max_iters, uint32_t sparse_limit, int dense, Ctl *mirror)
+// Adaptive frontier tolerance (the paper leaves the choice of tau_f by the
+// nature of the batch to future work, Section 5.2.4 and the Conclusion).
+// The initial marking measures how fast the frontier can grow: the mean
+// out-degree g of the vertices it marked.  Mesh-like neighbourhoods (g <= 8)
+// let the frontier creep outward over many iterations of changes far below
+// tol, so expansion stops early (tau_f = tol/10); hub-rich ones (g > 64)
+// reach most of the graph within a few iterations whatever tau_f is, so the
+// accurate tol/1e5 costs little; the steps between take tol/100 ... tol/1e4.
+// Integer comparisons only, so the choice is exact.
+__host__ __device__ inline int adaptive_ftol_exponent(unsigned long long marked,
+                                                      unsigned long long out_edges)
+{
+    if (marked == 0) return 5;
+    return out_edges <= 8 * marked ? 1 : out_edges <= 16 * marked ? 2
+         : out_edges <= 32 * marked ? 3 : out_edges <= 64 * marked ? 4 : 5;
+}
+
+__global__ void k_snap(Ctl *ctl, int32_t max_iters, uint32_t sparse_limit, int dense, Ctl *mirror,
+                       double tol, double ftol)
 {
     if (threadIdx.x == 0 && blockIdx.x == 0) {
+        if (ftol >= 0.0) {
+            ctl->ftol_used = ftol;
+        } else {
+            const double p10[6] = {1.0, 1e1, 1e2, 1e3, 1e4, 1e5};
+            ctl->ftol_used = tol / p10[adaptive_ftol_exponent(ctl->affected0, ctl->reach0)];
+        }
         unsigned long long tot = 0;
         for (int b = 0; b < kBins; b++) {
             ctl->snap[0][b] = ctl->live[b];
@@ -385,14 +535,21 @@ __global__ __launch_bounds__(kBlock) void k_mark_claim(IterArgs a, int64_t nd, c
     if (big) heavy[bh + __popcll(mh & below)] = u;
 }
 
-// Mark x (x < 0: no vertex).  Every lane of the wave calls it.
+// Mark x (x < 0: no vertex).  Every lane of the wave calls it.  Lane 0
+// counts the new marks in `mine` and, in `deg`, their out-edges.
 __device__ inline void mark_one(const IterArgs &a, int32_t x, bool append,
-                                unsigned long long &mine)
+                                unsigned long long &mine, unsigned long long &deg)
 {
     bool nw = false;
     if (x >= 0 && a.stamp[x] < a.sbase) nw = atomicMax(&a.stamp[x], a.sbase) < a.sbase;
     const unsigned long long m = __ballot(nw);
-    if (lane_id() == 0) mine += __popcll(m);
+    unsigned long long d = nw ? a.out_cnt[x] : 0u;
+#pragma unroll
+    for (int off = kWave / 2; off > 0; off >>= 1) d += __shfl_xor(d, off, kWave);
+    if (lane_id() == 0) {
+        mine += __popcll(m);
+        deg += d;
+    }
     if (append) {
         const int cls = nw ? bin_of(a.in_cnt[x]) : 0;
         append_to_bins(nw, x, cls, a.ctl, a.bins, a.n_stride);
@@ -409,21 +566,21 @@ __global__ __launch_bounds__(kBlock) void k_mark_initial(IterArgs a, int64_t nd,
                                                          const int32_t *light,
                                                          const int32_t *heavy, int dense)
 {
-    __shared__ unsigned long long s_new;
+    __shared__ unsigned long long s_new, s_deg;
     Ctl *ctl = a.ctl;
     if (ctl->err) return;
     const bool dn = dense || ctl->reach + (unsigned long long)nd > a.sparse_limit;
     const bool append = !dn;
     if (blockIdx.x == 0 && threadIdx.x == 0 && dn) ctl->dense = 1;
-    if (threadIdx.x == 0) s_new = 0;
+    if (threadIdx.x == 0) s_new = s_deg = 0;
     __syncthreads();
     const int lane = lane_id();
     const int64_t wave = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) / kWave;
     const int64_t waves = (int64_t)gridDim.x * kWavesPerBlock;
-    unsigned long long mine = 0;
+    unsigned long long mine = 0, mdeg = 0;
     for (int64_t b0 = wave * kWave; b0 < nd; b0 += waves * kWave) {
         const int64_t i = b0 + lane;
-        mark_one(a, i < nd ? dd[i] : -1, append, mine);
+        mark_one(a, i < nd ? dd[i] : -1, append, mine, mdeg);
     }
     const uint32_t nl = ctl->mk_light, nh = ctl->mk_heavy;
     for (int64_t w = wave; w < nl; w += waves) {
@@ -431,14 +588,20 @@ __global__ __launch_bounds__(kBlock) void k_mark_initial(IterArgs a, int64_t nd,
         const uint32_t ob = a.out_beg[u], oc = a.out_cnt[u];
         for (uint32_t kb = 0; kb < oc; kb += kWave) {
             const uint32_t k = kb + lane;
-            mark_one(a, k < oc ? a.out_idx[ob + k] : -1, append, mine);
+            mark_one(a, k < oc ? a.out_idx[ob + k] : -1, append, mine, mdeg);
         }
     }
     __shared__ HeavyShared hs;
-    walk_heavy(a, heavy, nh, hs, [&](int32_t x) { mark_one(a, x, append, mine); });
-    if (lane == 0 && mine) atomicAdd(&s_new, mine);
+    walk_heavy(a, heavy, nh, hs, [&](int32_t x) { mark_one(a, x, append, mine, mdeg); });
+    if (lane == 0 && mine) {
+        atomicAdd(&s_new, mine);
+        atomicAdd(&s_deg, mdeg);
+    }
     __syncthreads();
-    if (threadIdx.x == 0 && s_new) atomicAdd(&ctl->affected0, s_new);
+    if (threadIdx.x == 0 && s_new) {
+        atomicAdd(&ctl->affected0, s_new);
+        atomicAdd(&ctl->reach0, s_deg);
+    }
 }
 
 // Dynamic Traversal (Section 3.3.2): every vertex reachable from the
@@ -739,9 +902,10 @@ int check_params(const dfpr_params *p, dfpr_params &out)
     if (p) out = *p;
     else dfpr_params_default(&out);
     if (!(out.alpha >= 0.0 && out.alpha < 1.0) || !(out.tol >= 0.0) ||
-        !(out.frontier_tol >= 0.0) || out.max_iters < 0 || out.max_iters > 100000 ||
+        std::isnan(out.frontier_tol) || out.max_iters < 0 || out.max_iters > 100000 ||
         (out.precision != DFPR_FP64 && out.precision != DFPR_FP32_KAHAN) ||
-        (out.mode != DFPR_SYNC && out.mode != DFPR_ASYNC))
+        (out.mode != DFPR_SYNC && out.mode != DFPR_ASYNC) ||
+        (out.loop != DFPR_LOOP_LAUNCHES && out.loop != DFPR_LOOP_DEVICE))
         return set_error(DFPR_E_ARG, "invalid parameters");
     return DFPR_OK;
 }
@@ -774,6 +938,9 @@ IterArgs iter_args(dfpr_graph *g, const dfpr_params &p, uint32_t sbase)
     a.sparse_limit = g->sparse_limit;
     a.max_iters = p.max_iters;
     a.n_stride = g->n;
+    // in the asynchronous form a copy taken at the start of a workgroup
+    // would hide the writes of the same launch
+    a.hub = p.mode == DFPR_ASYNC ? 0u : kHubRows;
     return a;
 }
 
@@ -798,8 +965,11 @@ static int take_base(dfpr_graph *g, int32_t max_iters, uint32_t *base)
     if ((uint64_t)g->next_base + span >= 0xF0000000ull) {
         int rc = launch_fill_u32(g, g->stamp, (uint64_t)g->n, 0);
         if (!rc) rc = launch_fill_u32(g, g->xstamp, (uint64_t)g->n, 0);
+        if (!rc && g->mstamp) rc = launch_fill_u32(g, g->mstamp, (uint64_t)g->n, 0);
+        if (!rc && g->mxstamp) rc = launch_fill_u32(g, g->mxstamp, (uint64_t)g->n, 0);
         if (rc) return rc;
         g->next_base = 1;
+        g->last_iters = -1;           // the last update's marks are gone
     }
     *base = g->next_base;
     g->next_base += (uint32_t)span;
@@ -832,8 +1002,33 @@ static uint32_t sparse_grid(const dfpr_graph *g, const Ctl &c)
     return (uint32_t)std::min<uint64_t>(g->grid, std::max<uint64_t>(lo, need * 4 + 64));
 }
 
+// One launch of the small-frontier loop from iteration it0 on buffer
+// `base`, on the graph's stream; the host reads its final state from
+// g->ctl_host after the stream has passed evc[0].
+static int launch_small_loop(dfpr_graph *g, IterArgs a, bool f32, int it0, int base, int slot)
+{
+    LoopArgs L{};
+    for (int b = 0; b < 2; b++) {
+        L.R[b] = g->R[b];
+        L.C[b] = g->C[b];
+        L.C32[b] = g->C32[b];
+    }
+    L.base = base;
+    L.it0 = it0;
+    L.it_start = it0;
+    L.limit = kLoopRows;
+    L.bar = slot;
+    a.mirror = g->ctl_host;
+    void *args[] = {&a, &L};
+    const void *fn = f32 ? reinterpret_cast<const void *>(&k_loop<true>)
+                         : reinterpret_cast<const void *>(&k_loop<false>);
+    DFPR_HIP(hipLaunchCooperativeKernel(fn, dim3(kLoopGrid), dim3(kBlock), args, 0, g->stream));
+    DFPR_HIP(hipEventRecord(g->evc[0], g->stream));
+    return DFPR_OK;
+}
+
 static int run_loop(dfpr_graph *g, const dfpr_params &p, bool df, bool f32, uint32_t sbase,
-                    int it0, int base, int *res_buf)
+                    int it0, int base, int *res_buf, int small_slot = -1)
 {
     IterArgs a = iter_args(g, p, sbase);
     const bool async = p.mode == DFPR_ASYNC && !f32;
@@ -855,6 +1050,26 @@ static int run_loop(dfpr_graph *g, const dfpr_params &p, bool df, bool f32, uint
     double prev_dr = -1.0;
     int prev_it = it0;
     *res_buf = base;
+    // Dynamic Frontier on the class lists, if asked for: the first
+    // iterations, while the frontier is small, run inside one launch of the
+    // small-frontier loop
+    if (df && !async && small_slot >= 0 && g->coop && p.loop == DFPR_LOOP_DEVICE &&
+        p.max_iters > it0) {
+        DFPR_CHECK_RC(launch_small_loop(g, a, f32, it0, base, small_slot));
+        DFPR_HIP(hipEventSynchronize(g->evc[0]));
+        const Ctl &st = *g->ctl_host;
+        if (st.loop_fail) return set_error(DFPR_E_DEVICE, "small-frontier loop: grid barrier timed out");
+        next_it = std::max(it0, (int)st.iterations);
+        g->loop_iters += next_it - it0;
+        // its work is not part of the iteration kernel's profile
+        g->prof_base[0] = (int64_t)st.verts;
+        g->prof_base[1] = (int64_t)st.edges;
+        g->prof_base[2] = (int64_t)st.xverts;
+        g->prof_base[3] = (int64_t)st.xedges;
+        g->prof_base[4] = (int64_t)st.marked;
+        if (st.done || (f32 && st.phase_end)) stop = true;
+        else if (!st.dense) gsz = sparse_grid(g, st);
+    }
     auto launch = [&](int k) -> int {
         const int slot = nchunks & 1;
         a.mirror = mirror[slot];
@@ -983,7 +1198,8 @@ static void fill_stats(dfpr_graph *g, dfpr_stats *st, bool df)
     st->iterations = c.iterations;
     st->converged = c.converged;
     st->refine_sweeps = g->refine_sweeps;
-    st->reserved = 0;
+    st->loop_iterations = g->loop_iters;
+    st->frontier_tol_used = df ? c.ftol_used : 0.0;
     st->final_linf = c.final_linf;
     float ms = 0.f, ms0 = 0.f, ms1 = 0.f;
     (void)hipEventElapsedTime(&ms, g->ev0, g->ev1);
@@ -1025,10 +1241,12 @@ static int full_sweeps(dfpr_graph *g, const dfpr_params *pp, const double *prev,
     rc = ensure_schedule(g);
     if (rc) return rc;
     k_reset<<<1, 1, 0, s>>>(g->ctl);
-    k_snap<<<1, 1, 0, s>>>(g->ctl, p.max_iters, g->sparse_limit, 1, g->ctl_host);
+    k_snap<<<1, 1, 0, s>>>(g->ctl, p.max_iters, g->sparse_limit, 1, g->ctl_host, p.tol,
+                           p.frontier_tol);
     DFPR_HIP(hipGetLastError());
     int res = cur;
     g->refine_sweeps = 0;
+    g->loop_iters = 0;
     std::memset(g->prof_base, 0, sizeof(g->prof_base));
     DFPR_HIP(hipEventRecord(g->ev_mid, s));
     rc = run_loop(g, p, false, false, 0, 0, cur, &res);
@@ -1077,11 +1295,13 @@ int df_begin(dfpr_graph *g, const dfpr_params &p, int64_t nd, const int32_t *bds
         k_validate<<<blocks_for(nd + ni), kBlock, 0, s>>>(n, nd, bds, bdd, ni, bis, bid, g->ctl);
         launch_initial_marking(g, a, nd, bds, bdd, ni, bis, dense);
     }
-    k_snap<<<1, 1, 0, s>>>(g->ctl, p.max_iters, g->sparse_limit, dense, g->ctl_host);
+    k_snap<<<1, 1, 0, s>>>(g->ctl, p.max_iters, g->sparse_limit, dense, g->ctl_host, p.tol,
+                           p.frontier_tol);
     if (p.precision == DFPR_FP32_KAHAN)
         k_c32_init<<<blocks_for(n), kBlock, 0, s>>>(n, g->C[cur], g->C32[0], g->C32[1]);
     DFPR_HIP(hipGetLastError());
     g->refine_sweeps = 0;
+    g->loop_iters = 0;
     std::memset(g->prof_base, 0, sizeof(g->prof_base));
     *sbase_out = sbase;
     return DFPR_OK;
@@ -1153,7 +1373,7 @@ static int df_impl(dfpr_graph *g, const dfpr_params *pp, int64_t nd, const int32
     int res = cur;
     if (p.precision == DFPR_FP32_KAHAN) {
         // FP32 phase on FP32 copies of the contributions
-        rc = run_loop(g, p, true, true, sbase, 0, cur, &res);
+        rc = run_loop(g, p, true, true, sbase, 0, cur, &res, 0);
         if (rc) return rc;
         if (g->ctl_host->err)
             return set_error(DFPR_E_RANGE, "vertex id outside [0, n) in the batch");
@@ -1162,12 +1382,12 @@ static int df_impl(dfpr_graph *g, const dfpr_params *pp, int64_t nd, const int32
         if (rc) return rc;
         if (!done) {
             const int it0 = g->ctl_host->iterations;
-            rc = run_loop(g, p, true, false, sbase, it0, res, &res);
+            rc = run_loop(g, p, true, false, sbase, it0, res, &res, 1);
             if (rc) return rc;
             g->refine_sweeps = g->ctl_host->iterations - it0;
         }
     } else {
-        rc = run_loop(g, p, true, false, sbase, 0, cur, &res);
+        rc = run_loop(g, p, true, false, sbase, 0, cur, &res, 0);
         if (rc) return rc;
     }
     const int32_t iters = g->ctl_host->iterations;
@@ -1294,9 +1514,11 @@ static int dt_impl(dfpr_graph *g, const dfpr_params *pp, int64_t nd, const int32
     }
     // the reachable set is usually most of the graph: the iterations walk
     // the full schedule and read the stamps, no class lists are built
-    k_snap<<<1, 1, 0, s>>>(g->ctl, p.max_iters, g->sparse_limit, 1, g->ctl_host);
+    k_snap<<<1, 1, 0, s>>>(g->ctl, p.max_iters, g->sparse_limit, 1, g->ctl_host, p.tol,
+                           p.frontier_tol);
     DFPR_HIP(hipGetLastError());
     g->refine_sweeps = 0;
+    g->loop_iters = 0;
     std::memset(g->prof_base, 0, sizeof(g->prof_base));
     DFPR_HIP(hipEventRecord(g->ev_mid, s));
     int res = cur;
@@ -1314,6 +1536,25 @@ static int dt_impl(dfpr_graph *g, const dfpr_params *pp, int64_t nd, const int32
     DFPR_CHECK_RC(ctl_to_host(g));
     DFPR_HIP(hipStreamSynchronize(s));
     fill_stats(g, st, true);
+    return DFPR_OK;
+}
+
+// Stamp arrays of the marking-only calls (dfpr_mark_affected,
+// dfpr_mark_reachable), allocated on first use.  Keeping them apart from
+// the iterations' stamps leaves the marks of the last update readable.
+static int marking_stamps(dfpr_graph *g)
+{
+    if (g->mstamp) return DFPR_OK;
+    const size_t bytes = (size_t)g->n * sizeof(uint32_t);
+    DFPR_HIP(hipMalloc(&g->mstamp, bytes));
+    hipError_t e = hipMalloc(&g->mxstamp, bytes);
+    if (e != hipSuccess) {
+        (void)hipFree(g->mstamp);
+        g->mstamp = nullptr;
+        return hip_fail(e, "hipMalloc(marking stamps)");
+    }
+    DFPR_CHECK_RC(launch_fill_u32(g, g->mstamp, (uint64_t)g->n, 0));
+    DFPR_CHECK_RC(launch_fill_u32(g, g->mxstamp, (uint64_t)g->n, 0));
     return DFPR_OK;
 }
 
@@ -1405,9 +1646,12 @@ int dfpr_mark_reachable(dfpr_graph *g, int64_t n_del, const int32_t *del_src,
     dfpr_params p;
     dfpr_params_default(&p);
     uint32_t sbase = 0;
+    if (!rc) rc = marking_stamps(g);
     if (!rc) rc = take_base(g, 0, &sbase);
     if (rc) return rc;
     IterArgs a = iter_args(g, p, sbase);
+    a.stamp = g->mstamp;
+    a.xstamp = g->mxstamp;
     k_reset<<<1, 1, 0, s>>>(g->ctl);
     DFPR_HIP(hipGetLastError());
     if (n_del + n_ins > 0) {
@@ -1415,7 +1659,7 @@ int dfpr_mark_reachable(dfpr_graph *g, int64_t n_del, const int32_t *del_src,
         if (rc) return rc;
     }
     std::vector<uint32_t> st(n);
-    DFPR_HIP(hipMemcpyAsync(st.data(), g->stamp, (size_t)n * 4, hipMemcpyDeviceToHost, s));
+    DFPR_HIP(hipMemcpyAsync(st.data(), g->mstamp, (size_t)n * 4, hipMemcpyDeviceToHost, s));
     DFPR_HIP(hipStreamSynchronize(s));
     for (int32_t v = 0; v < n; v++) flags_out[v] = st[g->ext2int_h[v]] == sbase ? 1 : 0;
     return DFPR_OK;
@@ -1442,14 +1686,17 @@ int dfpr_mark_affected(dfpr_graph *g, int64_t n_del, const int32_t *del_src,
     dfpr_params p;
     dfpr_params_default(&p);
     uint32_t sbase = 0;
+    if (!rc) rc = marking_stamps(g);
     if (!rc) rc = take_base(g, 0, &sbase);
     if (rc) return rc;
     IterArgs a = iter_args(g, p, sbase);
+    a.stamp = g->mstamp;
+    a.xstamp = g->mxstamp;
     k_reset<<<1, 1, 0, s>>>(g->ctl);
     if (n_del + n_ins > 0) launch_initial_marking(g, a, n_del, bds, bdd, n_ins, bis, 1);
     DFPR_HIP(hipGetLastError());
     std::vector<uint32_t> st(n);
-    DFPR_HIP(hipMemcpyAsync(st.data(), g->stamp, (size_t)n * 4, hipMemcpyDeviceToHost, s));
+    DFPR_HIP(hipMemcpyAsync(st.data(), g->mstamp, (size_t)n * 4, hipMemcpyDeviceToHost, s));
     DFPR_HIP(hipStreamSynchronize(s));
     for (int32_t v = 0; v < n; v++) flags_out[v] = st[g->ext2int_h[v]] == sbase ? 1 : 0;
     return DFPR_OK;

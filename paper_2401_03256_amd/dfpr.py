@@ -28,6 +28,9 @@ FP64 = 0
 FP32_KAHAN = 1
 SYNC = 0
 ASYNC = 1
+LOOP_LAUNCHES = 0
+LOOP_DEVICE = 1
+FTOL_ADAPTIVE = -1.0
 
 EXPORTED = [
     "dfpr_params_default", "dfpr_load_graph", "dfpr_free_graph", "dfpr_set_stream",
@@ -52,17 +55,17 @@ class Params(ctypes.Structure):
     _fields_ = [("alpha", ctypes.c_double), ("tol", ctypes.c_double),
                 ("frontier_tol", ctypes.c_double), ("max_iters", ctypes.c_int32),
                 ("precision", ctypes.c_int32), ("mode", ctypes.c_int32),
-                ("reserved", ctypes.c_int32)]
+                ("loop", ctypes.c_int32)]
 
 
 class _Stats(ctypes.Structure):
     _fields_ = [("iterations", ctypes.c_int32), ("converged", ctypes.c_int32),
-                ("refine_sweeps", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("refine_sweeps", ctypes.c_int32), ("loop_iterations", ctypes.c_int32),
                 ("final_linf", ctypes.c_double), ("ms_device", ctypes.c_double),
                 ("affected_initial", ctypes.c_int64), ("affected_final", ctypes.c_int64),
                 ("vertices_processed", ctypes.c_int64), ("edges_processed", ctypes.c_int64),
                 ("ms_mark", ctypes.c_double), ("ms_iter", ctypes.c_double),
-                ("ms_apply", ctypes.c_double)]
+                ("ms_apply", ctypes.c_double), ("frontier_tol_used", ctypes.c_double)]
 
 
 class Profile(ctypes.Structure):
@@ -117,12 +120,14 @@ class Stats:
     ms_mark: float
     ms_iter: float
     ms_apply: float
+    loop_iterations: int = 0
+    frontier_tol_used: float = 0.0
 
 
 def _stats(s):
     return Stats(s.iterations, bool(s.converged), s.refine_sweeps, s.final_linf, s.ms_device,
                  s.affected_initial, s.affected_final, s.vertices_processed, s.edges_processed,
-                 s.ms_mark, s.ms_iter, s.ms_apply)
+                 s.ms_mark, s.ms_iter, s.ms_apply, s.loop_iterations, s.frontier_tol_used)
 
 
 _lib = None
@@ -194,7 +199,7 @@ def _i32(a):
 
 
 def params(alpha=None, tol=None, frontier_tol=None, max_iters=None, precision=None,
-           mode=None) -> Params:
+           mode=None, loop=None) -> Params:
     p = Params()
     lib().dfpr_params_default(ctypes.byref(p))
     if alpha is not None:
@@ -211,6 +216,8 @@ def params(alpha=None, tol=None, frontier_tol=None, max_iters=None, precision=No
         p.precision = precision
     if mode is not None:
         p.mode = mode
+    if loop is not None:
+        p.loop = loop
     return p
 
 

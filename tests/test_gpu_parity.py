@@ -897,3 +897,131 @@ def test_mega_row_star(dfpr):
     Rdo, sdo = o.dynamic_frontier(b, Ro, frontier_tol=1e-13)
     assert sd.converged and abs(sd.iterations - sdo.iterations) <= 1
     assert np.max(np.abs(Rd - Rdo)) < TOL_RANK
+
+
+# ---------------------------------------------------------------------------
+# small-frontier loop (Algorithm 1's loop inside one cooperative launch)
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_small_frontier_loop_matches_launch_pairs_and_oracle(dfpr, precision):
+    # a localised batch on a grid keeps the frontier small, so the call
+    # runs inside the small-frontier loop when asked to; the same call with
+    # one launch pair per iteration (the default) must give bitwise the same
+    # ranks and marks, and both must match the oracle
+    _say(f"small-frontier loop on a grid, {precision}")
+    side = 128
+    n, src, dst = synth.grid2d(side, 0.05, seed=5)
+    g, o = _pair(dfpr, n, src, dst)
+    prec = dfpr.FP64 if precision == "fp64" else dfpr.FP32_KAHAN
+    R0, _ = g.static(dfpr.params(tol=1e-13))
+    Ro, _ = o.static(tol=1e-13)
+    b = synth.localized_batch(src, dst, side, 4, 16, seed=6)
+    assert g.apply_batch(b) == o.apply_batch(b)
+    pa = dfpr.params(frontier_tol=1e-13, precision=prec, loop=dfpr.LOOP_DEVICE)
+    pl = dfpr.params(frontier_tol=1e-13, precision=prec)
+    Ra, sa = g.dynamic_frontier(b, prev=R0, p=pa)
+    fa = g.affected()
+    Rl, sl = g.dynamic_frontier(b, prev=R0, p=pl)
+    fl = g.affected()
+    assert sa.converged and sl.converged
+    _say(f"iterations {sa.iterations}, in the small loop {sa.loop_iterations}")
+    assert sa.loop_iterations > 0 and sl.loop_iterations == 0
+    assert sa.iterations == sl.iterations and sa.refine_sweeps == sl.refine_sweeps
+    assert np.array_equal(Ra, Rl) and np.array_equal(fa, fl)
+    Rd, sd, _, f1, ch = o.dynamic_frontier(b, Ro, frontier_tol=1e-13, return_flags=True,
+                                           return_changes=True)
+    assert np.max(np.abs(Ra - Rd)) < TOL_RANK
+    if precision == "fp64":
+        check_final_marks(fa, f1, ch, *o.csr(out=False), 1e-13, "small loop",
+                          sa.iterations == sd.iterations)
+
+
+def test_small_frontier_loop_hands_over_to_launches(dfpr):
+    # on R-MAT the frontier of a one-edge batch outgrows the small loop
+    # after a few iterations: the call continues with launch pairs and must
+    # still equal the all-launches call bitwise and the oracle within 1e-9
+    _say("small-frontier loop hand-over on R-MAT scale 16")
+    n, src, dst = synth.rmat(16, 16, seed=7)
+    g, o = _pair(dfpr, n, src, dst)
+    R0, _ = g.static()
+    Ro, _ = o.static()
+    b = synth.random_batch(src, dst, n, 0, 1, seed=8)
+    assert g.apply_batch(b) == o.apply_batch(b)
+    Ra, sa = g.dynamic_frontier(b, prev=R0, p=dfpr.params(loop=dfpr.LOOP_DEVICE))
+    Rl, sl = g.dynamic_frontier(b, prev=R0)
+    assert sa.converged and sl.converged
+    _say(f"iterations {sa.iterations}, in the small loop {sa.loop_iterations}")
+    assert 0 < sa.loop_iterations < sa.iterations
+    assert sa.iterations == sl.iterations and np.array_equal(Ra, Rl)
+    Rd, sd = o.dynamic_frontier(b, Ro)
+    assert np.max(np.abs(Ra - Rd)) < TOL_RANK
+    with pytest.raises(dfpr.DfprError):
+        g.dynamic_frontier(b, p=dfpr.params(loop=5))
+
+
+# ---------------------------------------------------------------------------
+# frontier tolerance on localised batches, and its adaptive choice
+# ---------------------------------------------------------------------------
+
+def _adaptive_exponent(marked, out_edges):
+    # the rule of dfpr_params.frontier_tol, from the oracle's initial marks
+    if marked == 0:
+        return 5
+    for k, t in ((1, 8), (2, 16), (3, 32), (4, 64)):
+        if out_edges <= t * marked:
+            return k
+    return 5
+
+
+@pytest.mark.parametrize("ftol", [1e-11, 1e-12, "adaptive"])
+def test_localised_grid_batch_frontier_tolerance(dfpr, ftol):
+    # tau/10 and tau/100 (the values Section 5.2.4 finds suitable for
+    # temporal graphs) and the adaptive choice, on a localised grid batch:
+    # ranks within 1e-9 of the oracle run at the same tolerance, final marks
+    # as sets; the adaptive choice equals the rule applied to the oracle's
+    # initial marks
+    _say(f"localised grid batch, frontier tolerance {ftol}")
+    side = 96
+    n, src, dst = synth.grid2d(side, 0.05, seed=12)
+    g, o = _pair(dfpr, n, src, dst)
+    R0, _ = g.static(dfpr.params(tol=1e-13))
+    Ro, _ = o.static(tol=1e-13)
+    b = synth.localized_batch(src, dst, side, 3, 12, seed=13)
+    assert g.apply_batch(b) == o.apply_batch(b)
+    p = dfpr.params(frontier_tol=dfpr.FTOL_ADAPTIVE if ftol == "adaptive" else ftol)
+    R, st = g.dynamic_frontier(b, prev=R0, p=p)
+    if ftol == "adaptive":
+        f0 = o.mark_initial(b).astype(bool)
+        off, _ = o.csr(out=True)
+        k = _adaptive_exponent(int(f0.sum()), int(np.diff(off)[f0].sum()))
+        _say(f"adaptive: marked {int(f0.sum())}, exponent {k}")
+        assert st.frontier_tol_used == 1e-10 / [1.0, 1e1, 1e2, 1e3, 1e4, 1e5][k]
+        assert k == 1                      # a grid: every out-degree is at most 6
+    else:
+        assert st.frontier_tol_used == ftol
+    Rd, sd, _, f1, ch = o.dynamic_frontier(b, Ro, frontier_tol=st.frontier_tol_used,
+                                           return_flags=True, return_changes=True)
+    assert st.converged and np.max(np.abs(R - Rd)) < TOL_RANK
+    check_final_marks(g.affected(), f1, ch, *o.csr(out=False), st.frontier_tol_used,
+                      f"grid {ftol}", st.iterations == sd.iterations)
+
+
+def test_adaptive_frontier_tolerance_on_rmat(dfpr):
+    # hub-rich neighbourhoods: the rule keeps the accurate tol/1e5
+    _say("adaptive frontier tolerance on R-MAT scale 12")
+    n, src, dst = synth.rmat(12, 16, seed=14)
+    g, o = _pair(dfpr, n, src, dst)
+    R0, _ = g.static()
+    Ro, _ = o.static()
+    b = synth.random_batch(src, dst, n, 4, 16, seed=15)
+    assert g.apply_batch(b) == o.apply_batch(b)
+    R, st = g.dynamic_frontier(b, p=dfpr.params(frontier_tol=dfpr.FTOL_ADAPTIVE))
+    f0 = o.mark_initial(b).astype(bool)
+    off, _ = o.csr(out=True)
+    k = _adaptive_exponent(int(f0.sum()), int(np.diff(off)[f0].sum()))
+    assert st.frontier_tol_used == 1e-10 / [1.0, 1e1, 1e2, 1e3, 1e4, 1e5][k]
+    Rd, sd = o.dynamic_frontier(b, Ro, frontier_tol=st.frontier_tol_used)
+    assert st.converged and np.max(np.abs(R - Rd)) < TOL_RANK
+    with pytest.raises(dfpr.DfprError):
+        g.dynamic_frontier(b, p=dfpr.params(frontier_tol=float("nan")))
