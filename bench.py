@@ -92,6 +92,13 @@ def main():
     ap.add_argument("--frontier-tol", type=float, default=1e-13)
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-comparators", action="store_true",
+                    help="skip the untimed comparator calls (for profiler runs)")
+    ap.add_argument("--headline-only", action="store_true",
+                    help="only the R-MAT scale 22 line, without the precision-form, grid "
+                         "and serving workloads that follow it by default")
+    ap.add_argument("--permute", action="store_true",
+                    help="relabel the R-MAT vertices by a seeded permutation")
     ap.add_argument("--workload", default="rmat22",
                     choices=["rmat22", "grid", "fp32", "serve", "sweep"],
                     help="rmat22: the headline line; grid: 4096x4096 grid, uniform and "
@@ -121,22 +128,39 @@ def main():
     torch.cuda.set_device(0)
     dfpr.lib()
     if args.serve or args.workload == "serve":
-        serve_bench(args, dfpr, synth)
+        print(json.dumps(serve_bench(args, dfpr, synth)), flush=True)
         return
     if args.workload == "grid":
-        grid_bench(args, dfpr, synth)
+        print(json.dumps(grid_bench(args, dfpr, synth)), flush=True)
         return
     if args.workload == "fp32":
-        fp32_bench(args, dfpr, synth)
+        print(json.dumps(fp32_bench(args, dfpr, synth)), flush=True)
         return
     if args.workload == "sweep":
         sweep_bench(args, dfpr, synth)
         return
+    out = headline_bench(args, dfpr, synth)
+    if not args.headline_only:
+        # the metric's other parts, on their own workloads (not timed into
+        # `value`): FP32 vs FP64 on R-MAT scale 24, the high-diameter grid,
+        # and the serving form
+        t = time.time()
+        out["precision_form"] = fp32_bench(args, dfpr, synth, per_size=2, oracle_check=True)
+        out["grid"] = grid_bench(args, dfpr, synth, per_kind=3, tol_sweep=False)
+        out["serving"] = serve_bench(args, dfpr, synth, nreq=min(args.serve_requests, 48))
+        log(f"side workloads: {time.time() - t:.1f}s")
+    print(json.dumps(out), flush=True)
+
+
+def headline_bench(args, dfpr, synth):
+    """R-MAT scale 22 Dynamic Frontier steps (the `value`), the kernel's
+    roofline, comparators and the CPU oracle baseline."""
+    import torch
     fracs = [float(x) for x in args.fracs.split(",")]
-    workload = f"rmat{args.scale}_ef{args.edge_factor}_df_fp64"
+    workload = f"rmat{args.scale}_ef{args.edge_factor}{'_perm' if args.permute else ''}_df_fp64"
 
     t = time.time()
-    n, src, dst = synth.rmat(args.scale, args.edge_factor, seed=1)
+    n, src, dst = synth.rmat(args.scale, args.edge_factor, seed=1, permute=args.permute)
     log(f"R-MAT scale {args.scale}: n={n} edges={src.size} ({time.time() - t:.1f}s)")
     t = time.time()
     g = dfpr.Graph(n, src, dst)
@@ -164,12 +188,19 @@ def main():
         g.apply_batch_device(*dev[i])
         return g.dynamic_frontier_device(*dev[i], p=p)
 
-    warm_ranks = []
+    # warmup steps; each is also run in the FP32 form from the same previous
+    # ranks (untimed), so that both can be compared with the oracle below
+    warm_ranks, warm32 = [], []
     for i in range(args.warmup):
+        R_prev = g.ranks()
         st = step(i)
         warm_ranks.append(g.ranks())
+        g.set_ranks(R_prev)
+        s32 = g.dynamic_frontier_device(*dev[i], p=p32)
+        warm32.append((g.ranks(), s32.refine_sweeps))
+        g.set_ranks(warm_ranks[-1])
         log(f"warmup {i}: batch {seq[i].size}, {st.iterations} it, "
-            f"affected {st.affected_final}, {st.ms_device:.2f} ms")
+            f"affected {st.affected_final}, {st.ms_device:.2f} ms; FP32 form {s32.ms_device:.2f} ms")
 
     g.profile_reset(True)
     lat, edges, per = [], 0, {}
@@ -196,7 +227,7 @@ def main():
     # Frontier, Naive-dynamic and Static on the same updated graph, the two
     # dynamic methods starting from the same previous ranks
     comparators = {"by_frac": {}}
-    for j, f in enumerate(fracs):
+    for j, f in enumerate([] if args.no_comparators else fracs):
         i = total + j
         R_prev = g.ranks()
         g.apply_batch_device(*dev[i])
@@ -266,7 +297,10 @@ def main():
 
     cpu = None
     if not args.no_cpu_baseline:
-        cpu = cpu_baseline(n, src, dst, seq, R0, warm_ranks, args, log)
+        cpu = cpu_baseline(n, src, dst, seq, R0, warm_ranks, warm32, args, log)
+    g.close()
+    del dev
+    torch.cuda.empty_cache()
 
     out = {
         "metric": METRIC, "value": round(value, 3), "unit": "GTEPS", "n_gpus": 1,
@@ -275,6 +309,7 @@ def main():
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
         "data": "synthetic",
         "config": {"workload": workload, "graph": f"R-MAT scale {args.scale}", "n": n, "m": m,
+                   "vertex_ids": "seeded permutation" if args.permute else "as generated",
                    "edge_factor": args.edge_factor, "rmat_abcd": [0.57, 0.19, 0.19, 0.05],
                    "batch_fracs": fracs, "insert_frac": 0.8, "alpha": 0.85, "tol": 1e-10,
                    "frontier_tol": args.frontier_tol, "parallelism": "single GPU"},
@@ -291,7 +326,7 @@ def main():
         "cpu_baseline": cpu,
         "comparators": comparators,
     }
-    print(json.dumps(out), flush=True)
+    return out
 
 
 def copy_bandwidth(torch, nbytes=1 << 30, reps=5):
@@ -314,42 +349,81 @@ def copy_bandwidth(torch, nbytes=1 << 30, reps=5):
     return best
 
 
-def cpu_baseline(n, src, dst, seq, R0, warm_ranks, args, log):
+def cpu_model():
+    """Host CPU model name (Linux), or the platform's processor string."""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    import platform
+    return platform.processor() or "unknown"
+
+
+def cpu_baseline(n, src, dst, seq, R0, warm_ranks, warm32, args, log):
     """The oracle (plain C, OpenMP) on the host cores, timed over marking +
     iterations (Section 5.1.5 excludes the graph update), on the first
-    batches of the same sequence until about --cpu-seconds have been spent.
-    Also reports how far the GPU's ranks for those batches are from the
-    oracle's."""
+    batches of the same sequence until about --cpu-seconds have been spent;
+    the first batch is also timed on one thread.  Also reports how far the
+    GPU's FP64 ranks and its FP32 form for those batches are from the
+    oracle's (each from the same previous ranks)."""
     import oracle
     oracle.build(force=False)
     t = time.time()
     o = oracle.OracleGraph(n, src, dst)
-    log(f"oracle loaded ({time.time() - t:.1f}s, {oracle.num_threads()} threads)")
+    cores = oracle.num_threads()
+    log(f"oracle loaded ({time.time() - t:.1f}s, {cores} threads)")
     R = R0
-    spent, edges, used, linf = 0.0, 0, 0, 0.0
+    spent, edges, used = 0.0, 0, 0
+    err64 = {"linf": 0.0, "l1": 0.0}
+    err32 = {"linf": 0.0, "l1": 0.0}
+    one = None
     for i, b in enumerate(seq[: len(warm_ranks)]):
         o.apply_batch(b)
+        if i == 0:
+            oracle.set_num_threads(1)
+            t = time.perf_counter()
+            _, st1 = o.dynamic_frontier(b, R, frontier_tol=args.frontier_tol)
+            dt1 = time.perf_counter() - t
+            oracle.set_num_threads(cores)
+            one = {"value": round(st1.edges_processed / dt1 / 1e9, 4), "unit": "GTEPS",
+                   "cores": 1, "seconds": round(dt1, 2),
+                   "sample": f"Dynamic Frontier on the first batch ({b.size} edges)"}
+            log(f"oracle batch 0 on one thread: {dt1:.2f}s")
         t = time.perf_counter()
-        R, st = o.dynamic_frontier(b, R, frontier_tol=args.frontier_tol)
+        Rn, st = o.dynamic_frontier(b, R, frontier_tol=args.frontier_tol)
         dt = time.perf_counter() - t
         spent += dt
         edges += st.edges_processed
         used += 1
-        linf = max(linf, float(np.max(np.abs(R - warm_ranks[i]))))
+        # the GPU's batch i started from its own result of batch i - 1, the
+        # oracle's from its own: the two agree to ~1e-17 at every step
+        for e, Rg in ((err64, warm_ranks[i]), (err32, warm32[i][0])):
+            d = np.abs(Rg - Rn)
+            e["linf"] = max(e["linf"], float(np.max(d)))
+            e["l1"] = max(e["l1"], float(np.sum(d)))
+        R = Rn
         log(f"oracle batch {i}: {b.size} edges, {st.iterations} it, {dt:.2f}s")
         if spent >= args.cpu_seconds:
             break
     return {"value": round(edges / spent / 1e9, 4), "unit": "GTEPS",
-            "cores": oracle.num_threads(), "kind": "oracle",
+            "cores": cores, "kind": "oracle", "cpu_model": cpu_model(),
             "sample": f"Dynamic Frontier (mark + iterate) on the first {used} batches of the "
                       f"same sequence and graph, {spent:.1f}s of CPU time",
-            "gpu_vs_oracle_linf": linf}
+            "one_thread": one,
+            "gpu_fp64_vs_oracle": err64, "gpu_fp32_form_vs_oracle": err32,
+            "batches_compared": used}
 
 
-def grid_bench(args, dfpr, synth, side=4096, kinds=("uniform", "localised"), per_kind=5):
+def grid_bench(args, dfpr, synth, side=4096, kinds=("uniform", "localised"), per_kind=5,
+               tol_sweep=True):
     """High-diameter workload: side x side grid with bidirectional
     4-neighbour edges and diagonal shortcuts for 5% of the vertices;
-    batches of 1e-5 |E|, uniform and localised to one square window."""
+    batches of 1e-5 |E|, uniform and localised to one square window.
+    tol_sweep adds fixed and adaptive frontier tolerances on one more
+    localised batch."""
     t = time.time()
     n, src, dst = synth.grid2d(side, 0.05, seed=1)
     g = dfpr.Graph(n, src, dst)
@@ -368,8 +442,8 @@ def grid_bench(args, dfpr, synth, side=4096, kinds=("uniform", "localised"), per
             g.apply_batch(b)
             _, st = g.dynamic_frontier(b, p=p, out=False)
             rows.append(st)
-            log(f"{kind}: batch {b.size}, {st.iterations} it, affected {st.affected_final}, "
-                f"{st.ms_device:.2f} ms")
+            log(f"{kind}: batch {b.size}, {st.iterations} it ({st.loop_iterations} in the "
+                f"small-frontier loop), affected {st.affected_final}, {st.ms_device:.2f} ms")
         ms = [r.ms_device for r in rows]
         # Naive-dynamic and Dynamic Traversal for the last batch, from the
         # same previous ranks as its Dynamic Frontier call
@@ -386,12 +460,22 @@ def grid_bench(args, dfpr, synth, side=4096, kinds=("uniform", "localised"), per
             "df_us_per_iteration": round(float(np.sum(ms) * 1e3 / np.sum([r.iterations for r in rows])), 1),
             "df_gteps": round(float(np.sum([r.edges_processed for r in rows]) / np.sum(ms) / 1e6), 2),
             "df_ms_last": round(rows[-1].ms_device, 3),
+            "df_loop_iterations_mean": round(float(np.mean([r.loop_iterations for r in rows])), 1),
             "naive_ms": round(st_nv.ms_device, 3), "naive_iterations": st_nv.iterations,
             "speedup_vs_naive": round(st_nv.ms_device / rows[-1].ms_device, 2),
             "dt_ms": round(st_dt.ms_device, 3), "dt_iterations": st_dt.iterations,
             "dt_affected": st_dt.affected_final,
             "speedup_vs_dt": round(st_dt.ms_device / rows[-1].ms_device, 2),
         }
+    out = {"metric": METRIC, "workload": f"grid{side}_diag5_df_fp64", "n": n, "m": m,
+           "batch": [nd, ni], "static_ms": round(st0.ms_device, 3),
+           "static_iterations": st0.iterations,
+           "static_gteps": round(st0.edges_processed / st0.ms_device / 1e6, 2), "kinds": res}
+    for kind in res:
+        res[kind]["speedup_vs_static"] = round(st0.ms_device / res[kind]["df_ms_p50"], 2)
+    if not tol_sweep:
+        g.close()
+        return out
     # frontier tolerance on localised batches (the paper leaves an adaptive
     # tau_f to future work; this compares fixed values): one more localised
     # batch, each tau_f from the same previous ranks, L1 against a reference
@@ -418,23 +502,20 @@ def grid_bench(args, dfpr, synth, side=4096, kinds=("uniform", "localised"), per
     ftol_cmp["naive_dynamic"] = {"ms": round(st.ms_device, 3), "iterations": st.iterations,
                                  "l1": float(np.sum(np.abs(R - Rr)))}
     g.set_ranks(R_df_end)
-    out = {"metric": METRIC, "workload": f"grid{side}_diag5_df_fp64", "n": n, "m": m,
-           "batch": [nd, ni], "static_ms": round(st0.ms_device, 3),
-           "localised_frontier_tol": ftol_cmp,
-           "static_iterations": st0.iterations,
-           "static_gteps": round(st0.edges_processed / st0.ms_device / 1e6, 2), "kinds": res}
-    for kind in res:
-        res[kind]["speedup_vs_static"] = round(st0.ms_device / res[kind]["df_ms_p50"], 2)
-    print(json.dumps(out), flush=True)
+    out["localised_frontier_tol"] = ftol_cmp
+    g.close()
+    return out
 
 
-def fp32_bench(args, dfpr, synth, scale=24, per_size=5):
+def fp32_bench(args, dfpr, synth, scale=24, per_size=5, oracle_check=False):
     """Precision form on R-MAT scale 24: for each batch, from the same
     previous ranks, plain FP64 Dynamic Frontier, the FP32 storage form (FP32
     phase + FP64 refinement) and the FP32 phase alone (the same call capped
-    at its FP32 iterations), with max-abs and L1 differences from the FP64
-    result, which stands for the FP64 method (the FP64 path matches the
-    oracle to ~1e-17 at scale 22)."""
+    at its FP32 iterations), with max-abs and L1 differences from the GPU's
+    FP64 result.  With oracle_check, the first batch of each size is also
+    run by the FP64 oracle from the same previous ranks (and capped at the
+    FP32 phase's iterations), and all three are compared with it."""
+    import torch
     t = time.time()
     n, src, dst = synth.rmat(scale, 16, seed=1)
     log(f"R-MAT scale {scale}: n={n} edges={src.size} ({time.time() - t:.1f}s)")
@@ -443,11 +524,20 @@ def fp32_bench(args, dfpr, synth, scale=24, per_size=5):
     p64 = dfpr.params(frontier_tol=args.frontier_tol)
     p32 = dfpr.params(frontier_tol=args.frontier_tol, precision=dfpr.FP32_KAHAN)
     g.static(p64, out=False)
-    counts = [synth.batch_counts(f, m) for f in (1e-6, 1e-4) * per_size]
+    sizes = (1e-6, 1e-4)
+    counts = [synth.batch_counts(f, m) for f in sizes * per_size]
     seq = synth.batch_sequence(src, dst, n, counts, seed=2)
-    by = {}
+    o = None
+    if oracle_check:
+        import oracle
+        oracle.build(force=False)
+        t = time.time()
+        o = oracle.OracleGraph(n, src, dst)
+        log(f"oracle loaded at scale {scale} ({time.time() - t:.1f}s)")
+    del src, dst
+    by, vs_oracle = {}, {}
     for i, b in enumerate(seq):
-        f = (1e-6, 1e-4)[i % 2]
+        f = sizes[i % 2]
         R_prev = g.ranks()
         g.apply_batch(b)
         # each variant starts from the same resident ranks (set outside the
@@ -467,26 +557,44 @@ def fp32_bench(args, dfpr, synth, scale=24, per_size=5):
                "fp32_refine_sweeps": s32.refine_sweeps,
                "linf": float(np.max(np.abs(R32 - R64))), "l1": float(np.sum(np.abs(R32 - R64))),
                "linf_fp32_phase": float(np.max(np.abs(R32p - R64))),
-               "l1_fp32_phase": float(np.sum(np.abs(R32p - R64))),
-               "rel_linf_fp32_phase": float(np.max(np.abs(R32p - R64) / R64))}
+               "l1_fp32_phase": float(np.sum(np.abs(R32p - R64)))}
         by.setdefault(str(f), []).append(row)
         log(f"{f}: batch {b.size}: FP64 {s64.ms_device:.2f} ms {s64.iterations} it; FP32 form "
-            f"{s32.ms_device:.2f} ms ({s32.refine_sweeps} refine); Linf {row['linf']:.2e}, "
-            f"FP32 phase alone {row['linf_fp32_phase']:.2e}")
+            f"{s32.ms_device:.2f} ms ({s32.refine_sweeps} refine); Linf {row['linf']:.2e}")
+        if o is not None and i < len(sizes):
+            t = time.time()
+            o.apply_batch(b)
+            Rd, sd = o.dynamic_frontier(b, R_prev, frontier_tol=args.frontier_tol)
+            Rk, _ = o.dynamic_frontier(b, R_prev, frontier_tol=args.frontier_tol, max_iters=k32)
+            cmp_ = {}
+            for name, R, ref in (("fp64", R64, Rd), ("fp32_form", R32, Rd),
+                                 ("fp32_phase", R32p, Rk)):
+                d = np.abs(R - ref)
+                cmp_[name] = {"linf": float(np.max(d)), "l1": float(np.sum(d)),
+                              "max_rel": float(np.max(d / ref))}
+            cmp_["oracle_iterations"] = sd.iterations
+            cmp_["fp32_phase_iterations"] = k32
+            vs_oracle[str(f)] = cmp_
+            log(f"{f}: oracle ({time.time() - t:.1f}s): {cmp_}")
     summ = {}
     for f, rows in by.items():
         t64 = [r["fp64_ms"] for r in rows]
         t32 = [r["fp32_ms"] for r in rows]
         summ[f] = {"fp64_ms_p50": round(pct(t64, 50), 3), "fp32_form_ms_p50": round(pct(t32, 50), 3),
                    "fp32_form_updates_per_s_vs_fp64": round(sum(t64) / sum(t32), 3),
+                   "fp64_updates_per_s": round(len(t64) / (sum(t64) / 1e3), 2),
+                   "fp32_form_updates_per_s": round(len(t32) / (sum(t32) / 1e3), 2),
                    "fp32_refine_sweeps_mean": round(float(np.mean([r["fp32_refine_sweeps"] for r in rows])), 1),
                    "max_linf_vs_fp64": max(r["linf"] for r in rows),
                    "max_l1_vs_fp64": max(r["l1"] for r in rows),
                    "max_linf_fp32_phase_vs_fp64": max(r["linf_fp32_phase"] for r in rows),
-                   "max_l1_fp32_phase_vs_fp64": max(r["l1_fp32_phase"] for r in rows),
-                   "max_rel_linf_fp32_phase": max(r["rel_linf_fp32_phase"] for r in rows)}
-    print(json.dumps({"metric": METRIC, "workload": f"rmat{scale}_ef16_fp32_form_vs_fp64",
-                      "n": n, "m": m, "by_frac": summ}), flush=True)
+                   "max_l1_fp32_phase_vs_fp64": max(r["l1_fp32_phase"] for r in rows)}
+    g.close()
+    del g, o
+    torch.cuda.empty_cache()
+    return {"metric": "FP32 vs FP64 at 1e-9 L-inf", "workload": f"rmat{scale}_ef16_fp32_form_vs_fp64",
+            "n": n, "m": m, "batches_per_size": per_size, "by_frac": summ,
+            "vs_fp64_oracle": vs_oracle}
 
 
 def sweep_bench(args, dfpr, synth, scale=22):
@@ -574,7 +682,7 @@ def sweep_bench(args, dfpr, synth, scale=22):
     print(json.dumps(out), flush=True)
 
 
-def serve_bench(args, dfpr, synth):
+def serve_bench(args, dfpr, synth, nreq=None):
     """Serving form: resident R-MAT graphs of scales 16..22 (three seeds
     each), update batches of log-uniform size in [1e-7, 1e-3] |E| for a
     uniformly chosen graph, FP32 storage on one graph of every scale.
@@ -594,7 +702,7 @@ def serve_bench(args, dfpr, synth):
     log(f"generated {len(graphs)} graphs ({time.time() - t:.1f}s)")
     G = len(graphs)
     rng = synth.rng_for(7)
-    nreq = args.serve_requests
+    nreq = nreq or args.serve_requests
 
     def request_set(tag):
         gid = rng.integers(0, G, size=nreq)
@@ -706,7 +814,9 @@ def serve_bench(args, dfpr, synth):
     out["value"] = round(st0["updates_per_s"], 3)
     out["unit"] = "updates/s"
     out["higher_is_better"] = True
-    print(json.dumps(out), flush=True)
+    for g in base + mine:
+        g.close()
+    return out
 
 
 if __name__ == "__main__":
