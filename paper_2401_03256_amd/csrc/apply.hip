@@ -163,7 +163,6 @@ __global__ void k_apply_reset(Ctl *ctl)
 {
     if (threadIdx.x == 0 && blockIdx.x == 0) {
         ctl->err = 0;
-        ctl->cls_moved = 0;
         for (int o = 0; o < 2; o++) {
             ctl->ntiny[o] = ctl->nsmall[o] = ctl->nbig[o] = ctl->novf[o] = 0;
             ctl->applied[o] = 0;
@@ -389,7 +388,6 @@ __global__ __launch_bounds__(kBlock) void k_apply_tiny(ApplyArgs a, uint32_t len
         if ((mins >> lane) & 1ull)
             idx[dest + pb - __popcll(mdel & lanes_mask(lo)) + __popcll(mins & below)] = col;
         if (lane == 0) {
-            if (o == 0 && sched_bin_of(c) != sched_bin_of(nc)) ctl->cls_moved = 1;
             cnt_a[row] = nc;
             beg_a[row] = dest;
             cap_a[row] = ncap;
@@ -688,7 +686,6 @@ __global__ __launch_bounds__(kBlock) void k_apply_rows(ApplyArgs a, uint32_t len
             }
             __syncthreads();
             if (threadIdx.x == 0) {
-                if (o == 0 && sched_bin_of(c) != sched_bin_of(nc)) ctl->cls_moved = 1;
                 cnt_a[row] = nc;
                 beg_a[row] = dest;
                 cap_a[row] = s_ncap;
@@ -1086,8 +1083,6 @@ int apply_batch_impl(dfpr_graph *g, int64_t n_del, const int32_t *ds, const int3
         if (g->ctl_host->novf[o] != novf)
             return set_error(DFPR_E_DEVICE, "row still overflows after re-layout");
     }
-    // the class schedule only changes when an in-row changed class
-    if (g->ctl_host->cls_moved) g->sched_dirty = 1;
     const int64_t eff_del = (int64_t)g->ctl_host->applied[0];
     const int64_t eff_ins = (int64_t)g->ctl_host->applied[1];
     g->m += eff_ins - eff_del;

@@ -37,20 +37,14 @@ __host__ __device__ constexpr int group_of(int bin)
            : bin == 5 ? 64 : kBlock;
 }
 
-// Schedule bins (dense mode): bin 0 holds the other rows of class 0, bin 1
-// the rows whose only in-entry is the self-loop, bin b + 1 class b >= 1.  A
-// self-loop-only row changes only if its own out-degree or rank does, so it
-// is walked without its row start and length.  Bins 0 and 1 together are
-// class 0 in id order, as a sweep of every row walks them.
-constexpr int kSchedBins = kBins + 1;
-__host__ __device__ inline int sched_bin_of(uint32_t deg)
-{
-    const int b = bin_of(deg);
-    return deg <= 1 ? 1 : b == 0 ? 0 : b + 1;
-}
-
 // Device control block of a graph (zeroed at creation).
 struct Ctl {
+    // Internal ids follow decreasing in-degree at load, so each in-degree
+    // class (as the graph was loaded) is one id range: class kBins - 1 - k
+    // is [cls[k], cls[k + 1]) for k < kBins, class 0 stopping where the rows
+    // whose only in-entry was the self-loop begin, [cls[kBins], cls[kBins + 1]).
+    // A row keeps the class of its id for the life of the graph.  Set at load.
+    uint32_t cls[kBins + 2];
     uint32_t live[kBins];       // entries appended to each class list (sparse mode)
     uint32_t snap[2][kBins];    // entries iteration i processes: snap[i & 1]
     uint32_t done;              // iteration loop finished (or aborted)
@@ -85,7 +79,6 @@ struct Ctl {
     uint32_t max_cap[2];        //   largest row capacity
     unsigned long long top[2];  //   first free slot of each index array
     unsigned long long applied[2];  // effective deletions, insertions
-    uint32_t cls_moved;         //   an in-row changed its schedule bin
     unsigned long long reach0;  // out-edges of the vertices the initial marking marked
     double ftol_used;           // frontier tolerance of the call (the adaptive rule's
                                 // choice when the parameter asks for it)
@@ -169,10 +162,9 @@ struct dfpr_graph {
     int32_t last_iters = -1;          //   Dynamic Frontier or Traversal call
     int32_t *bins = nullptr;          // kBins appended lists of n entries (sparse mode)
     int32_t *bfs_q = nullptr;         // traversal: 3 light + 3 heavy level queues, n each
-    int32_t *sched = nullptr;         // all vertices by schedule bin, sorted (dense mode)
-    uint32_t *sched_off = nullptr;    // kSchedBins + 1 offsets into sched (device)
-    uint32_t *sched_tmp = nullptr;    // per-workgroup class counts for the build
-    int sched_dirty = 1;              // in-degrees changed since the build
+    // id ranges of the in-degree classes at load (host copy of Ctl::cls):
+    // the full schedule walks them in place of a list of all vertices
+    uint32_t cls[dfpr::kBins + 2] = {};
     dfpr::Ctl *ctl = nullptr;         // device
     dfpr::Ctl *ctl_host = nullptr;    // pinned, coherent mirror (written by the kernels
                                       // that end a loop step, or copied)
@@ -196,7 +188,7 @@ struct dfpr_graph {
     int busy = 0;
     int grid = 1024;                  // iteration-kernel workgroups
     int coop = 0;                     // the device takes cooperative launches
-    uint32_t sparse_limit = 0;        // frontier size that switches to the schedule
+    uint32_t sparse_limit = 0;        // frontier size that switches to the full schedule
 };
 
 namespace dfpr {

@@ -108,12 +108,26 @@ static void free_csr(Csr &c)
 // Internal numbering: decreasing in-degree counted over the input edges
 // (repeats and self-loops included, which only affects ties), ties kept in
 // the caller's order.  A counting sort by degree.
+// Internal ids by decreasing in-degree (self-loop counted once, repeated
+// input edges as given), stable in the caller's ids.  cls[] receives the id
+// ranges of the in-degree classes in that order (see Ctl::cls).
 static void renumber(int32_t n, int64_t m, const int32_t *src, const int32_t *dst,
-                     std::vector<int32_t> &ext2int, std::vector<int32_t> &int2ext)
+                     std::vector<int32_t> &ext2int, std::vector<int32_t> &int2ext,
+                     uint32_t cls[kBins + 2])
 {
     std::vector<uint32_t> deg(n, 1);
     uint32_t dmax = 1;
     for (int64_t i = 0; i < m; i++) dmax = std::max(dmax, ++deg[dst[i]]);
+    // class kBins - 1 - k starts at id cls[k]: count the rows above it
+    uint64_t above[kBins + 1] = {};
+    for (int32_t v = 0; v < n; v++) {
+        const int b = bin_of(deg[v]);
+        for (int k = 1; k < kBins; k++) above[k] += b > kBins - 1 - k ? 1 : 0;
+        above[kBins] += deg[v] > 1 ? 1 : 0;
+    }
+    cls[0] = 0;
+    for (int k = 1; k <= kBins; k++) cls[k] = (uint32_t)above[k];
+    cls[kBins + 1] = (uint32_t)n;
     std::vector<uint64_t> start(dmax + 2, 0);
     for (int32_t v = 0; v < n; v++) start[dmax - deg[v] + 1]++;
     for (uint32_t d = 0; d <= dmax; d++) start[d + 1] += start[d];
@@ -292,9 +306,6 @@ void dfpr_free_graph(dfpr_graph *g)
     (void)hipFree(g->mxstamp);
     (void)hipFree(g->bins);
     (void)hipFree(g->bfs_q);
-    (void)hipFree(g->sched);
-    (void)hipFree(g->sched_off);
-    (void)hipFree(g->sched_tmp);
     (void)hipFree(g->ctl);
     (void)hipFree(g->scratch_sum);
     (void)hipFree(g->Rx);
@@ -338,7 +349,7 @@ int dfpr_load_graph(int32_t n, int64_t m, const int32_t *src, const int32_t *dst
     dfpr_graph *g = new dfpr_graph();
     g->n = n;
     uint32_t top[2] = {0, 0};
-    renumber(n, m, src, dst, g->ext2int_h, g->int2ext_h);
+    renumber(n, m, src, dst, g->ext2int_h, g->int2ext_h, g->cls);
     {
         std::vector<int32_t> s2(m), d2(m);
         for (int64_t i = 0; i < m; i++) {
@@ -360,9 +371,6 @@ int dfpr_load_graph(int32_t n, int64_t m, const int32_t *src, const int32_t *dst
         if (!rc) rc = al((void **)&g->stamp, (size_t)n * 4);
         if (!rc) rc = al((void **)&g->xstamp, (size_t)n * 4);
         if (!rc) rc = al((void **)&g->bins, (size_t)kBins * n * 4);
-        if (!rc) rc = al((void **)&g->sched, (size_t)n * 4);
-        if (!rc) rc = al((void **)&g->sched_off, (kSchedBins + 1) * 4);
-        if (!rc) rc = al((void **)&g->sched_tmp, ((size_t)n / 4096 + 1) * kSchedBins * 4);
         if (!rc) rc = al((void **)&g->ctl, sizeof(Ctl));
         if (!rc) rc = al((void **)&g->it.dr_part, kFoldSlots * 8);
         if (!rc) rc = al((void **)&g->it.rmax_part, kFoldSlots * 8);
@@ -423,6 +431,7 @@ int dfpr_load_graph(int32_t n, int64_t m, const int32_t *src, const int32_t *dst
             c0.top[o] = top[o];
             c0.max_cap[o] = g->csr[o].max_cap;
         }
+        for (int k = 0; k < kBins + 2; k++) c0.cls[k] = g->cls[k];
         hipError_t e = hipMemcpy(g->ctl, &c0, sizeof(Ctl), hipMemcpyHostToDevice);
         if (e != hipSuccess) rc = hip_fail(e, "hipMemcpy");
         g->sparse_limit = (uint32_t)std::max<int64_t>(4096, n / 64);

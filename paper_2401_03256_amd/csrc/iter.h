@@ -69,8 +69,6 @@ struct IterArgs {
     float *C32n;                // FP32 contributions written
     uint32_t *stamp, *xstamp;
     int32_t *bins;              // class lists (sparse mode), n entries each
-    const int32_t *sched;       // class schedule of all vertices
-    const uint32_t *sched_off;  // kSchedBins + 1 offsets
     Ctl *ctl;
     Ctl *mirror;                // host-visible copy of the control block, or NULL
     double *dr_part;            // kFoldSlots slots of the L-inf of Delta r
@@ -86,6 +84,16 @@ struct IterArgs {
 };
 
 __device__ __forceinline__ int lane_id() { return __lane_id(); }
+
+// In-degree class of internal id v (its id range, Ctl::cls; the self-loop
+// rows are in class 0).
+__device__ __forceinline__ int class_of_id(const IterArgs &a, int32_t v)
+{
+    int c = kBins - 1;
+#pragma unroll
+    for (int k = 1; k < kBins; k++) c -= (uint32_t)v >= a.ctl->cls[k] ? 1 : 0;
+    return c;
+}
 
 struct Acc {
     double dr_max = 0.0;
@@ -193,7 +201,7 @@ __device__ __forceinline__ void mark_out_row(const IterArgs &a, int32_t w, uint3
                 else a.stamp[x[j]] = sv;
             }
             if (SPARSE) {
-                const int cls = nw ? bin_of(a.in_cnt[x[j]]) : 0;
+                const int cls = nw ? class_of_id(a, x[j]) : 0;
                 append_to_bins(nw, x[j], cls, a.ctl, a.bins, a.n_stride);
             }
         }
@@ -238,7 +246,7 @@ __device__ __forceinline__ void expand_rows(const IterArgs &a, uint32_t incl, ui
             else a.stamp[x] = sv;
         }
         if (SPARSE) {
-            const int cls = nw ? bin_of(a.in_cnt[x]) : 0;
+            const int cls = nw ? class_of_id(a, x) : 0;
             append_to_bins(nw, x, cls, a.ctl, a.bins, a.n_stride);
         }
     }
@@ -267,12 +275,15 @@ __device__ __forceinline__ bool finish_row(const IterArgs &a, int32_t v, uint32_
     return false;
 }
 
-// One wave unit: 64/G rows of a class list, G lanes per row.  LOOP (G = 1):
-// rows whose only in-entry is the self-loop, so the sum is the row's own
-// contribution and its start and length are not read.
+// One wave unit: 64/G rows of a class list (`list`), or of the id range
+// starting at `id0` when `list` is NULL, G lanes per row.  LOOP (G = 1): the
+// id range of rows whose only in-entry was the self-loop at load; few of
+// them are marked, so their stamp is read first, and a row that has since
+// gained in-edges is summed like any class-0 row.
 template <int G, bool DF, bool F32, bool LOOP = false>
 __device__ __forceinline__ void wave_unit(const IterArgs &a, const Hub &hub, const int32_t *list,
-                                 uint32_t count, uint32_t first, bool check, bool sparse, Acc &acc)
+                                          uint32_t id0, uint32_t count, uint32_t first,
+                                          bool check, bool sparse, Acc &acc)
 {
     const int lane = lane_id();
     const int sub = lane & (G - 1);
@@ -282,16 +293,16 @@ __device__ __forceinline__ void wave_unit(const IterArgs &a, const Hub &hub, con
     uint32_t beg = 0, cnt = 0, oc = 1;
     double rc = 0.0;
     if (pos < count) {
-        v = list[pos];
+        v = list ? list[pos] : (int32_t)(id0 + pos);
         active = true;
         if (LOOP) {
-            // few of these rows are marked: the stamp decides first
-            cnt = 1;
             if (DF && check) {
                 const uint32_t st = a.stamp[v];
                 active = st >= a.sbase && st <= a.sbase + (uint32_t)a.it;
             }
             if (active) {
+                cnt = a.in_cnt[v];
+                beg = a.in_beg[v];
                 rc = a.Rc[v];
                 oc = a.out_cnt[v];
             }
@@ -318,6 +329,21 @@ __device__ __forceinline__ void wave_unit(const IterArgs &a, const Hub &hub, con
         if (cnt == 1) {
             // the self-loop is the only in-edge
             if (sub == 0) s = F32 ? (double)a.C32c[v] : a.Cc[v];
+        } else if (LOOP) {
+            // a self-loop row that has gained in-edges since the load: rare,
+            // summed in index order by its lane (as gather_sum with G = 1)
+            if (F32) {
+                float ks = 0.0f, kc = 0.0f;
+                for (uint32_t k = 0; k < cnt; k++) {
+                    const float y = a.C32c[load_idx(a.in_idx + beg + k)] - kc;
+                    const float t = ks + y;
+                    kc = (t - ks) - y;
+                    ks = t;
+                }
+                s = (double)ks - (double)kc;
+            } else {
+                for (uint32_t k = 0; k < cnt; k++) s += a.Cc[load_idx(a.in_idx + beg + k)];
+            }
         } else {
             s = gather_sum<F32>(a, hub, a.in_idx + beg, sub, G, cnt);
         }
@@ -434,9 +460,10 @@ __device__ __forceinline__ void block_fold(double &dr, double &rm, unsigned long
 struct Plan {
     double ftol;                // frontier tolerance in effect
     uint32_t cnt[kBins];
-    const int32_t *list[kBins];
-    uint32_t loop_cnt;
-    const int32_t *loop_list;
+    const int32_t *list[kBins]; // class lists (sparse), or NULL: the id range from id0
+    uint32_t id0[kBins];
+    uint32_t loop_cnt;          // the self-loop rows' id range (full schedule, DF)
+    uint32_t loop_id0;
     uint32_t ustart[kBins];     // k < kBins - 1: class kBins - 2 - k; kBins - 1: loop rows
     uint32_t nwu, nbu;
 };
@@ -450,18 +477,19 @@ __device__ __forceinline__ void make_plan(const IterArgs &a, const Ctl *ctl, boo
         if (sparse) {
             p.cnt[b] = ctl->snap[par][b];
             p.list[b] = a.bins + (size_t)b * a.n_stride;
+            p.id0[b] = 0;
         } else {
-            // schedule bin 0: class 0 without the self-loop-only rows;
-            // bin b + 1: class b >= 1
-            const int sb = b == 0 ? 0 : b + 1;
-            p.cnt[b] = a.sched_off[sb + 1] - a.sched_off[sb];
-            p.list[b] = a.sched + a.sched_off[sb];
+            // class b is the id range [cls[kBins - 1 - b], cls[kBins - b])
+            p.cnt[b] = ctl->cls[kBins - b] - ctl->cls[kBins - 1 - b];
+            p.list[b] = nullptr;
+            p.id0[b] = ctl->cls[kBins - 1 - b];
         }
     }
-    p.loop_cnt = sparse ? 0u : a.sched_off[2] - a.sched_off[1];
-    p.loop_list = a.sched + a.sched_off[1];
+    p.loop_cnt = sparse ? 0u : ctl->cls[kBins + 1] - ctl->cls[kBins];
+    p.loop_id0 = ctl->cls[kBins];
     if (!df) {
-        // every row is processed: bins 0 and 1 are one run, walked as class 0
+        // every row is processed: class 0 and the self-loop rows are one
+        // id range, walked as class 0
         p.cnt[0] += p.loop_cnt;
         p.loop_cnt = 0;
     }
@@ -547,26 +575,28 @@ __device__ __forceinline__ void iter_body(const IterArgs &a, uint32_t blk, uint3
     auto run_unit = [&](uint32_t u, int k) {
         if (k == kBins - 1) {
             const uint32_t first = (u - sh.plan.ustart[k]) * kWave;
-            wave_unit<1, DF, F32, true>(a, hub, sh.plan.loop_list, sh.plan.loop_cnt, first,
-                                        check, sparse, acc);
+            wave_unit<1, DF, F32, true>(a, hub, nullptr, sh.plan.loop_id0, sh.plan.loop_cnt,
+                                        first, check, sparse, acc);
             return;
         }
         const int b = kBins - 2 - k;
         const uint32_t first = (u - sh.plan.ustart[k]) * (kWave / group_of(b));
         const int32_t *list = sh.plan.list[b];
+        const uint32_t id0 = sh.plan.id0[b];
         const uint32_t cnt = sh.plan.cnt[b];
         switch (b) {
-        case 0: wave_unit<1, DF, F32>(a, hub, list, cnt, first, check, sparse, acc); break;
-        case 1: wave_unit<2, DF, F32>(a, hub, list, cnt, first, check, sparse, acc); break;
-        case 2: wave_unit<4, DF, F32>(a, hub, list, cnt, first, check, sparse, acc); break;
-        case 3: wave_unit<8, DF, F32>(a, hub, list, cnt, first, check, sparse, acc); break;
-        case 4: wave_unit<32, DF, F32>(a, hub, list, cnt, first, check, sparse, acc); break;
-        default: wave_unit<64, DF, F32>(a, hub, list, cnt, first, check, sparse, acc); break;
+        case 0: wave_unit<1, DF, F32>(a, hub, list, id0, cnt, first, check, sparse, acc); break;
+        case 1: wave_unit<2, DF, F32>(a, hub, list, id0, cnt, first, check, sparse, acc); break;
+        case 2: wave_unit<4, DF, F32>(a, hub, list, id0, cnt, first, check, sparse, acc); break;
+        case 3: wave_unit<8, DF, F32>(a, hub, list, id0, cnt, first, check, sparse, acc); break;
+        case 4: wave_unit<32, DF, F32>(a, hub, list, id0, cnt, first, check, sparse, acc); break;
+        default: wave_unit<64, DF, F32>(a, hub, list, id0, cnt, first, check, sparse, acc); break;
         }
     };
+    const int32_t *blist = sh.plan.list[kBins - 1];
     for (uint32_t u = blk; u < nbu; u += G)
-        block_row<DF, F32>(a, hub, sh.plan.list[kBins - 1][u], check, sparse, acc, sh.red,
-                           &sh.flag);
+        block_row<DF, F32>(a, hub, blist ? blist[u] : (int32_t)(sh.plan.id0[kBins - 1] + u), check,
+                           sparse, acc, sh.red, &sh.flag);
     for (uint32_t u = blk * kWavesPerBlock + wave; u < nwu; u += G * kWavesPerBlock) {
         int k = 0;
         while (k + 1 < kBins && u >= sh.plan.ustart[k + 1]) k++;

@@ -14,12 +14,14 @@
 //
 // Work layout.  Rows are split by in-degree into classes; a class-b row is
 // reduced by group_of(b) lanes of one wave (1, 2, 4, 8, 32 or 64 lanes) or,
-// above 1024 in-edges, by a whole workgroup.  Rows whose only in-entry is
-// the self-loop have a schedule bin of their own (sched_bin_of).  Each lane loads kUnroll
-// indices and then kUnroll contributions per round, so that many loads are
-// in flight per wave.  Each lane sums its strided share of a row in order
-// and the group folds the partial sums with a fixed butterfly, so the sum
-// of a row depends on nothing but the row and its class.
+// above 1024 in-edges, by a whole workgroup.  Internal ids follow
+// decreasing in-degree at load, so each class is an id range, and a row
+// keeps the class of its id for the life of the graph (Ctl::cls).
+// Rows whose only in-entry was the self-loop form the last range.  Each
+// lane loads kUnroll indices and then kUnroll contributions per round, so
+// that many loads are in flight per wave.  Each lane sums its strided share
+// of a row in order and the group folds the partial sums with a fixed
+// butterfly, so the sum of a row depends on nothing but the row and its id.
 //
 // Marks.  stamp[v] holds the iteration, offset by a per-call base, from
 // which v is affected: v is processed in iteration i iff
@@ -32,9 +34,10 @@
 //
 // Two ways to walk the affected rows.  While few vertices are marked, the
 // marking appends new vertices to per-class lists (sparse mode).  Once the
-// lists pass a size limit, iterations walk the whole class schedule built
-// from all vertices (sorted by id inside each class) and skip rows whose
-// stamp is out of range (dense mode); marks are then plain stores.
+// lists pass a size limit, iterations walk every class's id range and skip
+// rows whose stamp is out of range (dense mode, the "full schedule"); marks
+// are then plain stores.  Neither walk needs rebuilding when a batch
+// changes in-degrees.
 //
 // Ranks are double-buffered (synchronous form, Section 4.2).  Both buffers
 // hold identical values between calls; an iteration reads one and writes
@@ -53,7 +56,6 @@
 
 namespace dfpr {
 
-constexpr int kSchedChunk = 4096;   // vertices per workgroup in the schedule build
 
 template <bool DF, bool F32>
 __global__ __launch_bounds__(kBlock, DFPR_ITER_WAVES_PER_SIMD) void k_iter(IterArgs a)
@@ -299,121 +301,6 @@ __global__ void k_copy2(int32_t n, const double *a, double *a2, const double *b,
     }
 }
 
-// Schedule build: a stable counting sort of the vertices by schedule bin
-// (sched_bin_of: self-loop-only rows, then the in-degree classes).
-// Workgroup w owns vertices [w * kSchedChunk, (w + 1) * kSchedChunk)
-// and visits them in rounds of kBlock consecutive ids, so loads and the
-// per-class runs of stores are coalesced.
-constexpr int kScanThreads = 1024;
-
-__global__ __launch_bounds__(kBlock) void k_sched_count(int32_t n, const uint32_t *in_cnt,
-                                                        uint32_t *tmp, uint32_t nblocks)
-{
-    __shared__ uint32_t s[kWavesPerBlock][kSchedBins];
-    const int lane = lane_id(), wave = threadIdx.x / kWave;
-    uint32_t cnt[kSchedBins];
-#pragma unroll
-    for (int b = 0; b < kSchedBins; b++) cnt[b] = 0;
-    const uint32_t base = blockIdx.x * (uint32_t)kSchedChunk;
-    for (uint32_t r = 0; r < (uint32_t)kSchedChunk; r += kBlock) {
-        const uint32_t v = base + r + threadIdx.x;
-        const int c = v < (uint32_t)n ? sched_bin_of(in_cnt[v]) : kSchedBins;
-#pragma unroll
-        for (int b = 0; b < kSchedBins; b++) cnt[b] += (uint32_t)__popcll(__ballot(c == b));
-    }
-    if (lane == 0)
-#pragma unroll
-        for (int b = 0; b < kSchedBins; b++) s[wave][b] = cnt[b];
-    __syncthreads();
-    if (threadIdx.x < kSchedBins) {
-        uint32_t t = 0;
-        for (int w = 0; w < kWavesPerBlock; w++) t += s[w][threadIdx.x];
-        tmp[threadIdx.x * nblocks + blockIdx.x] = t;
-    }
-}
-
-// Exclusive scan of the bin-major count table; off[b] = start of bin b.
-// Each thread sums a contiguous run of the table, the run totals are
-// scanned across the workgroup, and each thread then rewrites its run.
-__global__ __launch_bounds__(kScanThreads) void k_sched_scan(uint32_t *tmp, uint32_t nblocks,
-                                                             uint32_t *off)
-{
-    __shared__ uint32_t s[kScanThreads];
-    const uint32_t len = nblocks * kSchedBins;
-    const uint32_t run = (len + kScanThreads - 1) / kScanThreads;
-    const uint32_t lo = min(len, threadIdx.x * run), hi = min(len, lo + run);
-    // eight loads in flight per thread
-    uint32_t tot = 0;
-    for (uint32_t i0 = lo; i0 < hi; i0 += 8) {
-        uint32_t x[8];
-#pragma unroll
-        for (int u = 0; u < 8; u++) x[u] = i0 + u < hi ? tmp[i0 + u] : 0u;
-#pragma unroll
-        for (int u = 0; u < 8; u++) tot += x[u];
-    }
-    s[threadIdx.x] = tot;
-    __syncthreads();
-    for (int o = 1; o < kScanThreads; o <<= 1) {
-        const uint32_t t = threadIdx.x >= (uint32_t)o ? s[threadIdx.x - o] : 0;
-        __syncthreads();
-        s[threadIdx.x] += t;
-        __syncthreads();
-    }
-    uint32_t acc = s[threadIdx.x] - tot;
-    for (uint32_t i0 = lo; i0 < hi; i0 += 8) {
-        uint32_t x[8];
-#pragma unroll
-        for (int u = 0; u < 8; u++) x[u] = i0 + u < hi ? tmp[i0 + u] : 0u;
-#pragma unroll
-        for (int u = 0; u < 8; u++) {
-            const uint32_t i = i0 + u;
-            if (i < hi) {
-                tmp[i] = acc;
-                if (i % nblocks == 0) off[i / nblocks] = acc;
-            }
-            acc += x[u];
-        }
-    }
-    if (threadIdx.x == kScanThreads - 1) off[kSchedBins] = s[kScanThreads - 1];
-}
-
-__global__ __launch_bounds__(kBlock) void k_sched_scatter(int32_t n, const uint32_t *in_cnt,
-                                                          const uint32_t *tmp, uint32_t nblocks,
-                                                          int32_t *sched)
-{
-    __shared__ uint32_t s_w[kWavesPerBlock][kSchedBins];   // per-wave class counts of a round
-    __shared__ uint32_t s_run[kSchedBins];                 // next position of each class
-    const int lane = lane_id(), wave = threadIdx.x / kWave;
-    const unsigned long long below = (1ull << lane) - 1ull;
-    if (threadIdx.x < kSchedBins) s_run[threadIdx.x] = tmp[threadIdx.x * nblocks + blockIdx.x];
-    __syncthreads();
-    const uint32_t base = blockIdx.x * (uint32_t)kSchedChunk;
-    for (uint32_t r = 0; r < (uint32_t)kSchedChunk; r += kBlock) {
-        const uint32_t v = base + r + threadIdx.x;
-        const int c = v < (uint32_t)n ? sched_bin_of(in_cnt[v]) : kSchedBins;
-        uint32_t rank = 0;
-#pragma unroll
-        for (int b = 0; b < kSchedBins; b++) {
-            const unsigned long long m = __ballot(c == b);
-            if (c == b) rank = (uint32_t)__popcll(m & below);
-            if (lane == 0) s_w[wave][b] = (uint32_t)__popcll(m);
-        }
-        __syncthreads();
-        if (c < kSchedBins) {
-            uint32_t pos = s_run[c] + rank;
-            for (int w = 0; w < wave; w++) pos += s_w[w][c];
-            sched[pos] = (int32_t)v;
-        }
-        __syncthreads();
-        if (threadIdx.x < kSchedBins) {
-            uint32_t t = 0;
-            for (int w = 0; w < kWavesPerBlock; w++) t += s_w[w][threadIdx.x];
-            s_run[threadIdx.x] += t;
-        }
-        __syncthreads();
-    }
-}
-
 // Flag (and abort the loop) if a batch id lies outside [0, n).
 __global__ void k_validate(int32_t n, int64_t nd, const int32_t *ds, const int32_t *dd,
                            int64_t ni, const int32_t *is, const int32_t *id, Ctl *ctl)
@@ -551,7 +438,7 @@ __device__ inline void mark_one(const IterArgs &a, int32_t x, bool append,
         deg += d;
     }
     if (append) {
-        const int cls = nw ? bin_of(a.in_cnt[x]) : 0;
+        const int cls = nw ? class_of_id(a, x) : 0;
         append_to_bins(nw, x, cls, a.ctl, a.bins, a.n_stride);
     }
 }
@@ -648,7 +535,7 @@ __device__ inline void bfs_claim(const IterArgs &a, int32_t x, const BfsQueues &
         if (big) q.hout[bh + __popcll(mh & below)] = x;
     }
     if (append) {
-        const int cls = nw ? bin_of(a.in_cnt[x]) : 0;
+        const int cls = nw ? class_of_id(a, x) : 0;
         append_to_bins(nw, x, cls, a.ctl, a.bins, a.n_stride);
     }
 }
@@ -923,8 +810,6 @@ IterArgs iter_args(dfpr_graph *g, const dfpr_params &p, uint32_t sbase)
     a.stamp = g->stamp;
     a.xstamp = g->xstamp;
     a.bins = g->bins;
-    a.sched = g->sched;
-    a.sched_off = g->sched_off;
     a.ctl = g->ctl;
     a.mirror = g->ctl_host;
     a.dr_part = g->it.dr_part;
@@ -942,20 +827,6 @@ IterArgs iter_args(dfpr_graph *g, const dfpr_params &p, uint32_t sbase)
     // would hide the writes of the same launch
     a.hub = p.mode == DFPR_ASYNC ? 0u : kHubRows;
     return a;
-}
-
-// Rebuild the class schedule if in-degrees changed since the last build.
-static int ensure_schedule(dfpr_graph *g)
-{
-    if (!g->sched_dirty) return DFPR_OK;
-    const uint32_t nb = (uint32_t)((g->n + kSchedChunk - 1) / kSchedChunk);
-    hipStream_t s = g->stream;
-    k_sched_count<<<nb, kBlock, 0, s>>>(g->n, g->csr[0].cnt, g->sched_tmp, nb);
-    k_sched_scan<<<1, kScanThreads, 0, s>>>(g->sched_tmp, nb, g->sched_off);
-    k_sched_scatter<<<nb, kBlock, 0, s>>>(g->n, g->csr[0].cnt, g->sched_tmp, nb, g->sched);
-    DFPR_HIP(hipGetLastError());
-    g->sched_dirty = 0;
-    return DFPR_OK;
 }
 
 // Take a stamp base for a new call; stamps of earlier calls are all below it.
@@ -1172,7 +1043,7 @@ static int run_loop(dfpr_graph *g, const dfpr_params &p, bool df, bool f32, uint
         g->prof.exp_rows += dxv;
         g->prof.exp_edges += dxe;
         g->prof.marked += dmk;
-        // per processed row: schedule entry 4 B, row start and length 8 B,
+        // per processed row: worklist entry 4 B, row start and length 8 B,
         // R[v] 8 B, |out(v)| 4 B, R'[v] and C'[v] written 16 B (12 B with an
         // FP32 contribution) (+ its mark 4 B and expansion stamp 4 B in
         // Dynamic Frontier); per in-edge: index 4 B and the gathered
@@ -1238,8 +1109,6 @@ static int full_sweeps(dfpr_graph *g, const dfpr_params *pp, const double *prev,
         k_init_ranks<<<blocks_for(n), kBlock, 0, s>>>(n, nullptr, g->R[0], g->R[1], g->C[0],
                                                       g->C[1], g->csr[1].cnt);
     }
-    rc = ensure_schedule(g);
-    if (rc) return rc;
     k_reset<<<1, 1, 0, s>>>(g->ctl);
     k_snap<<<1, 1, 0, s>>>(g->ctl, p.max_iters, g->sparse_limit, 1, g->ctl_host, p.tol,
                            p.frontier_tol);
@@ -1265,9 +1134,9 @@ static int full_sweeps(dfpr_graph *g, const dfpr_params *pp, const double *prev,
 }
 
 // Everything of a Dynamic Frontier call before its iterations, enqueued on
-// the graph's stream: optional previous ranks, the class schedule, a stamp
-// base, the initial marking of the batch (device arrays) and the snapshot
-// of iteration 0.  Returns the stamp base.
+// the graph's stream: optional previous ranks, a stamp base, the initial
+// marking of the batch (device arrays) and the snapshot of iteration 0.
+// Returns the stamp base.
 int df_begin(dfpr_graph *g, const dfpr_params &p, int64_t nd, const int32_t *bds,
              const int32_t *bdd, int64_t ni, const int32_t *bis, const int32_t *bid,
              const double *prev, int prev_dev, uint32_t *sbase_out)
@@ -1282,9 +1151,8 @@ int df_begin(dfpr_graph *g, const dfpr_params &p, int64_t nd, const int32_t *bds
         k_init_ranks<<<blocks_for(n), kBlock, 0, s>>>(n, g->R[cur], g->R[0], g->R[1], g->C[0],
                                                       g->C[1], g->csr[1].cnt);
     }
-    rc = ensure_schedule(g);
     uint32_t sbase = 0;
-    if (!rc) rc = take_base(g, p.max_iters, &sbase);
+    rc = take_base(g, p.max_iters, &sbase);
     if (rc) return rc;
     // the initial marking decides on the device whether the batch's
     // sources reach enough vertices to start on the full schedule
@@ -1501,9 +1369,8 @@ static int dt_impl(dfpr_graph *g, const dfpr_params *pp, int64_t nd, const int32
         k_init_ranks<<<blocks_for(n), kBlock, 0, s>>>(n, g->R[cur], g->R[0], g->R[1], g->C[0],
                                                       g->C[1], g->csr[1].cnt);
     }
-    rc = ensure_schedule(g);
     uint32_t sbase = 0;
-    if (!rc) rc = take_base(g, p.max_iters, &sbase);
+    rc = take_base(g, p.max_iters, &sbase);
     if (rc) return rc;
     IterArgs a = iter_args(g, p, sbase);
     k_reset<<<1, 1, 0, s>>>(g->ctl);

@@ -88,20 +88,18 @@ __global__ __launch_bounds__(kBlock) void k_gather_ctl(CtlGather g)
     }
 }
 
-// Workgroups that can have work in any iteration of a graph whose class
-// schedule has the given offsets: the count of the full schedule, which
-// bounds every frontier.
-static uint32_t blocks_bound(const uint32_t *off, uint32_t grid)
+// Workgroups that can have work in any iteration of a graph: the count of
+// the full schedule over its class id ranges, which bounds every frontier.
+static uint32_t blocks_bound(const dfpr_graph *g, uint32_t grid)
 {
-    // schedule bin 1: self-loop-only rows, one per lane; bin 0: the rest of
-    // class 0; bin b + 1: class b >= 1
-    uint64_t nwu = ((uint64_t)(off[2] - off[1]) + kWave - 1) / kWave;
+    const uint32_t *c = g->cls;
+    // the self-loop rows one per lane; class b the range [c[kBins-1-b], c[kBins-b])
+    uint64_t nwu = ((uint64_t)(c[kBins + 1] - c[kBins]) + kWave - 1) / kWave;
     for (int b = 0; b < kBins - 1; b++) {
-        const int sb = b == 0 ? 0 : b + 1;
         const uint64_t rows = kWave / group_of(b);
-        nwu += ((uint64_t)(off[sb + 1] - off[sb]) + rows - 1) / rows;
+        nwu += ((uint64_t)(c[kBins - b] - c[kBins - 1 - b]) + rows - 1) / rows;
     }
-    const uint64_t nbu = off[kSchedBins] - off[kSchedBins - 1];
+    const uint64_t nbu = c[1] - c[0];
     const uint64_t wblocks = (nwu + kWavesPerBlock - 1) / kWavesPerBlock;
     return (uint32_t)std::max<uint64_t>(1, std::max(std::min<uint64_t>(grid, nbu),
                                                     std::min<uint64_t>(grid, wblocks)));
@@ -170,7 +168,6 @@ struct dfpr_server {
     hipStream_t astream = nullptr;    // admission: apply + initial marking
     dfpr::Ctl *ctl_dev = nullptr;     // kMaxSlots gathered control blocks
     dfpr::Ctl *ctl_pin = nullptr;     // their pinned host copy
-    uint32_t *sched_pin = nullptr;    // class schedule offsets of an admitted graph
 };
 
 using namespace dfpr;
@@ -208,9 +205,7 @@ static int admit(dfpr_server *srv, int64_t r, Slot &sl, double now_ms)
         uint32_t sbase = 0;
         rc = df_begin(g, ge.p, nd, bds, bdd, ni, bis, bid, nullptr, 0, &sbase);
         if (rc) break;
-        if (hipMemcpyAsync(srv->sched_pin, g->sched_off, (kSchedBins + 1) * sizeof(uint32_t),
-                           hipMemcpyDeviceToHost, srv->astream) != hipSuccess ||
-            hipStreamSynchronize(srv->astream) != hipSuccess) {
+        if (hipStreamSynchronize(srv->astream) != hipSuccess) {
             rc = set_error(DFPR_E_DEVICE, "admission failed on the device");
             break;
         }
@@ -219,7 +214,7 @@ static int admit(dfpr_server *srv, int64_t r, Slot &sl, double now_ms)
         sl.sbase = sbase;
         sl.phase32 = ge.p.precision == DFPR_FP32_KAHAN ? 1 : 0;
         sl.base = g->cur;
-        sl.blocks = blocks_bound(srv->sched_pin, (uint32_t)g->grid);
+        sl.blocks = blocks_bound(g, (uint32_t)g->grid);
     } while (0);
     g->stream = srv->stream;
     return rc;
@@ -542,7 +537,6 @@ int dfpr_server_create(int32_t max_slots, int64_t hbm_budget_bytes, dfpr_server 
     if (e == hipSuccess) e = hipStreamCreateWithFlags(&s->astream, hipStreamNonBlocking);
     if (e == hipSuccess) e = hipMalloc(&s->ctl_dev, kMaxSlots * sizeof(Ctl));
     if (e == hipSuccess) e = hipHostMalloc(&s->ctl_pin, kMaxSlots * sizeof(Ctl));
-    if (e == hipSuccess) e = hipHostMalloc(&s->sched_pin, (kSchedBins + 1) * sizeof(uint32_t));
     if (e != hipSuccess) {
         dfpr_server_free(s);
         return hip_fail(e, "server set-up");
@@ -561,7 +555,6 @@ void dfpr_server_free(dfpr_server *s)
         }
     (void)hipFree(s->ctl_dev);
     (void)hipHostFree(s->ctl_pin);
-    (void)hipHostFree(s->sched_pin);
     delete s;
 }
 
