@@ -349,6 +349,15 @@ def copy_bandwidth(torch, nbytes=1 << 30, reps=5):
     return best
 
 
+def current_edges(g):
+    """Non-self-loop edges of a library graph (caller ids), for drawing a
+    batch against its current edge set."""
+    off, idx = g.csr(True)
+    src = np.repeat(np.arange(g.n, dtype=np.int32), np.diff(off))
+    keep = src != idx
+    return src[keep], idx[keep].astype(np.int32)
+
+
 def cpu_model():
     """Host CPU model name (Linux), or the platform's processor string."""
     try:
@@ -483,26 +492,31 @@ def grid_bench(args, dfpr, synth, side=4096, kinds=("uniform", "localised"), per
     # Each variant starts from the reference ranks of the graph before the
     # batch: on this graph (mean rank 6e-8) ranks that stopped at an L-inf
     # change of tau carry an L1 error of ~1e-4 that would hide tau_f.
-    extra = synth.localized_batch(src, dst, side, nd, ni, seed=99)
+    # fixed and adaptive tau_f on one more batch of each kind
     pref = dfpr.params(tol=0.0, max_iters=500)
     R_df_end = g.ranks()
-    R_prev, _ = g.static(pref)
-    g.apply_batch(extra)
-    Rr, _ = g.static(pref)
-    ftol_cmp = {}
-    for f in (1e-11, 1e-12, 1e-13, 1e-15):
+    extras = {"localised": synth.localized_batch(src, dst, side, nd, ni, seed=99),
+              "uniform": synth.random_batch(*current_edges(g), n, nd, ni, seed=98)}
+    for kind, extra in extras.items():
+        R_prev, _ = g.static(pref)
+        g.apply_batch(extra)
+        Rr, _ = g.static(pref)
+        ftol_cmp = {}
+        for f in (1e-11, 1e-12, 1e-13, 1e-15, "adaptive"):
+            g.set_ranks(R_prev)
+            ft = dfpr.FTOL_ADAPTIVE if f == "adaptive" else f
+            R, st = g.dynamic_frontier(extra, p=dfpr.params(frontier_tol=ft))
+            ftol_cmp[str(f)] = {"df_ms": round(st.ms_device, 3), "iterations": st.iterations,
+                                "affected": st.affected_final,
+                                "frontier_tol_used": st.frontier_tol_used,
+                                "l1": float(np.sum(np.abs(R - Rr)))}
+            log(f"{kind}, tau_f {f}: {ftol_cmp[str(f)]}")
         g.set_ranks(R_prev)
-        R, st = g.dynamic_frontier(extra, p=dfpr.params(frontier_tol=f))
-        ftol_cmp[str(f)] = {"df_ms": round(st.ms_device, 3), "iterations": st.iterations,
-                            "affected": st.affected_final,
-                            "l1": float(np.sum(np.abs(R - Rr)))}
-        log(f"localised, tau_f {f}: {ftol_cmp[str(f)]}")
-    g.set_ranks(R_prev)
-    R, st = g.naive_dynamic(p=dfpr.params())
-    ftol_cmp["naive_dynamic"] = {"ms": round(st.ms_device, 3), "iterations": st.iterations,
-                                 "l1": float(np.sum(np.abs(R - Rr)))}
-    g.set_ranks(R_df_end)
-    out["localised_frontier_tol"] = ftol_cmp
+        R, st = g.naive_dynamic(p=dfpr.params())
+        ftol_cmp["naive_dynamic"] = {"ms": round(st.ms_device, 3), "iterations": st.iterations,
+                                     "l1": float(np.sum(np.abs(R - Rr)))}
+        out[f"{kind}_frontier_tol"] = ftol_cmp
+        g.set_ranks(R)
     g.close()
     return out
 
@@ -622,9 +636,10 @@ def sweep_bench(args, dfpr, synth, scale=22):
 
     out = {"metric": METRIC, "workload": f"rmat{scale}_ef16_sweep", "n": n, "m": m}
     # frontier tolerance, three 1e-5 |E| batches
-    ftols = [tol / 10 ** k for k in range(6)]
+    ftols = [tol / 10 ** k for k in range(6)] + ["adaptive"]
     seq = synth.batch_sequence(src, dst, n, [synth.batch_counts(1e-5, m)] * 3, seed=40)
-    sweep = {str(f): {"ms": [], "l1": [], "affected": [], "iterations": []} for f in ftols}
+    sweep = {str(f): {"ms": [], "l1": [], "affected": [], "iterations": [], "used": []}
+             for f in ftols}
     nv = {"ms": [], "l1": []}
     for b in seq:
         R_prev = g.ranks()
@@ -632,12 +647,14 @@ def sweep_bench(args, dfpr, synth, scale=22):
         Rr = reference()
         for f in ftols:
             g.set_ranks(R_prev)
-            R, st = g.dynamic_frontier(b, p=dfpr.params(tol=tol, frontier_tol=f))
+            ft = dfpr.FTOL_ADAPTIVE if f == "adaptive" else f
+            R, st = g.dynamic_frontier(b, p=dfpr.params(tol=tol, frontier_tol=ft))
             d = sweep[str(f)]
             d["ms"].append(st.ms_device)
             d["l1"].append(l1(R, Rr))
             d["affected"].append(st.affected_final)
             d["iterations"].append(st.iterations)
+            d["used"].append(st.frontier_tol_used)
         g.set_ranks(R_prev)
         R, st = g.naive_dynamic(p=dfpr.params(tol=tol))
         nv["ms"].append(st.ms_device)
@@ -647,7 +664,8 @@ def sweep_bench(args, dfpr, synth, scale=22):
         f: {"df_ms_mean": round(float(np.mean(d["ms"])), 3),
             "l1_mean": float(np.mean(d["l1"])),
             "affected_mean": int(np.mean(d["affected"])),
-            "iterations_mean": round(float(np.mean(d["iterations"])), 1)}
+            "iterations_mean": round(float(np.mean(d["iterations"])), 1),
+            "frontier_tol_used": sorted(set(d["used"]))}
         for f, d in sweep.items()}
     out["frontier_tol_sweep"]["naive_dynamic"] = {"ms_mean": round(float(np.mean(nv["ms"])), 3),
                                                   "l1_mean": float(np.mean(nv["l1"]))}
