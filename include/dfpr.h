@@ -233,6 +233,22 @@ int dfpr_pagerank_dynamic_frontier_device(dfpr_graph *g, const dfpr_params *p,
                                           const int32_t *ins_dst, const double *prev,
                                           double *ranks_out, dfpr_stats *st);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): as
+ * dfpr_pagerank_dynamic_frontier_device, but the batch is staged in a
+ * fixed array the library holds on each GPU (16 MiB, kept until the process
+ * ends) instead of a buffer it grows on demand, so the call makes no
+ * allocation.  n_del + n_ins may be at most 1048576 (DFPR_E_LIMIT beyond,
+ * nothing changed).  Every call on a GPU shares that array: calls that
+ * overlap on one GPU race.  Iterations run as launch pairs whatever
+ * p->loop asks for. */
+int dfpr_pagerank_dynamic_frontier_device_noalloc(dfpr_graph *g, const dfpr_params *p,
+                                                  int64_t n_del, const int32_t *del_src,
+                                                  const int32_t *del_dst, int64_t n_ins,
+                                                  const int32_t *ins_src,
+                                                  const int32_t *ins_dst, const double *prev,
+                                                  double *ranks_out, dfpr_stats *st);
+
 /* Dynamic Traversal PageRank (Section 3.3.2), a comparator: every vertex
  * reachable from the source of a batch edge in G^{t-1} or in G^t is
  * updated, from prev (NULL = the resident ranks), until Delta R <= tol or

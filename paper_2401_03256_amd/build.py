@@ -8,7 +8,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB_PATH = os.path.join(HERE, "libdfpr.so")
-SOURCES = ["graph.hip", "rank.hip", "apply.hip", "serve.hip"]
+SOURCES = ["graph.hip", "rank.hip", "apply.hip", "serve.hip", "noalloc.hip"]
 ARCH = os.environ.get("DFPR_OFFLOAD_ARCH", "gfx950")
 
 HIPCC_FLAGS = [

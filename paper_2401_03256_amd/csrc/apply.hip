@@ -923,6 +923,21 @@ int stage_batch(dfpr_graph *g, int64_t n_del, const int32_t *ds, const int32_t *
     return DFPR_OK;
 }
 
+int stage_batch_into(dfpr_graph *g, int64_t n_del, const int32_t *ds, const int32_t *dd,
+                     int64_t n_ins, const int32_t *is, const int32_t *id, int32_t *buf,
+                     const int32_t **dds, const int32_t **ddd, const int32_t **dis,
+                     const int32_t **did)
+{
+    const int32_t *src[4] = {ds, dd, is, id};
+    const int64_t len[4] = {n_del, n_del, n_ins, n_ins};
+    if (n_del + n_ins > 0) DFPR_CHECK_RC(map_ids4(g, src, len, buf));
+    *dds = buf;
+    *ddd = buf + n_del;
+    *dis = buf + 2 * n_del;
+    *did = buf + 2 * n_del + n_ins;
+    return DFPR_OK;
+}
+
 static ApplyArgs apply_args(dfpr_graph *g)
 {
     ApplyArgs a{};

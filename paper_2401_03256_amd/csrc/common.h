@@ -186,6 +186,7 @@ struct dfpr_graph {
     int32_t refine_sweeps = 0;        // FP64 iterations after the FP32 phase
     int32_t loop_iters = 0;           // iterations the small-frontier loop ran
     int busy = 0;
+    int device = 0;                   // the HIP device the graph lives on
     int grid = 1024;                  // iteration-kernel workgroups
     int coop = 0;                     // the device takes cooperative launches
     uint32_t sparse_limit = 0;        // frontier size that switches to the full schedule
@@ -217,6 +218,12 @@ int stage_batch(dfpr_graph *g, int64_t n_del, const int32_t *ds, const int32_t *
                 int64_t n_ins, const int32_t *is, const int32_t *id, int on_device,
                 const int32_t **dds, const int32_t **ddd, const int32_t **dis,
                 const int32_t **did);
+// The same for device arrays, into a caller-chosen buffer of at least
+// 2 (n_del + n_ins) ints (no allocation).
+int stage_batch_into(dfpr_graph *g, int64_t n_del, const int32_t *ds, const int32_t *dd,
+                     int64_t n_ins, const int32_t *is, const int32_t *id, int32_t *buf,
+                     const int32_t **dds, const int32_t **ddd, const int32_t **dis,
+                     const int32_t **did);
 int check_ids_host(int32_t n, int64_t len, const int32_t *a, const int32_t *b);
 
 // renumbering at the boundary (graph.hip); enqueued on g->stream

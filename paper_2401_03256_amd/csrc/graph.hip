@@ -417,11 +417,13 @@ int dfpr_load_graph(int32_t n, int64_t m, const int32_t *src, const int32_t *dst
         g->stream = g->own_stream;
     }
     if (!rc) {
+        (void)hipGetDevice(&g->device);
         hipDeviceProp_t prop;
-        if (hipGetDeviceProperties(&prop, 0) == hipSuccess && prop.multiProcessorCount > 0)
+        if (hipGetDeviceProperties(&prop, g->device) == hipSuccess && prop.multiProcessorCount > 0)
             g->grid = std::min(kMaxGrid, prop.multiProcessorCount * kGridPerCU);
         int coop = 0;
-        if (hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, 0) == hipSuccess)
+        if (hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, g->device) ==
+            hipSuccess)
             g->coop = coop ? 1 : 0;
     }
     if (!rc) {

@@ -709,7 +709,12 @@ IterArgs iter_args(dfpr_graph *g, const dfpr_params &p, uint32_t sbase);
 int check_params(const dfpr_params *p, dfpr_params &out);
 int df_begin(dfpr_graph *g, const dfpr_params &p, int64_t nd, const int32_t *bds,
              const int32_t *bdd, int64_t ni, const int32_t *bis, const int32_t *bid,
-             const double *prev, int prev_dev, uint32_t *sbase_out);
+             const double *prev, int prev_dev, uint32_t *sbase_out, int32_t *lists = nullptr);
+// A Dynamic Frontier call on device arrays whose batch is staged in
+// `staging` (4 (nd + ni) ints) instead of the library's buffer.
+int df_device_staged(dfpr_graph *g, const dfpr_params *pp, int64_t nd, const int32_t *ds,
+                     const int32_t *dd, int64_t ni, const int32_t *is, const int32_t *id,
+                     const double *prev, double *ranks_out, dfpr_stats *st, int32_t *staging);
 int df_phase_end(dfpr_graph *g, int res, bool call_done);
 int df_finish(dfpr_graph *g, uint32_t sbase, int res, int32_t iters);
 

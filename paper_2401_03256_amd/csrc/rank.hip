@@ -726,12 +726,13 @@ static inline int blocks_for(int64_t items, int per_block = kBlock)
 }
 
 // Both passes of the initial marking on the graph's stream.  The batch
-// arrays are in the staging buffer, which has room for the source lists.
+// arrays are staged in device memory; `lists` has room for the two source
+// lists (2 (nd + ni) entries).
 static void launch_initial_marking(dfpr_graph *g, const IterArgs &a, int64_t nd,
                                    const int32_t *ds, const int32_t *dd, int64_t ni,
-                                   const int32_t *is, int dense)
+                                   const int32_t *is, int dense, int32_t *lists)
 {
-    int32_t *light = g->ap.batch_dev + 2 * (nd + ni);
+    int32_t *light = lists;
     int32_t *heavy = light + (nd + ni);
     k_mark_claim<<<blocks_for(nd + ni), kBlock, 0, g->stream>>>(a, nd, ds, ni, is, light, heavy);
     const int64_t waves = std::max<int64_t>(nd + ni, 1024);
@@ -1139,8 +1140,9 @@ static int full_sweeps(dfpr_graph *g, const dfpr_params *pp, const double *prev,
 // Returns the stamp base.
 int df_begin(dfpr_graph *g, const dfpr_params &p, int64_t nd, const int32_t *bds,
              const int32_t *bdd, int64_t ni, const int32_t *bis, const int32_t *bid,
-             const double *prev, int prev_dev, uint32_t *sbase_out)
+             const double *prev, int prev_dev, uint32_t *sbase_out, int32_t *lists)
 {
+    if (!lists) lists = g->ap.batch_dev + 2 * (nd + ni);
     const int32_t n = g->n;
     hipStream_t s = g->stream;
     const int cur = g->cur;
@@ -1161,7 +1163,7 @@ int df_begin(dfpr_graph *g, const dfpr_params &p, int64_t nd, const int32_t *bds
     k_reset<<<1, 1, 0, s>>>(g->ctl);
     if (nd + ni > 0) {
         k_validate<<<blocks_for(nd + ni), kBlock, 0, s>>>(n, nd, bds, bdd, ni, bis, bid, g->ctl);
-        launch_initial_marking(g, a, nd, bds, bdd, ni, bis, dense);
+        launch_initial_marking(g, a, nd, bds, bdd, ni, bis, dense, lists);
     }
     k_snap<<<1, 1, 0, s>>>(g->ctl, p.max_iters, g->sparse_limit, dense, g->ctl_host, p.tol,
                            p.frontier_tol);
@@ -1212,13 +1214,18 @@ int df_finish(dfpr_graph *g, uint32_t sbase, int res, int32_t iters)
     return DFPR_OK;
 }
 
+// A Dynamic Frontier call.  `staging` (device arrays only): a caller-chosen
+// buffer of 4 (nd + ni) ints for the staged batch and the marking's source
+// lists, in place of the library's own; such a call allocates nothing.
 static int df_impl(dfpr_graph *g, const dfpr_params *pp, int64_t nd, const int32_t *ds,
                    const int32_t *dd, int64_t ni, const int32_t *is, const int32_t *id,
-                   int on_device, const double *prev, double *ranks_out, dfpr_stats *st)
+                   int on_device, const double *prev, double *ranks_out, dfpr_stats *st,
+                   int32_t *staging = nullptr)
 {
     dfpr_params p;
     int rc = check_params(pp, p);
     if (rc) return rc;
+    if (staging && !on_device) return set_error(DFPR_E_ARG, "staging needs device arrays");
     if (nd < 0 || ni < 0 || (nd && (!ds || !dd)) || (ni && (!is || !id)))
         return set_error(DFPR_E_ARG, "bad batch arrays");
     if (!on_device) {
@@ -1231,11 +1238,13 @@ static int df_impl(dfpr_graph *g, const dfpr_params *pp, int64_t nd, const int32
     hipStream_t s = g->stream;
     DFPR_HIP(hipEventRecord(g->ev0, s));
     const int32_t *bds, *bdd, *bis, *bid;
-    rc = stage_batch(g, nd, ds, dd, ni, is, id, on_device, &bds, &bdd, &bis, &bid);
+    if (staging) rc = stage_batch_into(g, nd, ds, dd, ni, is, id, staging, &bds, &bdd, &bis, &bid);
+    else rc = stage_batch(g, nd, ds, dd, ni, is, id, on_device, &bds, &bdd, &bis, &bid);
     if (rc) return rc;
     const int cur = g->cur;
     uint32_t sbase = 0;
-    rc = df_begin(g, p, nd, bds, bdd, ni, bis, bid, prev, on_device, &sbase);
+    rc = df_begin(g, p, nd, bds, bdd, ni, bis, bid, prev, on_device, &sbase,
+                  staging ? staging + 2 * (nd + ni) : nullptr);
     if (rc) return rc;
     DFPR_HIP(hipEventRecord(g->ev_mid, s));
     int res = cur;
@@ -1271,6 +1280,13 @@ static int df_impl(dfpr_graph *g, const dfpr_params *pp, int64_t nd, const int32
     DFPR_HIP(hipStreamSynchronize(s));
     fill_stats(g, st, true);
     return DFPR_OK;
+}
+
+int df_device_staged(dfpr_graph *g, const dfpr_params *pp, int64_t nd, const int32_t *ds,
+                     const int32_t *dd, int64_t ni, const int32_t *is, const int32_t *id,
+                     const double *prev, double *ranks_out, dfpr_stats *st, int32_t *staging)
+{
+    return df_impl(g, pp, nd, ds, dd, ni, is, id, 1, prev, ranks_out, st, staging);
 }
 
 // Workgroups for a traversal level of `q` light vertices (a wave per 64),
@@ -1560,7 +1576,9 @@ int dfpr_mark_affected(dfpr_graph *g, int64_t n_del, const int32_t *del_src,
     a.stamp = g->mstamp;
     a.xstamp = g->mxstamp;
     k_reset<<<1, 1, 0, s>>>(g->ctl);
-    if (n_del + n_ins > 0) launch_initial_marking(g, a, n_del, bds, bdd, n_ins, bis, 1);
+    if (n_del + n_ins > 0)
+        launch_initial_marking(g, a, n_del, bds, bdd, n_ins, bis, 1,
+                               g->ap.batch_dev + 2 * (n_del + n_ins));
     DFPR_HIP(hipGetLastError());
     std::vector<uint32_t> st(n);
     DFPR_HIP(hipMemcpyAsync(st.data(), g->mstamp, (size_t)n * 4, hipMemcpyDeviceToHost, s));

@@ -37,6 +37,7 @@ EXPORTED = [
     "dfpr_graph_info", "dfpr_apply_batch", "dfpr_apply_batch_device",
     "dfpr_pagerank_static", "dfpr_pagerank_naive_dynamic",
     "dfpr_pagerank_dynamic_frontier", "dfpr_pagerank_dynamic_frontier_device",
+    "dfpr_pagerank_dynamic_frontier_device_noalloc",
     "dfpr_mark_affected", "dfpr_get_affected", "dfpr_get_ranks", "dfpr_set_ranks",
     "dfpr_export_csr", "dfpr_last_error", "dfpr_profile_reset", "dfpr_profile_read",
     "dfpr_pagerank_dynamic_traversal", "dfpr_mark_reachable",
@@ -163,6 +164,7 @@ def lib():
     L.dfpr_pagerank_naive_dynamic.argtypes = [_P, _P, _P, _P, _P]
     L.dfpr_pagerank_dynamic_frontier.argtypes = [_P, _P, *batch, _P, _P, _P]
     L.dfpr_pagerank_dynamic_frontier_device.argtypes = [_P, _P, *batch, _P, _P, _P]
+    L.dfpr_pagerank_dynamic_frontier_device_noalloc.argtypes = [_P, _P, *batch, _P, _P, _P]
     L.dfpr_mark_affected.argtypes = [_P, *batch, _P]
     L.dfpr_pagerank_dynamic_traversal.argtypes = [_P, _P, *batch, _P, _P, _P]
     L.dfpr_mark_reachable.argtypes = [_P, *batch, _P]
@@ -328,16 +330,18 @@ class Graph:
         return R, _stats(st)
 
     def dynamic_frontier_device(self, ds, dd, is_, id_, prev=None, out=None,
-                                p: Params | None = None):
-        """Batch as torch int32 GPU tensors; prev/out optional float64 GPU tensors."""
+                                p: Params | None = None, noalloc=False):
+        """Batch as torch int32 GPU tensors; prev/out optional float64 GPU
+        tensors.  noalloc: the entry point that makes no allocation."""
         import torch
         nd, ni = ds.numel(), is_.numel()
         st = _Stats()
-        _check(lib().dfpr_pagerank_dynamic_frontier_device(
-            self._h, ctypes.byref(p) if p else None, nd, _dev_ptr(ds, torch.int32),
-            _dev_ptr(dd, torch.int32, nd), ni, _dev_ptr(is_, torch.int32),
-            _dev_ptr(id_, torch.int32, ni), _dev_ptr(prev, torch.float64, self.n),
-            _dev_ptr(out, torch.float64, self.n), ctypes.byref(st)))
+        fn = (lib().dfpr_pagerank_dynamic_frontier_device_noalloc if noalloc
+              else lib().dfpr_pagerank_dynamic_frontier_device)
+        _check(fn(self._h, ctypes.byref(p) if p else None, nd, _dev_ptr(ds, torch.int32),
+                  _dev_ptr(dd, torch.int32, nd), ni, _dev_ptr(is_, torch.int32),
+                  _dev_ptr(id_, torch.int32, ni), _dev_ptr(prev, torch.float64, self.n),
+                  _dev_ptr(out, torch.float64, self.n), ctypes.byref(st)))
         return _stats(st)
 
     # -- inspection ---------------------------------------------------------
