@@ -7,23 +7,29 @@
 // in flight (one writer per graph, Section 3.2) and (c) the HBM budget
 // covers the resident graphs plus the scratch of every admitted request.
 // Admission applies the batch to the graph and runs the initial marking on
-// a second stream, while the iterations of the requests already admitted
-// keep running on the first.
+// a stream of its own, while the iterations of the requests already
+// admitted keep running.
 //
-// Every step runs one iteration of every admitted request in one launch:
-// each slot owns a range of workgroups sized for its graph (the class
-// schedule bounds the work of any iteration), the hardware dispatcher
-// spreads the ranges over the chip, and workgroups of a small graph that
-// finish early leave their compute units to the others.  FP64 slots and
-// slots in the FP32 phase of the precision form share the launch.  Steps
-// are enqueued in chunks; the chunk length follows the observed geometric
-// decay of Delta R of the slots (so a slot is retired soon after it
-// converges) and is kept short while requests wait, because requests join
-// and leave at chunk boundaries.
+// Requests run in two lanes, each on its own stream.  A large graph (at
+// least kLargeEdges edges: an iteration over its full schedule fills the
+// GPU) takes the large lane, which holds one request at a time, so large
+// requests run one after another in arrival order and never queue behind
+// small ones.  The large lane keeps a second chunk of steps queued behind
+// the one running, so its request does not wait for the host between
+// chunks.  All other requests share the small lane: every step runs one
+// iteration of each of them in one launch, each slot owning a range of
+// workgroups sized for its graph, so small updates progress beside a large
+// one instead of waiting for it.  While a large request runs, a small-lane
+// step takes at most kSmallLaneBlocks workgroups.  FP64 slots and slots in
+// the FP32 phase of the precision form share a launch.  Chunk lengths
+// follow the observed geometric decay of Delta R of the slots (so a slot is
+// retired soon after it converges); small-lane chunks are kept short while
+// requests wait for a slot, because requests join and leave at chunk
+// boundaries.  The host serves whichever lane finishes a chunk first.
 //
 // Each slot runs exactly the per-row code of the single-graph engine
 // (iter.h) with the same class of every row, so a request's result does not
-// depend on what else is in flight.
+// depend on what else is in flight or on its lane.
 #include <algorithm>
 #include <chrono>
 #include <cmath>
@@ -40,6 +46,14 @@ constexpr int kMaxSlots = 8;
 constexpr int kMaxChunk = 32;
 constexpr int64_t kRequestBytesPerEntry = 96;   // device scratch per batch entry
 constexpr double kChunkMsWhileWaiting = 1.0;   // chunk length while requests wait
+constexpr int64_t kLargeEdges = int64_t(1) << 25;   // edges that put a graph in the large lane
+constexpr int kLanes = 2;                      // 0: large graphs, one at a time; 1: the rest
+constexpr int kDepth = 2;                      // chunks a lane may have in flight
+// Workgroups of one small-lane step while a large request runs (0: no cap).
+#ifndef DFPR_SMALL_LANE_BLOCKS
+#define DFPR_SMALL_LANE_BLOCKS 512
+#endif
+constexpr uint32_t kSmallLaneBlocks = DFPR_SMALL_LANE_BLOCKS;
 
 struct MultiArgs {
     int32_t nslots;
@@ -59,12 +73,17 @@ static_assert(sizeof(Ctl) % 4 == 0, "control blocks are copied as words");
 __global__ __launch_bounds__(kBlock, DFPR_ITER_WAVES_PER_SIMD) void k_iter_multi(MultiArgs m)
 {
     __shared__ IterShared sh;
+#if DFPR_HUB
+    __shared__ double hub[kHubRows];
+#else
+    double *hub = nullptr;
+#endif
     const uint32_t b = blockIdx.x;
     int s = 0;
     while (s + 1 < m.nslots && b >= m.off[s + 1]) s++;
     const uint32_t G = m.off[s + 1] - m.off[s];
-    if ((m.f32_mask >> s) & 1u) iter_body<true, true>(m.s[s], b - m.off[s], G, sh);
-    else iter_body<true, false>(m.s[s], b - m.off[s], G, sh);
+    if ((m.f32_mask >> s) & 1u) iter_body<true, true>(m.s[s], b - m.off[s], G, sh, hub);
+    else iter_body<true, false>(m.s[s], b - m.off[s], G, sh, hub);
 }
 
 // One workgroup per slot.
@@ -122,7 +141,9 @@ struct Slot {
     int phase32 = 0;          // in the FP32 phase of the precision form
     int it0 = 0;              // first iteration of the current phase
     int base = 0;             // buffer the current phase started on
-    int it = 0;               // next iteration
+    int it = 0;               // iterations done at the last look
+    int itq = 0;              // first iteration not yet queued
+    uint32_t epoch = 0;       // changes when the slot changes request or phase
     uint32_t blocks = 1;      // workgroups in a coalesced launch
     double prev_dr = -1.0;    // Delta R and iteration count at the last look
     int prev_it = 0;
@@ -134,16 +155,17 @@ struct GraphEntry {
     dfpr_params p{};
     int64_t bytes = 0;
     int busy = 0;
+    int lane = 1;
 };
 
-// Device bytes a graph holds (CSRs, rank and contribution buffers, marks,
-// class lists and schedule).
+// Device bytes a graph holds (CSRs, rank and contribution buffers, stamps,
+// id maps, class lists, FP32 contributions).
 static int64_t graph_bytes(const dfpr_graph *g)
 {
     const int64_t n = g->n;
     int64_t b = 0;
     for (int o = 0; o < 2; o++) b += (int64_t)g->csr[o].slots * 4 + 3 * n * 4;
-    b += 5 * n * 8 + 2 * n * 4 + 2 * n * 4 + (int64_t)kBins * n * 4 + n * 4 + 2 * n * 4;
+    b += 5 * n * 8 + 2 * n * 4 + 2 * n * 4 + (int64_t)kBins * n * 4 + 2 * n * 4;
     return b + apply_slab_bytes(g);   // the applier's row copies of long rows
 }
 
@@ -164,10 +186,13 @@ struct dfpr_server {
     int64_t resident = 0;
     std::vector<dfpr::GraphEntry> graphs;
     std::vector<dfpr::Request> reqs;
-    hipStream_t stream = nullptr;     // iterations, phase ends, finishing
-    hipStream_t astream = nullptr;    // admission: apply + initial marking
-    dfpr::Ctl *ctl_dev = nullptr;     // kMaxSlots gathered control blocks
-    dfpr::Ctl *ctl_pin = nullptr;     // their pinned host copy
+    hipStream_t stream[dfpr::kLanes] = {};   // per lane: iterations, phase ends, finishing
+    hipStream_t astream = nullptr;           // admission: apply + initial marking
+    // per lane and chunk in flight: its end, its gathered control blocks
+    // (kMaxSlots) and their pinned host copy
+    hipEvent_t done[dfpr::kLanes][dfpr::kDepth] = {};
+    dfpr::Ctl *ctl_dev[dfpr::kLanes][dfpr::kDepth] = {};
+    dfpr::Ctl *ctl_pin[dfpr::kLanes][dfpr::kDepth] = {};
 };
 
 using namespace dfpr;
@@ -216,20 +241,29 @@ static int admit(dfpr_server *srv, int64_t r, Slot &sl, double now_ms)
         sl.base = g->cur;
         sl.blocks = blocks_bound(g, (uint32_t)g->grid);
     } while (0);
-    g->stream = srv->stream;
+    g->stream = srv->stream[ge.lane];
     return rc;
 }
 
-// Enqueue K coalesced steps of the slots in the chunk, then one copy of
-// their control blocks to the host.
-static int launch_chunk(dfpr_server *srv, std::vector<Slot *> &cs, int K)
+// Enqueue K coalesced steps of the slots in the chunk, from each slot's
+// first unqueued iteration, then one copy of their control blocks to the
+// host (buffer `buf` of the lane).  With `cap` > 0 the slots share at most
+// about `cap` workgroups, in proportion to their bounds (each slot walks its
+// rows grid-stride, so the workgroup count changes no result).
+static int launch_chunk(dfpr_server *srv, int lane, int buf, std::vector<Slot *> &cs, int K,
+                        uint32_t cap)
 {
+    hipStream_t stream = srv->stream[lane];
     MultiArgs m{};
     m.nslots = (int32_t)cs.size();
+    uint64_t want = 0;
+    for (const Slot *sl : cs) want += sl->blocks;
     uint32_t at = 0;
     for (int i = 0; i < m.nslots; i++) {
         m.off[i] = at;
-        at += cs[i]->blocks;
+        uint32_t nb = cs[i]->blocks;
+        if (cap && want > cap) nb = (uint32_t)std::max<uint64_t>(1, (uint64_t)nb * cap / want);
+        at += nb;
         if (cs[i]->phase32) m.f32_mask |= 1u << i;
     }
     m.off[m.nslots] = at;
@@ -241,7 +275,7 @@ static int launch_chunk(dfpr_server *srv, std::vector<Slot *> &cs, int K)
             dfpr_graph *g = ge.g;
             IterArgs a = iter_args(g, ge.p, sl.sbase);
             a.mirror = nullptr;       // the slots' blocks come back gathered
-            const int it = sl.it + j;
+            const int it = sl.itq + j;
             const int src = sl.base ^ ((it - sl.it0) & 1);
             a.Rc = g->R[src];
             a.Cc = g->C[src];
@@ -252,17 +286,19 @@ static int launch_chunk(dfpr_server *srv, std::vector<Slot *> &cs, int K)
             a.it = it;
             m.s[i] = a;
         }
-        k_iter_multi<<<at, kBlock, 0, srv->stream>>>(m);
-        k_final_multi<<<m.nslots, kFinalThreads, 0, srv->stream>>>(m);
+        k_iter_multi<<<at, kBlock, 0, stream>>>(m);
+        k_final_multi<<<m.nslots, kFinalThreads, 0, stream>>>(m);
     }
     CtlGather cg{};
     cg.n = m.nslots;
     for (int i = 0; i < m.nslots; i++) cg.src[i] = srv->graphs[srv->reqs[cs[i]->req].gid].g->ctl;
-    cg.dst = srv->ctl_dev;
-    k_gather_ctl<<<1, kBlock, 0, srv->stream>>>(cg);
+    cg.dst = srv->ctl_dev[lane][buf];
+    k_gather_ctl<<<1, kBlock, 0, stream>>>(cg);
     DFPR_HIP(hipGetLastError());
-    DFPR_HIP(hipMemcpyAsync(srv->ctl_pin, srv->ctl_dev, m.nslots * sizeof(Ctl),
-                            hipMemcpyDeviceToHost, srv->stream));
+    DFPR_HIP(hipMemcpyAsync(srv->ctl_pin[lane][buf], srv->ctl_dev[lane][buf],
+                            m.nslots * sizeof(Ctl), hipMemcpyDeviceToHost, stream));
+    DFPR_HIP(hipEventRecord(srv->done[lane][buf], stream));
+    for (Slot *sl : cs) sl->itq += K;
     return DFPR_OK;
 }
 
@@ -283,24 +319,47 @@ static void predict(Slot &sl, const Ctl &c, double tol)
     sl.pred = next;
 }
 
+// A chunk in flight: its slots (with their epochs at launch), its steps,
+// the lane buffer its control blocks go to and its host launch time.
+struct Chunk {
+    std::vector<Slot *> cs;
+    std::vector<uint32_t> epoch;
+    int K = 0;
+    int buf = 0;
+    Clock::time_point t;
+};
+
+// A lane's chunks in flight, oldest first.  The large lane keeps a second
+// chunk queued behind the first, so its request does not wait for the host
+// (admissions, the other lane) between chunks; the small lane holds one,
+// so that its slots can change at every chunk boundary.
+struct LaneState {
+    Chunk q[kDepth];
+    int head = 0, n = 0;
+    double step_ms = 0.0;         // recent wall time of one step (small lane)
+    Chunk &oldest() { return q[head]; }
+    int free_buf() const { return (head + n) % kDepth; }
+};
+
 static int run(dfpr_server *srv, dfpr_server_stats *st)
 {
     std::vector<Slot> slots(srv->max_slots);
+    std::vector<int> slot_lane(srv->max_slots, -1);
     std::vector<int64_t> order(srv->reqs.size());
     for (size_t i = 0; i < order.size(); i++) order[i] = (int64_t)i;
     std::stable_sort(order.begin(), order.end(), [&](int64_t a, int64_t b) {
         return srv->reqs[a].arrival_ms < srv->reqs[b].arrival_ms;
     });
-    // work already queued on a graph's own stream comes first; the server
-    // streams carry every graph while it runs and the graphs get their
-    // streams back at the end
+    // work already queued on a graph's own stream comes first; each graph
+    // runs on its lane's stream while the server runs and gets its own
+    // stream back at the end
     std::vector<hipStream_t> saved(srv->graphs.size());
     for (size_t i = 0; i < srv->graphs.size(); i++) {
         GraphEntry &ge = srv->graphs[i];
         if (hipStreamSynchronize(ge.g->stream) != hipSuccess)
             return set_error(DFPR_E_DEVICE, "stream synchronisation failed");
         saved[i] = ge.g->stream;
-        ge.g->stream = srv->stream;
+        ge.g->stream = srv->stream[ge.lane];
         ge.busy = 0;
     }
     int64_t pending = 0;          // requests of earlier runs keep their results
@@ -309,55 +368,94 @@ static int run(dfpr_server *srv, dfpr_server_stats *st)
     size_t next = 0;              // first request of `order` not yet admitted
     int64_t done = 0, failed = 0;
     int32_t steps = 0, max_active = 0;
-    double step_ms = 0.0;         // recent wall time of one step
+    uint32_t epochs = 0;
+    LaneState lanes[kLanes];
     const Clock::time_point t0 = Clock::now();
     double last_done = 0.0;
     int rc = DFPR_OK;
+    auto active_in = [&](int lane) {
+        int k = 0;
+        for (int i = 0; i < srv->max_slots; i++) k += slots[i].req >= 0 && slot_lane[i] == lane;
+        return k;
+    };
+    auto launch = [&](int lane, std::vector<Slot *> &cs, int K) -> int {
+        LaneState &L = lanes[lane];
+        const int buf = L.free_buf();
+        // small steps leave most of the GPU to a large request
+        const uint32_t cap = lane == 1 && active_in(0) > 0 ? kSmallLaneBlocks : 0u;
+        const int lrc = launch_chunk(srv, lane, buf, cs, K, cap);
+        if (lrc) return lrc;
+        Chunk &c = L.q[buf];
+        c.cs = cs;
+        c.epoch.clear();
+        for (Slot *sl : cs) c.epoch.push_back(sl->epoch);
+        c.K = K;
+        c.buf = buf;
+        c.t = Clock::now();
+        L.n++;
+        steps += K;
+        return DFPR_OK;
+    };
     while (done + failed < pending) {
-        // 1. launch a chunk of steps for the admitted requests
-        std::vector<Slot *> cs;
-        for (Slot &s : slots)
-            if (s.req >= 0) cs.push_back(&s);
-        int K = 0;
-        Clock::time_point tc = Clock::now();
-        if (!cs.empty()) {
-            K = kMaxChunk;
-            for (Slot *s : cs) K = std::min(K, s->pred);
-            // requests join at chunk boundaries: keep chunks short while
-            // a slot is free and requests are still to come
-            while (next < order.size() && srv->reqs[order[next]].state != 0) next++;
-            if (next < order.size() && (int)cs.size() < srv->max_slots && step_ms > 0.0)
-                K = std::min(K, std::max(1, (int)(kChunkMsWhileWaiting / step_ms)));
-            K = std::max(K, 1);
-            rc = launch_chunk(srv, cs, K);
-            if (rc) goto out;
-            steps += K;
-            max_active = std::max(max_active, (int32_t)cs.size());
+        // 1. chunks for the lanes with admitted requests
+        int active = 0;
+        for (const Slot &s : slots) active += s.req >= 0;
+        max_active = std::max(max_active, (int32_t)active);
+        while (next < order.size() && srv->reqs[order[next]].state != 0) next++;
+        const bool waiting = next < order.size() && active < srv->max_slots;
+        for (int lane = 0; lane < kLanes; lane++) {
+            LaneState &L = lanes[lane];
+            std::vector<Slot *> cs;
+            for (int i = 0; i < srv->max_slots; i++)
+                if (slots[i].req >= 0 && slot_lane[i] == lane) cs.push_back(&slots[i]);
+            if (cs.empty()) continue;
+            if (L.n == 0) {
+                int K = kMaxChunk;
+                for (Slot *s : cs) K = std::min(K, s->pred);
+                // requests join the small lane at chunk boundaries: keep its
+                // chunks short while a slot is free and requests are still to come
+                if (lane == 1 && waiting && L.step_ms > 0.0)
+                    K = std::min(K, std::max(1, (int)(kChunkMsWhileWaiting / L.step_ms)));
+                rc = launch(lane, cs, std::max(K, 1));
+                if (rc) goto out;
+            }
+            if (lane == 0 && L.n == 1) {
+                // the iterations predicted beyond those queued, and at least
+                // two more, so that the device has work while the host looks
+                Slot *s = cs[0];
+                const int K = std::min(kMaxChunk, std::max(2, s->pred - (s->itq - s->it)));
+                rc = launch(lane, cs, K);
+                if (rc) goto out;
+            }
         }
-        // 2. admission in arrival order, overlapping the chunk; a request
-        // whose graph is busy waits without blocking later ones; the budget
-        // is first come, first served
-        int admitted = 0;
+        // 2. admission in arrival order, overlapping the chunks; a request
+        // whose graph is busy, or whose lane is full, waits without blocking
+        // later ones; the budget is first come, first served
         {
+            int admitted = 0;
             double now = ms_since(t0);
             auto view = [&](int64_t r) {
                 const Request &q = srv->reqs[r];
                 return PendingView{q.arrival_ms, q.state, q.gid, q.charge};
             };
-            auto busy = [&](int32_t gid) { return srv->graphs[gid].busy != 0; };
+            auto blocked = [&](int32_t gid) {
+                const GraphEntry &ge = srv->graphs[gid];
+                return ge.busy != 0 || (ge.lane == 0 && active_in(0) > 0);
+            };
             for (size_t from = next;;) {
                 auto free_slot = std::find_if(slots.begin(), slots.end(),
                                               [](const Slot &s) { return s.req < 0; });
                 const int64_t pos = next_admission(order, from, now, free_slot != slots.end(), view,
-                                                   busy, srv->resident + in_flight, srv->budget);
+                                                   blocked, srv->resident + in_flight, srv->budget);
                 if (pos < 0) break;
                 from = (size_t)pos + 1;
-                const size_t k = (size_t)pos;
-                Request &q = srv->reqs[order[k]];
+                Request &q = srv->reqs[order[(size_t)pos]];
                 srv->graphs[q.gid].busy = 1;
                 in_flight += q.charge;
                 peak = std::max(peak, srv->resident + in_flight);
-                const int arc = admit(srv, order[k], *free_slot, now);
+                const size_t si = (size_t)(free_slot - slots.begin());
+                slot_lane[si] = srv->graphs[q.gid].lane;
+                const int arc = admit(srv, order[(size_t)pos], *free_slot, now);
                 if (arc) {
                     // a rejected batch leaves its graph unchanged
                     q.state = 2;
@@ -372,14 +470,24 @@ static int run(dfpr_server *srv, dfpr_server_stats *st)
                         goto out;
                     }
                 } else {
+                    free_slot->epoch = ++epochs;
                     admitted++;
                 }
                 now = ms_since(t0);
             }
+            // a new request may start a chunk on an idle lane at once
+            if (admitted) {
+                bool idle = false;
+                for (int lane = 0; lane < kLanes; lane++)
+                    idle |= lanes[lane].n == 0 && active_in(lane) > 0;
+                if (idle) continue;
+            }
         }
-        if (cs.empty()) {
+        bool any_busy = false;
+        for (const LaneState &L : lanes) any_busy |= L.n > 0;
+        if (!any_busy) {
             while (next < order.size() && srv->reqs[order[next]].state != 0) next++;
-            if (!admitted && next < order.size()) {
+            if (next < order.size()) {
                 const double wait = srv->reqs[order[next]].arrival_ms - ms_since(t0);
                 if (wait > 0.05)
                     std::this_thread::sleep_for(std::chrono::duration<double, std::milli>(
@@ -387,98 +495,136 @@ static int run(dfpr_server *srv, dfpr_server_stats *st)
             }
             continue;
         }
-        // 3. the chunk's results
-        if (hipStreamSynchronize(srv->stream) != hipSuccess) {
-            rc = set_error(DFPR_E_DEVICE, "stream synchronisation failed");
-            goto out;
-        }
-        {
-            const double chunk_ms =
-                std::chrono::duration<double, std::milli>(Clock::now() - tc).count();
-            const double per = chunk_ms / K;
-            step_ms = step_ms > 0.0 ? 0.5 * step_ms + 0.5 * per : per;
-        }
-        std::vector<Slot *> fin;
-        for (size_t i = 0; i < cs.size(); i++) {
-            Slot &s = *cs[i];
-            Request &q = srv->reqs[s.req];
-            GraphEntry &ge = srv->graphs[q.gid];
-            dfpr_graph *g = ge.g;
-            const Ctl c = srv->ctl_pin[i];
-            *g->ctl_host = c;
-            s.it = c.iterations;
-            const int res = s.base ^ ((c.iterations - s.it0) & 1);
-            if (c.err) {
-                q.res.status = DFPR_E_RANGE;
-                fin.push_back(&s);
-                continue;
-            }
-            if (s.phase32 && (c.phase_end || c.done)) {
-                rc = df_phase_end(g, res, c.done != 0);
-                if (rc) goto out;
-                if (!c.done) {
-                    s.phase32 = 0;
-                    s.it0 = c.iterations;
-                    s.base = res;
-                    s.prev_dr = -1.0;
-                    s.pred = 2;
-                    q.res.refine_sweeps = -c.iterations;   // completed at retirement
-                    continue;
+        // 3. the results of the first lane to finish its oldest chunk; while
+        // the lanes run, look for arrivals that could take a free slot
+        int lane = -1;
+        while (lane < 0) {
+            for (int l = 0; l < kLanes && lane < 0; l++) {
+                if (lanes[l].n == 0) continue;
+                const hipError_t e = hipEventQuery(srv->done[l][lanes[l].oldest().buf]);
+                if (e == hipSuccess) lane = l;
+                else if (e != hipErrorNotReady) {
+                    rc = set_error(DFPR_E_DEVICE, "stream synchronisation failed");
+                    goto out;
                 }
             }
-            if (c.done) {
-                rc = df_finish(g, s.sbase, res, c.iterations);
-                if (rc) goto out;
-                fin.push_back(&s);
-                continue;
+            if (lane >= 0) break;
+            while (next < order.size() && srv->reqs[order[next]].state != 0) next++;
+            int act = 0;
+            for (const Slot &s : slots) act += s.req >= 0;
+            if (next < order.size() && act < srv->max_slots &&
+                srv->reqs[order[next]].arrival_ms <= ms_since(t0)) {
+                // an arrival could start now: admit it before waiting more
+                // (its lane may be idle)
+                break;
             }
-            predict(s, c, ge.p.tol);
+            std::this_thread::yield();
         }
-        if (!fin.empty()) {
-            CtlGather cg{};
-            cg.n = (int32_t)fin.size();
-            for (size_t i = 0; i < fin.size(); i++)
-                cg.src[i] = srv->graphs[srv->reqs[fin[i]->req].gid].g->ctl;
-            cg.dst = srv->ctl_dev;
-            k_gather_ctl<<<1, kBlock, 0, srv->stream>>>(cg);
-            if (hipGetLastError() != hipSuccess ||
-                hipMemcpyAsync(srv->ctl_pin, srv->ctl_dev, fin.size() * sizeof(Ctl),
-                               hipMemcpyDeviceToHost, srv->stream) != hipSuccess ||
-                hipStreamSynchronize(srv->stream) != hipSuccess) {
-                rc = set_error(DFPR_E_DEVICE, "finishing failed on the device");
-                goto out;
+        if (lane < 0) continue;
+        {
+            LaneState &L = lanes[lane];
+            Chunk ch = L.oldest();
+            L.head = (L.head + 1) % kDepth;
+            L.n--;
+            if (lane == 1) {
+                const double chunk_ms =
+                    std::chrono::duration<double, std::milli>(Clock::now() - ch.t).count();
+                const double per = chunk_ms / ch.K;
+                L.step_ms = L.step_ms > 0.0 ? 0.5 * L.step_ms + 0.5 * per : per;
             }
-            const double t = ms_since(t0);
-            for (size_t i = 0; i < fin.size(); i++) {
-                Slot &s = *fin[i];
+            const Ctl *pin = srv->ctl_pin[lane][ch.buf];
+            std::vector<Slot *> fin;
+            std::vector<Ctl> fin_ctl;
+            for (size_t i = 0; i < ch.cs.size(); i++) {
+                Slot &s = *ch.cs[i];
+                // a slot retired or moved to its next phase by an earlier
+                // chunk only ran steps that returned at once here
+                if (s.req < 0 || s.epoch != ch.epoch[i]) continue;
                 Request &q = srv->reqs[s.req];
                 GraphEntry &ge = srv->graphs[q.gid];
-                const Ctl &c = srv->ctl_pin[i];
-                *ge.g->ctl_host = c;
-                q.state = 2;
-                q.res.done_ms = t;
-                if (q.res.status == DFPR_OK) {
-                    q.res.iterations = c.iterations;
-                    q.res.converged = c.converged;
-                    q.res.final_linf = c.final_linf;
-                    q.res.edges_processed = (int64_t)c.edges;
-                    q.res.affected = (int64_t)c.affected;
-                    q.res.refine_sweeps =
-                        q.res.refine_sweeps < 0 ? c.iterations + q.res.refine_sweeps : 0;
-                    done++;
-                } else {
-                    failed++;
+                dfpr_graph *g = ge.g;
+                const Ctl c = pin[i];
+                *g->ctl_host = c;
+                s.it = c.iterations;
+                const int res = s.base ^ ((c.iterations - s.it0) & 1);
+                if (c.err) {
+                    q.res.status = DFPR_E_RANGE;
+                    fin.push_back(&s);
+                    continue;
                 }
-                last_done = t;
-                ge.busy = 0;
-                in_flight -= q.charge;
-                s = Slot();
+                if (s.phase32 && (c.phase_end || c.done)) {
+                    rc = df_phase_end(g, res, c.done != 0);
+                    if (rc) goto out;
+                    if (!c.done) {
+                        s.phase32 = 0;
+                        s.it0 = c.iterations;
+                        s.itq = c.iterations;
+                        s.epoch = ++epochs;
+                        s.base = res;
+                        s.prev_dr = -1.0;
+                        s.pred = 2;
+                        q.res.refine_sweeps = -c.iterations;   // completed at retirement
+                        continue;
+                    }
+                }
+                if (c.done) {
+                    rc = df_finish(g, s.sbase, res, c.iterations);
+                    if (rc) goto out;
+                    fin.push_back(&s);
+                    continue;
+                }
+                predict(s, c, ge.p.tol);
+            }
+            if (!fin.empty()) {
+                // the lane's later chunk, if any, only has steps of finished
+                // slots that return at once (the large lane holds one slot),
+                // so waiting for the stream is short
+                CtlGather cg{};
+                cg.n = (int32_t)fin.size();
+                for (size_t i = 0; i < fin.size(); i++)
+                    cg.src[i] = srv->graphs[srv->reqs[fin[i]->req].gid].g->ctl;
+                cg.dst = srv->ctl_dev[lane][ch.buf];
+                k_gather_ctl<<<1, kBlock, 0, srv->stream[lane]>>>(cg);
+                if (hipGetLastError() != hipSuccess ||
+                    hipMemcpyAsync(srv->ctl_pin[lane][ch.buf], srv->ctl_dev[lane][ch.buf],
+                                   fin.size() * sizeof(Ctl), hipMemcpyDeviceToHost,
+                                   srv->stream[lane]) != hipSuccess ||
+                    hipStreamSynchronize(srv->stream[lane]) != hipSuccess) {
+                    rc = set_error(DFPR_E_DEVICE, "finishing failed on the device");
+                    goto out;
+                }
+                const double t = ms_since(t0);
+                for (size_t i = 0; i < fin.size(); i++) {
+                    Slot &s = *fin[i];
+                    Request &q = srv->reqs[s.req];
+                    GraphEntry &ge = srv->graphs[q.gid];
+                    const Ctl &c = srv->ctl_pin[lane][ch.buf][i];
+                    *ge.g->ctl_host = c;
+                    q.state = 2;
+                    q.res.done_ms = t;
+                    if (q.res.status == DFPR_OK) {
+                        q.res.iterations = c.iterations;
+                        q.res.converged = c.converged;
+                        q.res.final_linf = c.final_linf;
+                        q.res.edges_processed = (int64_t)c.edges;
+                        q.res.affected = (int64_t)c.affected;
+                        q.res.refine_sweeps =
+                            q.res.refine_sweeps < 0 ? c.iterations + q.res.refine_sweeps : 0;
+                        done++;
+                    } else {
+                        failed++;
+                    }
+                    last_done = t;
+                    ge.busy = 0;
+                    in_flight -= q.charge;
+                    s = Slot();
+                }
             }
         }
     }
 out:
     if (rc) {
-        (void)hipStreamSynchronize(srv->stream);
+        for (int l = 0; l < kLanes; l++) (void)hipStreamSynchronize(srv->stream[l]);
         (void)hipStreamSynchronize(srv->astream);
         // requests in flight end with the run's error; later runs do not
         // take them up again
@@ -533,10 +679,16 @@ int dfpr_server_create(int32_t max_slots, int64_t hbm_budget_bytes, dfpr_server 
     dfpr_server *s = new dfpr_server();
     s->max_slots = max_slots;
     s->budget = hbm_budget_bytes;
-    hipError_t e = hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking);
-    if (e == hipSuccess) e = hipStreamCreateWithFlags(&s->astream, hipStreamNonBlocking);
-    if (e == hipSuccess) e = hipMalloc(&s->ctl_dev, kMaxSlots * sizeof(Ctl));
-    if (e == hipSuccess) e = hipHostMalloc(&s->ctl_pin, kMaxSlots * sizeof(Ctl));
+    hipError_t e = hipStreamCreateWithFlags(&s->astream, hipStreamNonBlocking);
+    for (int l = 0; l < kLanes; l++) {
+        if (e == hipSuccess) e = hipStreamCreateWithFlags(&s->stream[l], hipStreamNonBlocking);
+        for (int b = 0; b < kDepth; b++) {
+            if (e == hipSuccess)
+                e = hipEventCreateWithFlags(&s->done[l][b], hipEventDisableTiming);
+            if (e == hipSuccess) e = hipMalloc(&s->ctl_dev[l][b], kMaxSlots * sizeof(Ctl));
+            if (e == hipSuccess) e = hipHostMalloc(&s->ctl_pin[l][b], kMaxSlots * sizeof(Ctl));
+        }
+    }
     if (e != hipSuccess) {
         dfpr_server_free(s);
         return hip_fail(e, "server set-up");
@@ -548,13 +700,17 @@ int dfpr_server_create(int32_t max_slots, int64_t hbm_budget_bytes, dfpr_server 
 void dfpr_server_free(dfpr_server *s)
 {
     if (!s) return;
-    for (hipStream_t st : {s->stream, s->astream})
+    for (hipStream_t st : {s->stream[0], s->stream[1], s->astream})
         if (st) {
             (void)hipStreamSynchronize(st);
             (void)hipStreamDestroy(st);
         }
-    (void)hipFree(s->ctl_dev);
-    (void)hipHostFree(s->ctl_pin);
+    for (int l = 0; l < kLanes; l++)
+        for (int b = 0; b < kDepth; b++) {
+            if (s->done[l][b]) (void)hipEventDestroy(s->done[l][b]);
+            (void)hipFree(s->ctl_dev[l][b]);
+            (void)hipHostFree(s->ctl_pin[l][b]);
+        }
     delete s;
 }
 
@@ -568,6 +724,7 @@ int dfpr_server_add_graph(dfpr_server *s, dfpr_graph *g, const dfpr_params *p, i
         if (x.g == g) return set_error(DFPR_E_ARG, "graph already added");
     ge.g = g;
     ge.bytes = graph_bytes(g);
+    ge.lane = g->m >= kLargeEdges ? 0 : 1;
     if (s->resident + ge.bytes > s->budget)
         return set_error(DFPR_E_NOMEM, "resident graphs exceed the HBM budget");
     DFPR_HIP(hipStreamSynchronize(g->stream));
