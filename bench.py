@@ -276,6 +276,7 @@ def headline_bench(args, dfpr, synth):
         str(f): round(float(np.mean([x[0] for x in v])), 3) for f, v in sorted(per.items())}
 
     achieved = prof.bytes / (prof.ms / 1e3) / 1e9 if prof.ms > 0 else 0.0
+    iters_timed = int(sum(x[1] for v in per.values() for x in v))
     tb = measured_traffic(workload)
     copy_gbs = copy_bandwidth(torch)
     log(f"achievable copy bandwidth {copy_gbs:.0f} GB/s")
@@ -288,7 +289,13 @@ def headline_bench(args, dfpr, synth):
         "traffic": (None if tb is None or prof.ms <= 0 else
                     round(tb / (prof.ms / 1e3 / max(prof.launches, 1)) / 1e9, 1)),
         "traffic_bytes_per_launch": None if tb is None else round(tb, 1),
+        # every launch of the kernel, as rocprofv3 counts them: the
+        # iterations plus the few launches queued after a call converged,
+        # which return at once
         "launches": prof.launches, "avg_launch_us": round(prof.ms * 1e3 / max(prof.launches, 1), 2),
+        # the iterations alone (the returning launches cost ~4 us each)
+        "iterations": iters_timed,
+        "avg_iteration_us": round(prof.ms * 1e3 / max(iters_timed, 1), 2),
         "algorithmic_bytes_per_launch": round(prof.bytes / max(prof.launches, 1), 1),
         "kernel_gteps": round(prof.edges / prof.ms / 1e6, 2) if prof.ms > 0 else None,
         "achievable_copy_GBps": round(copy_gbs, 1),
