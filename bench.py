@@ -69,8 +69,10 @@ def kernel_hash():
 
 
 def measured_traffic(workload):
-    """HBM bytes per iteration launch from committed rocprofv3 counter runs,
-    if they were taken on the current kernel source for this workload."""
+    """HBM bytes per iteration (launches that ran an iteration; those queued
+    after a call converged return at once and move nothing) from committed
+    rocprofv3 counter runs, if they were taken on the current kernel source
+    for this workload."""
     try:
         with open(TRAFFIC_FILE) as f:
             t = json.load(f)
@@ -78,7 +80,7 @@ def measured_traffic(workload):
         return None
     if t.get("kernel_sha") != kernel_hash() or t.get("workload") != workload:
         return None
-    return t.get("bytes_per_launch")
+    return t.get("bytes_per_iteration")
 
 
 def main():
@@ -284,11 +286,12 @@ def headline_bench(args, dfpr, synth):
         "bound": "hbm", "kernel": "k_iter<true, false> (FP64 pull + Delta r + L-inf + expand)",
         "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
         "frac": round(achieved / HBM_PEAK_GBS, 4),
-        # measured HBM bytes per launch (committed counter runs on these
-        # sources) over the same per-launch time as `achieved`
+        # measured HBM bytes (committed counter runs on these sources) over
+        # the same kernel time as `achieved`
         "traffic": (None if tb is None or prof.ms <= 0 else
-                    round(tb / (prof.ms / 1e3 / max(prof.launches, 1)) / 1e9, 1)),
-        "traffic_bytes_per_launch": None if tb is None else round(tb, 1),
+                    round(tb * iters_timed / (prof.ms / 1e3) / 1e9, 1)),
+        "traffic_bytes_per_launch": (None if tb is None else
+                                     round(tb * iters_timed / max(prof.launches, 1), 1)),
         # every launch of the kernel, as rocprofv3 counts them: the
         # iterations plus the few launches queued after a call converged,
         # which return at once

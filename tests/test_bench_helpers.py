@@ -33,8 +33,8 @@ def test_traffic_only_for_the_source_and_workload_measured(tmp_path, monkeypatch
     monkeypatch.setattr(bench, "TRAFFIC_FILE", str(f))
     assert bench.measured_traffic("w") is None                 # no file
     f.write_text(json.dumps({"workload": "w", "kernel_sha": bench.kernel_hash(),
-                             "bytes_per_launch": 123.0}))
+                             "bytes_per_iteration": 123.0}))
     assert bench.measured_traffic("w") == 123.0
     assert bench.measured_traffic("other") is None
-    f.write_text(json.dumps({"workload": "w", "kernel_sha": "0" * 16, "bytes_per_launch": 1.0}))
+    f.write_text(json.dumps({"workload": "w", "kernel_sha": "0" * 16, "bytes_per_iteration": 1.0}))
     assert bench.measured_traffic("w") is None                 # kernel changed since
