@@ -703,7 +703,8 @@ def sweep_bench(args, dfpr, synth, scale=22):
                           "speedup_vs_static": round(ss.ms_device / sd.ms_device, 2),
                           "speedup_vs_naive": round(sn.ms_device / sd.ms_device, 2),
                           "df_l1": l1(Rd, Rr), "naive_l1": l1(Rn, Rr), "static_l1": l1(Rs, Rr),
-                          "df_affected": sd.affected_final}
+                          "df_affected": sd.affected_final, "df_iterations": sd.iterations,
+                          "naive_iterations": sn.iterations, "static_iterations": ss.iterations}
             g.set_ranks(Rd)
             log(f"{key}: {mixes[key]}")
     out["batch_mixes"] = mixes

@@ -51,6 +51,8 @@ struct Ctl {
     uint32_t dense;             // iterations walk the full schedule
     uint32_t force_dense;       // set during a sparse iteration: walk the full
                                 // schedule from the next iteration on
+    uint32_t plain_marks;       // expansions on the class lists mark with plain stores
+                                // (and set force_dense) instead of appending
     uint32_t phase_end;         // the FP32 phase of the precision form is over
     int32_t phase_iters;        // iterations of the current FP32 phase
     double prev_linf;           // Delta R of the previous iteration

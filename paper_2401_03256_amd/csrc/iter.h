@@ -100,6 +100,7 @@ struct Acc {
     double r_max = 0.0;
     unsigned long long c[kCounters] = {0, 0, 0, 0};   // rows, edges, xrows, xedges
     double ftol = 0.0;          // frontier tolerance in effect
+    bool plain = false;         // expansions mark with plain stores (Ctl::plain_marks)
 };
 
 // Sum of the contributions of in-edges idx[k] for k = first, first + step,
@@ -368,15 +369,19 @@ __device__ __forceinline__ void wave_unit(const IterArgs &a, const Hub &hub, con
                 if (lane >= d) incl += y;
             }
             const uint32_t total = __shfl(incl, kWave - 1);
-            if (sparse) expand_rows<true>(a, incl, deg, ob, total, sv);
-            else expand_rows<false>(a, incl, deg, ob, total, sv);
+            if (sparse && !acc.plain) {
+                expand_rows<true>(a, incl, deg, ob, total, sv);
+            } else {
+                if (sparse && lane == 0) a.ctl->force_dense = 1;
+                expand_rows<false>(a, incl, deg, ob, total, sv);
+            }
         }
         unsigned long long q = __ballot(expand && !small);
         while (q) {
             const int l = __ffsll((long long)q) - 1;
             const int32_t w = __shfl(v, l);
             const uint32_t wc = __shfl(oc, l);
-            if (sparse && !heavy_in_sparse(a, wc)) {
+            if (sparse && !acc.plain && !heavy_in_sparse(a, wc)) {
                 mark_out_row<true>(a, w, lane, kWave, sv);
             } else {
                 if (sparse && lane == 0) a.ctl->force_dense = 1;
@@ -410,7 +415,7 @@ __device__ __forceinline__ void block_row(const IterArgs &a, const Hub &hub, int
     __syncthreads();
     if (DF && *flag) {
         const uint32_t sv = a.sbase + (uint32_t)a.it + 1;
-        if (sparse && !heavy_in_sparse(a, a.out_cnt[v])) {
+        if (sparse && !acc.plain && !heavy_in_sparse(a, a.out_cnt[v])) {
             mark_out_row<true>(a, v, threadIdx.x, kBlock, sv);
         } else {
             if (sparse && threadIdx.x == 0) a.ctl->force_dense = 1;
@@ -459,6 +464,7 @@ __device__ __forceinline__ void block_fold(double &dr, double &rm, unsigned long
 // the class-6 rows.
 struct Plan {
     double ftol;                // frontier tolerance in effect
+    uint32_t plain;             // Ctl::plain_marks
     uint32_t cnt[kBins];
     const int32_t *list[kBins]; // class lists (sparse), or NULL: the id range from id0
     uint32_t id0[kBins];
@@ -473,6 +479,7 @@ __device__ __forceinline__ void make_plan(const IterArgs &a, const Ctl *ctl, boo
 {
     // a negative frontier tolerance asks for the call's adaptive choice
     p.ftol = a.ftol >= 0.0 ? a.ftol : ctl->ftol_used;
+    p.plain = ctl->plain_marks;
     for (int b = 0; b < kBins; b++) {
         if (sparse) {
             p.cnt[b] = ctl->snap[par][b];
@@ -571,6 +578,7 @@ __device__ __forceinline__ void iter_body(const IterArgs &a, uint32_t blk, uint3
 
     Acc acc;
     acc.ftol = sh.plan.ftol;
+    acc.plain = sh.plan.plain != 0;
     const int wave = threadIdx.x / kWave;
     auto run_unit = [&](uint32_t u, int k) {
         if (k == kBins - 1) {

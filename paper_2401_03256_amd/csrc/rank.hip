@@ -210,6 +210,7 @@ __global__ void k_reset(Ctl *ctl)
         ctl->done = 0;
         ctl->dense = 0;
         ctl->force_dense = 0;
+        ctl->plain_marks = 0;
         ctl->phase_end = 0;
         ctl->phase_iters = 0;
         ctl->prev_linf = 0.0;
@@ -267,6 +268,12 @@ __global__ void k_snap(Ctl *ctl, int32_t max_iters, uint32_t sparse_limit, int d
             tot += ctl->live[b];
         }
         ctl->dense = (dense || ctl->dense || tot > sparse_limit) ? 1 : 0;
+        // a first frontier with more out-edges than the class lists take
+        // would append most of them in its first expansions, one list
+        // atomic per wave and round on counters that share a cache line;
+        // its expansions mark with plain stores instead, and the call walks
+        // the full schedule from the next iteration on
+        ctl->plain_marks = ctl->reach0 > sparse_limit ? 1 : 0;
         ctl->done = (ctl->err || max_iters <= 0) ? 1 : 0;
         if (mirror) __builtin_memcpy(mirror, ctl, sizeof(Ctl));
     }
