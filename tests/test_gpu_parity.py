@@ -1025,3 +1025,62 @@ def test_adaptive_frontier_tolerance_on_rmat(dfpr):
     assert st.converged and np.max(np.abs(R - Rd)) < TOL_RANK
     with pytest.raises(dfpr.DfprError):
         g.dynamic_frontier(b, p=dfpr.params(frontier_tol=float("nan")))
+
+
+def _wide_first_frontier_batch(n, src, dst, limit):
+    """A deletion-only batch whose claimed sources reach few out-edges (the
+    first walk stays on the class lists) while the vertices the marking
+    marks have more out-edges than `limit`: deleted edges are sampled from
+    existing ones, so their sources lean to hubs.  Found by a seeded search
+    on the CPU; returns the batch and the marking's two out-edge sums."""
+    outdeg = np.bincount(src, minlength=n) + 1           # with the self-loop
+    for seed in range(200):
+        for nd in (2, 3, 4):
+            b = synth.batch_sequence(src, dst, n, [(nd, 0)], seed=1000 + seed)[0]
+            # after the deletions each source has one out-edge fewer
+            reach = int(outdeg[np.unique(b.del_src)].sum()) - nd
+            if reach + nd > 0.8 * limit:
+                continue
+            marks = np.zeros(n, bool)
+            for u in np.unique(b.del_src):
+                marks[_out_row(src, dst, u)] = True
+                marks[u] = True
+            marks[b.del_dst] = True
+            reach0 = int(outdeg[marks].sum())
+            if marks.sum() < 0.8 * limit and reach0 > 2 * limit:
+                return b, reach, reach0
+    raise AssertionError("no batch with a wide first frontier found")
+
+
+def _out_row(src, dst, u):
+    return dst[src == u]
+
+
+def test_wide_first_frontier_marks_plainly(dfpr):
+    # R-MAT scale 16: class-list limit max(4096, n/64) = 4096.  The first
+    # iteration walks the class lists, and its expansions mark with plain
+    # stores and move the call to the full schedule (the marking's
+    # out-edge sum exceeds the limit); ranks and final marks against the
+    # oracle as in any other call
+    n, src, dst = synth.rmat(16, 16, seed=21)
+    limit = max(4096, n // 64)
+    b, reach, reach0 = _wide_first_frontier_batch(n, src, dst, limit)
+    _say(f"wide first frontier: {b.size} deletions, sources reach {reach}, marks reach {reach0}")
+    g, o = _pair(dfpr, n, src, dst)
+    p = dfpr.params(tol=1e-10, frontier_tol=1e-13)
+    R0, _ = g.static(p)
+    R0o, _ = o.static()
+    assert g.apply_batch(b) == o.apply_batch(b)
+    f0 = o.mark_initial(b)
+    assert np.array_equal(g.mark_affected(b), f0)
+    R, st = g.dynamic_frontier(b, p=p)
+    Ro, sto, _, f1, ch = o.dynamic_frontier(b, R0o, frontier_tol=1e-13, return_flags=True,
+                                            return_changes=True)
+    assert st.converged and sto.converged
+    assert st.affected_initial == int(f0.sum())
+    assert np.max(np.abs(R - Ro)) < TOL_RANK
+    check_final_marks(g.affected(), f1, ch, *o.csr(out=False), 1e-13, "wide first frontier",
+                      st.iterations == sto.iterations)
+    # the same call again from the same previous ranks: bitwise equal
+    Rd, _ = g.dynamic_frontier(b, prev=R0, p=p)
+    assert np.array_equal(R, Rd)
