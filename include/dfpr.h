@@ -127,8 +127,8 @@ typedef struct {
     int64_t vertices_processed; /* rank updates, summed over iterations        */
     int64_t edges_processed;    /* in-edges gathered, summed over iterations   */
     double ms_mark;             /* part of ms_device before the first
-                                   iteration: batch staging, starting ranks,
-                                   class schedule, and the initial marking
+                                   iteration: batch staging, starting ranks
+                                   and the initial marking
                                    (Dynamic Frontier) or the reachability
                                    search (Dynamic Traversal)                 */
     double ms_iter;             /* the rest of ms_device: iterations (FP32

@@ -459,8 +459,8 @@ __device__ __forceinline__ void block_fold(double &dr, double &rm, unsigned long
 }
 
 // Work of one iteration: per class, the list and its length; wave units
-// of classes 5..0 and then of the self-loop-only rows (their own schedule
-// bin; class lists hold them in class 0), in that order; block units are
+// of classes 5..0 and then of the self-loop-only rows (their own id
+// range; class lists hold them in class 0), in that order; block units are
 // the class-6 rows.
 struct Plan {
     double ftol;                // frontier tolerance in effect

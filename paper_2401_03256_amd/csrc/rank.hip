@@ -36,8 +36,11 @@
 // marking appends new vertices to per-class lists (sparse mode).  Once the
 // lists pass a size limit, iterations walk every class's id range and skip
 // rows whose stamp is out of range (dense mode, the "full schedule"); marks
-// are then plain stores.  Neither walk needs rebuilding when a batch
-// changes in-degrees.
+// are then plain stores.  Expansions that would append more than the lists
+// take (a row with a very long out-row, or a first frontier whose out-rows
+// together pass the limit) also mark with plain stores, and the call walks
+// the full schedule from the next iteration on.  Neither walk needs
+// rebuilding when a batch changes in-degrees.
 //
 // Ranks are double-buffered (synchronous form, Section 4.2).  Both buffers
 // hold identical values between calls; an iteration reads one and writes
