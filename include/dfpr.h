@@ -379,6 +379,14 @@ typedef struct {
 int dfpr_server_create(int32_t max_slots, int64_t hbm_budget_bytes, dfpr_server **out);
 void dfpr_server_free(dfpr_server *s);
 
+/* Requests on graphs of at least large_edges edges (self-loops included)
+ * run in the server's large lane: one at a time, in arrival order, on a
+ * stream of their own; all other requests share coalesced steps in the
+ * small lane.  Default 2^25 (a graph whose full sweep fills an MI355X).
+ * Applies to the graphs already added and to later ones.  DFPR_E_ARG for
+ * large_edges < 1. */
+int dfpr_server_set_large_edges(dfpr_server *s, int64_t large_edges);
+
 /* Add a resident graph (parameters p, NULL = defaults; p->precision picks
  * FP64 or the FP32 form for its updates).  DFPR_E_NOMEM if the resident
  * graphs would exceed the budget.  *graph_id receives its index. */

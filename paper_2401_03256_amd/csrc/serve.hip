@@ -182,6 +182,7 @@ static double pct(std::vector<double> v, double q)
 
 struct dfpr_server {
     int32_t max_slots = 1;
+    int64_t large_edges = dfpr::kLargeEdges;   // graphs this large take the large lane
     int64_t budget = 0;
     int64_t resident = 0;
     std::vector<dfpr::GraphEntry> graphs;
@@ -714,6 +715,14 @@ void dfpr_server_free(dfpr_server *s)
     delete s;
 }
 
+int dfpr_server_set_large_edges(dfpr_server *s, int64_t large_edges)
+{
+    if (!s || large_edges < 1) return set_error(DFPR_E_ARG, "need a server and large_edges >= 1");
+    s->large_edges = large_edges;
+    for (GraphEntry &ge : s->graphs) ge.lane = ge.g->m >= large_edges ? 0 : 1;
+    return DFPR_OK;
+}
+
 int dfpr_server_add_graph(dfpr_server *s, dfpr_graph *g, const dfpr_params *p, int32_t *graph_id)
 {
     if (!s || !g) return set_error(DFPR_E_ARG, "NULL argument");
@@ -724,7 +733,7 @@ int dfpr_server_add_graph(dfpr_server *s, dfpr_graph *g, const dfpr_params *p, i
         if (x.g == g) return set_error(DFPR_E_ARG, "graph already added");
     ge.g = g;
     ge.bytes = graph_bytes(g);
-    ge.lane = g->m >= kLargeEdges ? 0 : 1;
+    ge.lane = g->m >= s->large_edges ? 0 : 1;
     if (s->resident + ge.bytes > s->budget)
         return set_error(DFPR_E_NOMEM, "resident graphs exceed the HBM budget");
     DFPR_HIP(hipStreamSynchronize(g->stream));

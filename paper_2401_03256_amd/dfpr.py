@@ -42,7 +42,7 @@ EXPORTED = [
     "dfpr_export_csr", "dfpr_last_error", "dfpr_profile_reset", "dfpr_profile_read",
     "dfpr_pagerank_dynamic_traversal", "dfpr_mark_reachable",
     "dfpr_server_create", "dfpr_server_free", "dfpr_server_add_graph", "dfpr_server_submit",
-    "dfpr_server_run", "dfpr_server_result",
+    "dfpr_server_run", "dfpr_server_result", "dfpr_server_set_large_edges",
 ]
 
 
@@ -177,6 +177,7 @@ def lib():
     L.dfpr_server_create.argtypes = [_I32, _I64, ctypes.POINTER(_P)]
     L.dfpr_server_free.argtypes = [_P]
     L.dfpr_server_free.restype = None
+    L.dfpr_server_set_large_edges.argtypes = [_P, _I64]
     L.dfpr_server_add_graph.argtypes = [_P, _P, _P, _P]
     L.dfpr_server_submit.argtypes = [_P, _I32, ctypes.c_double, *batch, _P]
     L.dfpr_server_run.argtypes = [_P, _P]
@@ -453,6 +454,10 @@ class Server:
             self.close()
         except Exception:
             pass
+
+    def set_large_edges(self, edges: int) -> None:
+        """Graphs of at least `edges` edges run in the large lane."""
+        _check(lib().dfpr_server_set_large_edges(self._h, int(edges)))
 
     def add_graph(self, graph: Graph, p: Params | None = None) -> int:
         gid = _I32()

@@ -553,6 +553,56 @@ def test_serving_results_equal_alone_and_in_the_mix(dfpr):
         assert np.array_equal(g.ranks(), alone[gid][0])
 
 
+def test_serving_large_lane_in_order_one_at_a_time(dfpr):
+    # the same workload with half the graphs moved to the large lane (by
+    # lowering its edge threshold): every result still equals the plain
+    # calls bitwise, and the large lane runs its requests one at a time, in
+    # arrival order, beside the coalesced small lane
+    work = _serving_workload()
+    alone = []
+    for n, s, d, prec, batches in work:
+        g = dfpr.Graph(n, s, d)
+        p = dfpr.params(frontier_tol=1e-13, precision=prec)
+        g.static(dfpr.params(frontier_tol=1e-13))
+        for b in batches:
+            g.apply_batch(b)
+            g.dynamic_frontier(b, p=p)
+        alone.append(g.ranks())
+        g.close()
+    graphs = []
+    srv = dfpr.Server(max_slots=4)
+    for n, s, d, prec, batches in work:
+        g = dfpr.Graph(n, s, d)
+        g.static(dfpr.params(frontier_tol=1e-13))
+        graphs.append((g, g.m))
+    threshold = sorted(m for _, m in graphs)[len(graphs) // 2]
+    srv.set_large_edges(threshold)
+    large = [m >= threshold for _, m in graphs]
+    assert 0 < sum(large) < len(large)
+    gids = [srv.add_graph(g, dfpr.params(frontier_tol=1e-13, precision=w[3]))
+            for (g, _), w in zip(graphs, work)]
+    rids = []
+    for k in range(4):
+        for gid, w in zip(gids, work):
+            rids.append((gid, srv.submit(gid, 0.0, w[4][k])))
+    st = srv.run()
+    assert st["completed"] == len(rids) and st["failed"] == 0
+    for gid, rid in rids:
+        r = srv.result(rid)
+        assert r["status"] == 0 and r["converged"]
+    for (g, _), R in zip(graphs, alone):
+        assert np.array_equal(g.ranks(), R)
+    # large-lane requests: admitted in submission order (all arrive at 0),
+    # each after the previous one finished
+    big = [srv.result(rid) for gid, rid in rids if large[gid]]
+    for a, b in zip(big, big[1:]):
+        assert b["admit_ms"] >= a["done_ms"]
+    # the small lane ran beside it
+    small = [srv.result(rid) for gid, rid in rids if not large[gid]]
+    assert any(s["admit_ms"] < big[-1]["done_ms"] and s["done_ms"] > big[0]["admit_ms"]
+               for s in small)
+
+
 def test_serving_budget_limits_concurrency(dfpr):
     n, s, d = synth.rmat(10, 16, seed=5)
     gs = []
