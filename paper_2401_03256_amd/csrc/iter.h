@@ -640,33 +640,9 @@ __device__ __forceinline__ void iter_body(const IterArgs &a, uint32_t blk, uint3
 __device__ __forceinline__ void final_body(const IterArgs &a, bool df, bool f32, FinalShared &sh, bool last)
 {
     Ctl *ctl = a.ctl;
+    if (ctl->done || (f32 && ctl->phase_end)) return;
     const int par = a.it & 1;
-    // Thread 0 reads every control-block field the step needs before the
-    // slots, not after the fold, so that the step waits for one round of
-    // loads.  A call (or FP32 phase) that has already ended left its slots
-    // clear, since its iterations return before writing them: folding and
-    // clearing them again changes nothing.
-    bool ended = false, was_dense = false, force = false;
-    uint32_t live[kBins], seen[kBins];
-    unsigned long long tot[kCounters + 1];
-    int32_t piters = 0;
-    double prev = 0.0;
-    if (threadIdx.x == 0) {
-        ended = ctl->done || (f32 && ctl->phase_end);
-        was_dense = ctl->dense != 0;
-        force = ctl->force_dense != 0;
-        for (int b = 0; b < kBins; b++) {
-            live[b] = ctl->live[b];
-            seen[b] = ctl->snap[par][b];
-        }
-        tot[0] = ctl->verts;
-        tot[1] = ctl->edges;
-        tot[2] = ctl->xverts;
-        tot[3] = ctl->xedges;
-        tot[4] = ctl->marked;
-        piters = ctl->phase_iters;
-        prev = ctl->prev_linf;
-    }
+    const bool sparse = df && !ctl->dense;
     double dr = 0.0, rm = 0.0;
     unsigned long long c[kCounters] = {0, 0, 0, 0};
     // each thread reads its slots and clears them for the next iteration
@@ -682,48 +658,42 @@ __device__ __forceinline__ void final_body(const IterArgs &a, bool df, bool f32,
     }
     block_fold<kFinalWaves>(dr, rm, c, sh.wdr, sh.wrm, sh.wc);
     if (threadIdx.x == 0) {
-        sh.copy = 0;
-        if (!ended) {
-            const bool sparse = df && !was_dense;
-            ctl->verts = tot[0] + c[0];
-            ctl->edges = tot[1] + c[1];
-            ctl->xverts = tot[2] + c[2];
-            ctl->xedges = tot[3] + c[3];
-            ctl->iterations = a.it + 1;
-            ctl->final_linf = dr;
-            ctl->final_rmax = rm;
-            bool done = false;
-            if (sparse) {
-                unsigned long long before = 0, after = 0;
-                for (int b = 0; b < kBins; b++) {
-                    before += seen[b];
-                    after += live[b];
-                    ctl->snap[par ^ 1][b] = live[b];
-                }
-                ctl->marked = tot[4] + (after - before);
-                if (after > a.sparse_limit || force) ctl->dense = 1;
+        ctl->verts += c[0];
+        ctl->edges += c[1];
+        ctl->xverts += c[2];
+        ctl->xedges += c[3];
+        ctl->iterations = a.it + 1;
+        ctl->final_linf = dr;
+        ctl->final_rmax = rm;
+        if (sparse) {
+            unsigned long long before = 0, after = 0;
+            for (int b = 0; b < kBins; b++) {
+                const uint32_t l = ctl->live[b];
+                before += ctl->snap[par][b];
+                after += l;
+                ctl->snap[par ^ 1][b] = l;
             }
-            if (f32) {
-                // FP32 contributions carry a relative rounding error of 2^-24;
-                // changes below about 2^-22 of the largest rank are noise.  A
-                // Delta R that stops falling counts as a stall only near that
-                // floor (early on it can rise while the frontier grows).
-                const double floor32 = rm * 0x1p-22;
-                const bool stalled = piters >= 3 && dr >= 0.97 * prev && dr <= rm * 0x1p-16;
-                ctl->phase_iters = piters + 1;
-                const bool phase_end = dr <= a.tol || dr <= floor32 || stalled;
-                if (phase_end) ctl->phase_end = 1;
-                done = a.it + 1 >= a.max_iters;
-                sh.copy = a.mirror && (last || done || phase_end);
-            } else {
-                const bool conv = dr <= a.tol;
-                if (conv) ctl->converged = 1;
-                done = conv || a.it + 1 >= a.max_iters;
-                sh.copy = a.mirror && (last || done);
-            }
-            if (done) ctl->done = 1;
-            ctl->prev_linf = dr;
+            ctl->marked += after - before;
+            if (after > a.sparse_limit || ctl->force_dense) ctl->dense = 1;
         }
+        if (f32) {
+            // FP32 contributions carry a relative rounding error of 2^-24;
+            // changes below about 2^-22 of the largest rank are noise.  A
+            // Delta R that stops falling counts as a stall only near that
+            // floor (early on it can rise while the frontier grows).
+            const double floor32 = rm * 0x1p-22;
+            const bool stalled = ctl->phase_iters >= 3 && dr >= 0.97 * ctl->prev_linf &&
+                                 dr <= rm * 0x1p-16;
+            ctl->phase_iters += 1;
+            if (dr <= a.tol || dr <= floor32 || stalled) ctl->phase_end = 1;
+            if (a.it + 1 >= a.max_iters) ctl->done = 1;
+        } else {
+            const bool conv = dr <= a.tol;
+            if (conv) ctl->converged = 1;
+            if (conv || a.it + 1 >= a.max_iters) ctl->done = 1;
+        }
+        ctl->prev_linf = dr;
+        sh.copy = a.mirror && (last || ctl->done || (f32 && ctl->phase_end));
     }
     __syncthreads();
     if (sh.copy && threadIdx.x < kWave) {
