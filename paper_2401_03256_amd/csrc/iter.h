@@ -530,10 +530,11 @@ struct IterShared {
     unsigned long long wc[kWavesPerBlock][kCounters];
 };
 
-// Threads of the per-iteration fold.  Its time is mostly the dependent
-// loads of the control block, not the fold: 1024 threads (one round of
-// loads for a full grid) were no faster on R-MAT scale 22 and cost ~3 us
-// per iteration more on small frontiers.
+// Threads of the per-iteration fold.  Its time is the launch and one round
+// trip to the slots, not the fold: 1024 threads (one round of loads for a
+// full grid) were no faster on R-MAT scale 22 and cost ~3 us per iteration
+// more on small frontiers, and loading the control-block fields beside the
+// slots left it at 4.3 us.
 #ifndef DFPR_FINAL_THREADS
 #define DFPR_FINAL_THREADS 256
 #endif
