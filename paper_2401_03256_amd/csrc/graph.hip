@@ -23,6 +23,12 @@ namespace dfpr {
 #define DFPR_GRID_PER_CU 32
 #endif
 constexpr int kGridPerCU = DFPR_GRID_PER_CU;
+// Workgroups per CU of the wide full-schedule kernel (12 waves each, two
+// resident per CU): about as many waves in all as the grid above.
+#ifndef DFPR_WIDE_GRID_PER_CU
+#define DFPR_WIDE_GRID_PER_CU 11
+#endif
+constexpr int kWideGridPerCU = DFPR_WIDE_GRID_PER_CU;
 
 static thread_local std::string g_last_error;
 
@@ -420,7 +426,10 @@ int dfpr_load_graph(int32_t n, int64_t m, const int32_t *src, const int32_t *dst
         (void)hipGetDevice(&g->device);
         hipDeviceProp_t prop;
         if (hipGetDeviceProperties(&prop, g->device) == hipSuccess && prop.multiProcessorCount > 0)
+        {
             g->grid = std::min(kMaxGrid, prop.multiProcessorCount * kGridPerCU);
+            g->grid_wide = std::min(kMaxGrid, prop.multiProcessorCount * kWideGridPerCU);
+        }
         int coop = 0;
         if (hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, g->device) ==
             hipSuccess)

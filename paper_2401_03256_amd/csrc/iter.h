@@ -98,7 +98,9 @@ __device__ __forceinline__ int class_of_id(const IterArgs &a, int32_t v)
 struct Acc {
     double dr_max = 0.0;
     double r_max = 0.0;
-    unsigned long long c[kCounters] = {0, 0, 0, 0};   // rows, edges, xrows, xedges
+    // rows, edges, xrows, xedges of this lane: each below the graph's edge
+    // slots (under 2^32), so 32 bits per lane; widened for the fold
+    uint32_t c[kCounters] = {0, 0, 0, 0};
     double ftol = 0.0;          // frontier tolerance in effect
     bool plain = false;         // expansions mark with plain stores (Ctl::plain_marks)
 };
@@ -395,31 +397,44 @@ __device__ __forceinline__ void wave_unit(const IterArgs &a, const Hub &hub, con
 // One row of more than 1024 in-edges, the whole workgroup.  All threads
 // call it with the same v.
 template <bool DF, bool F32>
-__device__ __forceinline__ void block_row(const IterArgs &a, const Hub &hub, int32_t v, bool check,
-                                 bool sparse, Acc &acc, double *red, int *flag)
+__device__ __forceinline__ void block_row(const IterArgs &a, const Hub &hub, int32_t v, bool valid,
+                                 bool check, bool sparse, Acc &acc, double *red, int *flag)
 {
-    if (DF && check) {
+    // A row of this class is summed by kBlock threads; a workgroup of more
+    // threads sums one such row per kBlock of them (its sub-blocks), each
+    // with the same partition and order as a kBlock workgroup.  Every
+    // thread reaches the barriers, whether its sub-block has a row or not.
+    const uint32_t t = threadIdx.x % kBlock;
+    bool active = valid;
+    if (active && DF && check) {
         const uint32_t st = a.stamp[v];
-        if (!(st >= a.sbase && st <= a.sbase + (uint32_t)a.it)) return;   // uniform
+        active = st >= a.sbase && st <= a.sbase + (uint32_t)a.it;
     }
-    const uint32_t beg = a.in_beg[v], cnt = a.in_cnt[v];
-    double s = gather_sum<F32>(a, hub, a.in_idx + beg, threadIdx.x, kBlock, cnt);
+    uint32_t cnt = 0;
+    if (active) {
+        const uint32_t beg = a.in_beg[v];
+        cnt = a.in_cnt[v];
+        double s = gather_sum<F32>(a, hub, a.in_idx + beg, t, kBlock, cnt);
 #pragma unroll
-    for (int off = kWave / 2; off > 0; off >>= 1) s += __shfl_xor(s, off, kWave);
-    if (lane_id() == 0) red[threadIdx.x / kWave] = s;
+        for (int off = kWave / 2; off > 0; off >>= 1) s += __shfl_xor(s, off, kWave);
+        if (lane_id() == 0) red[t / kWave] = s;
+    }
     __syncthreads();
-    if (threadIdx.x == 0) {
-        const double t = ((red[0] + red[1]) + red[2]) + red[3];
-        *flag = finish_row<DF, F32>(a, v, cnt, t, a.Rc[v], a.out_cnt[v], acc) ? 1 : 0;
+    if (t == 0) {
+        *flag = 0;
+        if (active) {
+            const double r = ((red[0] + red[1]) + red[2]) + red[3];
+            *flag = finish_row<DF, F32>(a, v, cnt, r, a.Rc[v], a.out_cnt[v], acc) ? 1 : 0;
+        }
     }
     __syncthreads();
     if (DF && *flag) {
         const uint32_t sv = a.sbase + (uint32_t)a.it + 1;
         if (sparse && !acc.plain && !heavy_in_sparse(a, a.out_cnt[v])) {
-            mark_out_row<true>(a, v, threadIdx.x, kBlock, sv);
+            mark_out_row<true>(a, v, t, kBlock, sv);
         } else {
-            if (sparse && threadIdx.x == 0) a.ctl->force_dense = 1;
-            mark_out_row<false>(a, v, threadIdx.x, kBlock, sv);
+            if (sparse && t == 0) a.ctl->force_dense = 1;
+            mark_out_row<false>(a, v, t, kBlock, sv);
         }
     }
     __syncthreads();
@@ -515,20 +530,24 @@ __device__ __forceinline__ void make_plan(const IterArgs &a, const Ctl *ctl, boo
 
 // Workgroups that have work in an iteration: 0 .. active-1.  With no work
 // at all, workgroup 0 alone records the (empty) iteration.
+template <int NW = kWavesPerBlock>
 __device__ __forceinline__ uint32_t active_blocks(const Plan &p, uint32_t grid)
 {
-    const uint32_t wblocks = (p.nwu + kWavesPerBlock - 1) / kWavesPerBlock;
-    return max(1u, max(min(grid, p.nbu), min(grid, wblocks)));
+    constexpr uint32_t S = NW / kWavesPerBlock;    // rows of the block class at once
+    const uint32_t wblocks = (p.nwu + NW - 1) / NW;
+    return max(1u, max(min(grid, (p.nbu + S - 1) / S), min(grid, wblocks)));
 }
 
 // Shared memory of one workgroup of an iteration.
-struct IterShared {
+template <int NW = kWavesPerBlock>
+struct IterSharedT {
     Plan plan;
-    double red[kWavesPerBlock];
-    int flag;
-    double wdr[kWavesPerBlock], wrm[kWavesPerBlock];
-    unsigned long long wc[kWavesPerBlock][kCounters];
+    double red[NW];
+    int flag[NW / kWavesPerBlock];
+    double wdr[NW], wrm[NW];
+    unsigned long long wc[NW][kCounters];
 };
+using IterShared = IterSharedT<>;
 
 // Threads of the per-iteration fold.  Its time is the launch and one round
 // trip to the slots, not the fold: 1024 threads (one round of loads for a
@@ -551,9 +570,9 @@ struct FinalShared {
 // One workgroup's share of an iteration of one graph: workgroup blk of the
 // G workgroups given to the graph.  Its results are folded into slot
 // blk mod kFoldSlots.
-template <bool DF, bool F32>
-__device__ __forceinline__ void iter_body(const IterArgs &a, uint32_t blk, uint32_t G, IterShared &sh,
-                                 double *hub_lds = nullptr)
+template <bool DF, bool F32, int NW = kWavesPerBlock>
+__device__ __forceinline__ void iter_body(const IterArgs &a, uint32_t blk, uint32_t G,
+                                 IterSharedT<NW> &sh, double *hub_lds = nullptr)
 {
     const Ctl *ctl = a.ctl;
     if (ctl->done || (F32 && ctl->phase_end)) return;
@@ -562,7 +581,7 @@ __device__ __forceinline__ void iter_body(const IterArgs &a, uint32_t blk, uint3
     const bool check = DF && !sparse;
     if (threadIdx.x == 0) make_plan(a, ctl, sparse, DF, par, sh.plan);
     __syncthreads();
-    if (blk >= active_blocks(sh.plan, G)) return;
+    if (blk >= active_blocks<NW>(sh.plan, G)) return;
     const uint32_t nbu = sh.plan.nbu, nwu = sh.plan.nwu;
     // a sweep over the full schedule reads the hub contributions from LDS
     Hub hub{hub_lds, reinterpret_cast<const float *>(hub_lds), 0u};
@@ -570,9 +589,9 @@ __device__ __forceinline__ void iter_body(const IterArgs &a, uint32_t blk, uint3
         hub.n = min(a.hub, (uint32_t)a.n);
         if (F32) {
             float *f = reinterpret_cast<float *>(hub_lds);
-            for (uint32_t k = threadIdx.x; k < hub.n; k += kBlock) f[k] = a.C32c[k];
+            for (uint32_t k = threadIdx.x; k < hub.n; k += NW * kWave) f[k] = a.C32c[k];
         } else {
-            for (uint32_t k = threadIdx.x; k < hub.n; k += kBlock) hub_lds[k] = a.Cc[k];
+            for (uint32_t k = threadIdx.x; k < hub.n; k += NW * kWave) hub_lds[k] = a.Cc[k];
         }
         __syncthreads();
     }
@@ -603,10 +622,16 @@ __device__ __forceinline__ void iter_body(const IterArgs &a, uint32_t blk, uint3
         }
     };
     const int32_t *blist = sh.plan.list[kBins - 1];
-    for (uint32_t u = blk; u < nbu; u += G)
-        block_row<DF, F32>(a, hub, blist ? blist[u] : (int32_t)(sh.plan.id0[kBins - 1] + u), check,
-                           sparse, acc, sh.red, &sh.flag);
-    for (uint32_t u = blk * kWavesPerBlock + wave; u < nwu; u += G * kWavesPerBlock) {
+    constexpr uint32_t S = NW / kWavesPerBlock;     // sub-blocks of kBlock threads
+    const uint32_t sub = threadIdx.x / kBlock;
+    for (uint32_t u0 = blk * S; u0 < nbu; u0 += G * S) {
+        const uint32_t u = u0 + sub;
+        const bool valid = u < nbu;
+        const int32_t v = !valid ? 0 : blist ? blist[u] : (int32_t)(sh.plan.id0[kBins - 1] + u);
+        block_row<DF, F32>(a, hub, v, valid, check, sparse, acc, sh.red + sub * kWavesPerBlock,
+                           sh.flag + sub);
+    }
+    for (uint32_t u = blk * NW + wave; u < nwu; u += G * NW) {
         int k = 0;
         while (k + 1 < kBins && u >= sh.plan.ustart[k + 1]) k++;
         run_unit(u, k);
@@ -616,7 +641,7 @@ __device__ __forceinline__ void iter_body(const IterArgs &a, uint32_t blk, uint3
     unsigned long long c[kCounters];
 #pragma unroll
     for (int j = 0; j < kCounters; j++) c[j] = acc.c[j];
-    block_fold(dr, rm, c, sh.wdr, sh.wrm, sh.wc);
+    block_fold<NW>(dr, rm, c, sh.wdr, sh.wrm, sh.wc);
     if (threadIdx.x == 0) {
         // non-negative doubles order like their bit patterns
         const uint32_t slot = blk % kFoldSlots;

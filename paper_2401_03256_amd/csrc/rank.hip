@@ -72,6 +72,33 @@ __global__ __launch_bounds__(kBlock, DFPR_ITER_WAVES_PER_SIMD) void k_iter(IterA
 #endif
 }
 
+// Static and Naive-dynamic sweeps (Eq. 1 over every vertex) in workgroups
+// of kWideWaves waves, two per CU: the same waves per SIMD as k_iter, with
+// one LDS copy of the first kWideHub contributions per kWideWaves waves
+// instead of one of kHubRows per four, so that about 34% of the gathers on
+// R-MAT scale 22 read LDS instead of 18% (4% less time per sweep).  Results
+// are bitwise those of k_iter: block-class rows keep their kBlock partition
+// (see block_row).
+#ifndef DFPR_WIDE
+#define DFPR_WIDE 1
+#endif
+#ifndef DFPR_WIDE_BOUND
+#define DFPR_WIDE_BOUND 6
+#endif
+#ifndef DFPR_WIDE_HUB
+#define DFPR_WIDE_HUB 9216
+#endif
+constexpr int kWideWaves = 12;
+constexpr int kWideThreads = kWideWaves * kWave;
+constexpr uint32_t kWideHub = DFPR_WIDE_HUB;
+
+__global__ __launch_bounds__(kWideThreads, DFPR_WIDE_BOUND) void k_iter_wide(IterArgs a)
+{
+    __shared__ IterSharedT<kWideWaves> sh;
+    __shared__ double hub[kWideHub];
+    iter_body<false, false, kWideWaves>(a, blockIdx.x, gridDim.x, sh, hub);
+}
+
 // After each iteration (one workgroup): fold the slots the iteration's
 // workgroups left, decide convergence or the cap, and prepare the next
 // iteration.  The launch boundary orders it after k_iter.
@@ -929,6 +956,11 @@ static int run_loop(dfpr_graph *g, const dfpr_params &p, bool df, bool f32, uint
     int target = 8, cap = 4;
     bool stop = false;
     uint32_t gsz = (uint32_t)g->grid;
+    // Static and Naive-dynamic sweeps (synchronous FP64) run the wide
+    // kernel.  Dynamic Frontier iterations on the full schedule gained
+    // nothing from it on R-MAT scale 22 (whole calls within 0.3%), so they
+    // stay on k_iter.
+    const bool wide = DFPR_WIDE && !f32 && !async && !df;
     double prev_dr = -1.0;
     int prev_it = it0;
     *res_buf = base;
@@ -968,7 +1000,13 @@ static int run_loop(dfpr_graph *g, const dfpr_params &p, bool df, bool f32, uint
             a.C32n = g->C32[src ^ 1];
             a.it = i;
             if (g->prof.enabled) DFPR_HIP(hipEventRecord(ev[2 * j], g->stream));
-            if (!df) k_iter<false, false><<<gsz, kBlock, 0, g->stream>>>(a);
+            if (wide) {
+                IterArgs aw = a;
+                aw.hub = a.hub ? kWideHub : 0u;
+                const uint32_t gw = (uint32_t)g->grid_wide;
+                k_iter_wide<<<gw, kWideThreads, 0, g->stream>>>(aw);
+            }
+            else if (!df) k_iter<false, false><<<gsz, kBlock, 0, g->stream>>>(a);
             else if (f32) k_iter<true, true><<<gsz, kBlock, 0, g->stream>>>(a);
             else k_iter<true, false><<<gsz, kBlock, 0, g->stream>>>(a);
             if (g->prof.enabled) DFPR_HIP(hipEventRecord(ev[2 * j + 1], g->stream));
