@@ -190,7 +190,8 @@ struct dfpr_graph {
     int busy = 0;
     int device = 0;                   // the HIP device the graph lives on
     int grid = 1024;                  // iteration-kernel workgroups
-    int grid_wide = 1024;             //   ... of the wide full-schedule kernel
+    int grid_wide = 1024;             //   ... of the wide full-sweep kernel
+    int grid_wide_df = 1024;          //   ... of the wide Dynamic Frontier kernel
     int coop = 0;                     // the device takes cooperative launches
     uint32_t sparse_limit = 0;        // frontier size that switches to the full schedule
 };

@@ -23,12 +23,17 @@ namespace dfpr {
 #define DFPR_GRID_PER_CU 32
 #endif
 constexpr int kGridPerCU = DFPR_GRID_PER_CU;
-// Workgroups per CU of the wide full-schedule kernel (12 waves each, two
-// resident per CU): about as many waves in all as the grid above.
+// Workgroups per CU of the wide full-schedule kernels: 12-wave sweeps (two
+// resident per CU; 11 beat 8 and 16) and 8-wave Dynamic Frontier
+// iterations (three resident per CU).
 #ifndef DFPR_WIDE_GRID_PER_CU
 #define DFPR_WIDE_GRID_PER_CU 11
 #endif
+#ifndef DFPR_WIDE_DF_GRID_PER_CU
+#define DFPR_WIDE_DF_GRID_PER_CU 16
+#endif
 constexpr int kWideGridPerCU = DFPR_WIDE_GRID_PER_CU;
+constexpr int kWideDfGridPerCU = DFPR_WIDE_DF_GRID_PER_CU;
 
 static thread_local std::string g_last_error;
 
@@ -429,6 +434,7 @@ int dfpr_load_graph(int32_t n, int64_t m, const int32_t *src, const int32_t *dst
         {
             g->grid = std::min(kMaxGrid, prop.multiProcessorCount * kGridPerCU);
             g->grid_wide = std::min(kMaxGrid, prop.multiProcessorCount * kWideGridPerCU);
+            g->grid_wide_df = std::min(kMaxGrid, prop.multiProcessorCount * kWideDfGridPerCU);
         }
         int coop = 0;
         if (hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, g->device) ==

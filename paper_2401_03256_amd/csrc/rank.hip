@@ -72,31 +72,35 @@ __global__ __launch_bounds__(kBlock, DFPR_ITER_WAVES_PER_SIMD) void k_iter(IterA
 #endif
 }
 
-// Static and Naive-dynamic sweeps (Eq. 1 over every vertex) in workgroups
-// of kWideWaves waves, two per CU: the same waves per SIMD as k_iter, with
-// one LDS copy of the first kWideHub contributions per kWideWaves waves
-// instead of one of kHubRows per four, so that about 34% of the gathers on
-// R-MAT scale 22 read LDS instead of 18% (4% less time per sweep).  Results
-// are bitwise those of k_iter: block-class rows keep their kBlock partition
-// (see block_row).
+// The full schedule in wide workgroups: more waves per workgroup, fewer
+// workgroups per CU, the same 6 waves per SIMD as k_iter, and one larger
+// LDS copy of the first contributions per workgroup instead of one of
+// kHubRows per four waves.  Static and Naive-dynamic sweeps (Eq. 1 over
+// every vertex) use 12 waves and 9216 entries (two workgroups per CU; about
+// 34% of the gathers on R-MAT scale 22 read LDS instead of 18%, 4% less time
+// per sweep).  Dynamic Frontier iterations on the full schedule use 8 waves
+// and 6144 entries (three per CU; 12 waves left that kernel at the 80-VGPR
+// cap with a spill and no gain, 8 give 1.3% per call).  Results are bitwise
+// those of k_iter: block-class rows keep their kBlock partition (see
+// block_row).
 #ifndef DFPR_WIDE
 #define DFPR_WIDE 1
-#endif
-#ifndef DFPR_WIDE_BOUND
-#define DFPR_WIDE_BOUND 6
 #endif
 #ifndef DFPR_WIDE_HUB
 #define DFPR_WIDE_HUB 9216
 #endif
-constexpr int kWideWaves = 12;
-constexpr int kWideThreads = kWideWaves * kWave;
-constexpr uint32_t kWideHub = DFPR_WIDE_HUB;
+#ifndef DFPR_WIDE_DF_HUB
+#define DFPR_WIDE_DF_HUB 6144
+#endif
+constexpr int kWideWaves = 12, kWideDfWaves = 8;
+constexpr uint32_t kWideHub = DFPR_WIDE_HUB, kWideDfHub = DFPR_WIDE_DF_HUB;
 
-__global__ __launch_bounds__(kWideThreads, DFPR_WIDE_BOUND) void k_iter_wide(IterArgs a)
+template <bool DF, int NW, uint32_t HUB>
+__global__ __launch_bounds__(NW * kWave, 6) void k_iter_wide(IterArgs a)
 {
-    __shared__ IterSharedT<kWideWaves> sh;
-    __shared__ double hub[kWideHub];
-    iter_body<false, false, kWideWaves>(a, blockIdx.x, gridDim.x, sh, hub);
+    __shared__ IterSharedT<NW> sh;
+    __shared__ double hub[HUB];
+    iter_body<DF, false, NW>(a, blockIdx.x, gridDim.x, sh, hub);
 }
 
 // After each iteration (one workgroup): fold the slots the iteration's
@@ -956,11 +960,10 @@ static int run_loop(dfpr_graph *g, const dfpr_params &p, bool df, bool f32, uint
     int target = 8, cap = 4;
     bool stop = false;
     uint32_t gsz = (uint32_t)g->grid;
-    // Static and Naive-dynamic sweeps (synchronous FP64) run the wide
-    // kernel.  Dynamic Frontier iterations on the full schedule gained
-    // nothing from it on R-MAT scale 22 (whole calls within 0.3%), so they
-    // stay on k_iter.
-    const bool wide = DFPR_WIDE && !f32 && !async && !df;
+    // synchronous FP64 walks of the full schedule run a wide kernel: Static
+    // and Naive-dynamic from the start, Dynamic Frontier once a state shows
+    // the full schedule
+    bool wide = DFPR_WIDE && !f32 && !async && !df;
     double prev_dr = -1.0;
     int prev_it = it0;
     *res_buf = base;
@@ -1002,9 +1005,15 @@ static int run_loop(dfpr_graph *g, const dfpr_params &p, bool df, bool f32, uint
             if (g->prof.enabled) DFPR_HIP(hipEventRecord(ev[2 * j], g->stream));
             if (wide) {
                 IterArgs aw = a;
-                aw.hub = a.hub ? kWideHub : 0u;
-                const uint32_t gw = (uint32_t)g->grid_wide;
-                k_iter_wide<<<gw, kWideThreads, 0, g->stream>>>(aw);
+                if (!df) {
+                    aw.hub = a.hub ? kWideHub : 0u;
+                    k_iter_wide<false, kWideWaves, kWideHub>
+                        <<<g->grid_wide, kWideWaves * kWave, 0, g->stream>>>(aw);
+                } else {
+                    aw.hub = a.hub ? kWideDfHub : 0u;
+                    k_iter_wide<true, kWideDfWaves, kWideDfHub>
+                        <<<g->grid_wide_df, kWideDfWaves * kWave, 0, g->stream>>>(aw);
+                }
             }
             else if (!df) k_iter<false, false><<<gsz, kBlock, 0, g->stream>>>(a);
             else if (f32) k_iter<true, true><<<gsz, kBlock, 0, g->stream>>>(a);
@@ -1056,6 +1065,7 @@ static int run_loop(dfpr_graph *g, const dfpr_params &p, bool df, bool f32, uint
         // iterations still needed after this state, from the observed
         // geometric decay of Delta R
         gsz = df && !st.dense ? sparse_grid(g, st) : (uint32_t)g->grid;
+        wide = DFPR_WIDE && !f32 && !async && (!df || st.dense);
         const double dr = st.final_linf;
         const int its = st.iterations;
         int need = std::min(chunk * 2, 32);
