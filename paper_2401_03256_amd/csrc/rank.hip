@@ -89,18 +89,21 @@ __global__ __launch_bounds__(kBlock, DFPR_ITER_WAVES_PER_SIMD) void k_iter(IterA
 #ifndef DFPR_WIDE_HUB
 #define DFPR_WIDE_HUB 9216
 #endif
+#ifndef DFPR_WIDE_F32_MUL
+#define DFPR_WIDE_F32_MUL 2
+#endif
 #ifndef DFPR_WIDE_DF_HUB
 #define DFPR_WIDE_DF_HUB 6144
 #endif
 constexpr int kWideWaves = 12, kWideDfWaves = 8;
 constexpr uint32_t kWideHub = DFPR_WIDE_HUB, kWideDfHub = DFPR_WIDE_DF_HUB;
 
-template <bool DF, int NW, uint32_t HUB>
+template <bool DF, bool F32, int NW, uint32_t HUB>
 __global__ __launch_bounds__(NW * kWave, 6) void k_iter_wide(IterArgs a)
 {
     __shared__ IterSharedT<NW> sh;
     __shared__ double hub[HUB];
-    iter_body<DF, false, NW>(a, blockIdx.x, gridDim.x, sh, hub);
+    iter_body<DF, F32, NW>(a, blockIdx.x, gridDim.x, sh, hub);
 }
 
 // After each iteration (one workgroup): fold the slots the iteration's
@@ -963,7 +966,7 @@ static int run_loop(dfpr_graph *g, const dfpr_params &p, bool df, bool f32, uint
     // synchronous FP64 walks of the full schedule run a wide kernel: Static
     // and Naive-dynamic from the start, Dynamic Frontier once a state shows
     // the full schedule
-    bool wide = DFPR_WIDE && !f32 && !async && !df;
+    bool wide = DFPR_WIDE && !async && !df;
     double prev_dr = -1.0;
     int prev_it = it0;
     *res_buf = base;
@@ -1007,11 +1010,16 @@ static int run_loop(dfpr_graph *g, const dfpr_params &p, bool df, bool f32, uint
                 IterArgs aw = a;
                 if (!df) {
                     aw.hub = a.hub ? kWideHub : 0u;
-                    k_iter_wide<false, kWideWaves, kWideHub>
+                    k_iter_wide<false, false, kWideWaves, kWideHub>
                         <<<g->grid_wide, kWideWaves * kWave, 0, g->stream>>>(aw);
+                } else if (f32) {
+                    // FP32 contributions: the same LDS holds twice the entries
+                    aw.hub = a.hub ? kWideDfHub * DFPR_WIDE_F32_MUL : 0u;
+                    k_iter_wide<true, true, kWideDfWaves, kWideDfHub>
+                        <<<g->grid_wide_df, kWideDfWaves * kWave, 0, g->stream>>>(aw);
                 } else {
                     aw.hub = a.hub ? kWideDfHub : 0u;
-                    k_iter_wide<true, kWideDfWaves, kWideDfHub>
+                    k_iter_wide<true, false, kWideDfWaves, kWideDfHub>
                         <<<g->grid_wide_df, kWideDfWaves * kWave, 0, g->stream>>>(aw);
                 }
             }
@@ -1065,7 +1073,7 @@ static int run_loop(dfpr_graph *g, const dfpr_params &p, bool df, bool f32, uint
         // iterations still needed after this state, from the observed
         // geometric decay of Delta R
         gsz = df && !st.dense ? sparse_grid(g, st) : (uint32_t)g->grid;
-        wide = DFPR_WIDE && !f32 && !async && (!df || st.dense);
+        wide = DFPR_WIDE && !async && (!df || st.dense);
         const double dr = st.final_linf;
         const int its = st.iterations;
         int need = std::min(chunk * 2, 32);
