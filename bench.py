@@ -284,11 +284,11 @@ def headline_bench(args, dfpr, synth):
     log(f"achievable copy bandwidth {copy_gbs:.0f} GB/s")
     roofline = {
         # the Dynamic Frontier iteration: k_iter on the class lists and the
-        # first iterations on the full schedule, k_iter_wide<true, 8, 6144>
+        # first iterations on the full schedule, k_iter_wide<true, false, 8, 6144>
         # on the full schedule once the host has seen it (one launch per
         # iteration either way)
         "bound": "hbm",
-        "kernel": "k_iter<true, false> + k_iter_wide<true, 8, 6144> "
+        "kernel": "k_iter<true, false> + k_iter_wide<true, false, 8, 6144> "
                   "(FP64 Dynamic Frontier iteration: pull + Delta r + L-inf + expand)",
         "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
         "frac": round(achieved / HBM_PEAK_GBS, 4),
