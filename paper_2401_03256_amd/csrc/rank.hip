@@ -80,9 +80,10 @@ __global__ __launch_bounds__(kBlock, DFPR_ITER_WAVES_PER_SIMD) void k_iter(IterA
 // 34% of the gathers on R-MAT scale 22 read LDS instead of 18%, 4% less time
 // per sweep).  Dynamic Frontier iterations on the full schedule use 8 waves
 // and 6144 entries (three per CU; 12 waves left that kernel at the 80-VGPR
-// cap with a spill and no gain, 8 give 1.3% per call).  Results are bitwise
-// those of k_iter: block-class rows keep their kBlock partition (see
-// block_row).
+// cap with a spill and no gain, 8 give 1% per call), or 12288 FP32 entries
+// in the FP32 phase of the precision form (2.5% per call at R-MAT scale 24).
+// Results are bitwise those of k_iter: block-class rows keep their kBlock
+// partition (see block_row).
 #ifndef DFPR_WIDE
 #define DFPR_WIDE 1
 #endif
