@@ -603,6 +603,57 @@ def test_serving_large_lane_in_order_one_at_a_time(dfpr):
                for s in small)
 
 
+def _hub_graph(n, hubs, fan_in, background, seed):
+    # `hubs` vertices of in-degree fan_in (whole-workgroup rows), on top of
+    # uniform background edges
+    rng = np.random.default_rng(seed)
+    hs = np.repeat(np.arange(hubs, dtype=np.int32), fan_in)
+    hsrc = rng.integers(hubs, n, size=hs.size, dtype=np.int32)
+    bs = rng.integers(0, n, size=background, dtype=np.int32)
+    bd = rng.integers(0, n, size=background, dtype=np.int32)
+    return np.concatenate([hsrc, bs]), np.concatenate([hs, bd])
+
+
+@pytest.mark.parametrize("hubs", [7, 8])
+def test_wide_kernels_block_rows_match(dfpr, hubs):
+    # Full-schedule walks run in 8- or 12-wave workgroups whose 256-thread
+    # sub-blocks sum two or three whole-workgroup rows at a time; with 7
+    # such rows some sub-blocks have none.  Static against the oracle, and
+    # Dynamic Frontier (4-wave class lists, then the 8-wave kernel) against
+    # the serving loop's 4-wave kernel, bitwise
+    _say(f"wide kernels, {hubs} whole-workgroup rows")
+    n = 20000
+    src, dst = _hub_graph(n, hubs, 3000, 120000, seed=40 + hubs)
+    g, o = _pair(dfpr, n, src, dst)
+    R0, s0 = g.static()
+    Ro, _ = o.static()
+    assert s0.converged and np.max(np.abs(R0 - Ro)) < TOL_RANK
+    Rn, _ = g.naive_dynamic(None, p=dfpr.params())
+    Rno, _ = o.naive_dynamic(Ro)
+    assert np.max(np.abs(Rn - Rno)) < TOL_RANK
+    g.set_ranks(R0)
+    # a batch touching every hub: the first frontier takes the full schedule
+    b = synth.Batch(np.zeros(0, np.int32), np.zeros(0, np.int32),
+                    np.arange(hubs, 2 * hubs, dtype=np.int32), np.arange(hubs, dtype=np.int32))
+    g2 = dfpr.Graph(n, src, dst)
+    g2.static()
+    assert g.apply_batch(b) == o.apply_batch(b)
+    p = dfpr.params(tol=1e-14, frontier_tol=1e-16)
+    Rd, sd = g.dynamic_frontier(b, prev=R0, p=p)
+    assert sd.converged and sd.iterations > 12
+    Rdo, _ = o.dynamic_frontier(b, Ro, tol=1e-14, frontier_tol=1e-16)
+    assert np.max(np.abs(Rd - Rdo)) < TOL_RANK
+    srv = dfpr.Server(max_slots=2)
+    gid = srv.add_graph(g2, p)
+    rid = srv.submit(gid, 0.0, b)
+    st = srv.run()
+    assert st["completed"] == 1 and srv.result(rid)["converged"]
+    assert np.array_equal(g2.ranks(), Rd)
+    srv.close()
+    g.close()
+    g2.close()
+
+
 def test_serving_budget_limits_concurrency(dfpr):
     n, s, d = synth.rmat(10, 16, seed=5)
     gs = []
